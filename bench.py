@@ -1,0 +1,184 @@
+"""Throughput benchmark of the coupled phase-field LB step on one MI355X.
+
+One step = one time step of the whole hot path (moments and implicit
+recovery, stencils, flow macros and viscosity law, time-derivative terms,
+collision of f, g, h1, h2 with their sources, streaming) over every node.
+
+Default workload: the 2-D rising bubble with interfacial mass transfer,
+256 x 1024 D2Q9 (four population sets), FP32, half-way bounce-back walls.
+Inputs are synthetic (a signed-distance bubble) and resident in HBM before
+the timed region starts.
+
+Prints one JSON line.  `value` is MLUPS (million node updates per second,
+all four sets per update) over the timed region; `roofline` relates the
+step kernel's algorithmic HBM bytes to its average duration, both measured
+with HIP events on the library's stream inside the timed region.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled-LB MLUPS + HBM GB/s vs peak; closure speedup at equal scalar error"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def alg_bytes_per_node(p):
+    """Algorithmic HBM bytes per node and step: every population read once
+    and written once, plus the (u, phi, c1, c2) history read and written."""
+    d = 2 if p["lattice"] == "d2q9" else 3
+    qtot = 36 if d == 2 else 40
+    s_pop = {"f64": 8, "f32": 4, "f32_s16f": 2, "f32_s16b": 2}[p["precision"]]
+    s_hist = 8 if p["precision"] == "f64" else 4
+    return 2 * qtot * s_pop + 2 * (d + 3) * s_hist
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "rising_bubble_256x1024":
+        return W.rising_bubble_2d(256, 1024, "f32")
+    if name.startswith("rising_droplet_256c"):
+        prec = name[len("rising_droplet_256c_"):] or "f32"
+        return W.rising_droplet_3d(256, prec)
+    if name == "static_drop_64x64":
+        return W.static_drop_64()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_gpu(w, steps, warmup):
+    import torch
+
+    from paper_2402_15752_amd import cplb
+    p = w["params"]
+    lat = cplb.Lattice(p)
+    lat.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    lat.step(warmup)
+    stream = lat.stream
+    n = int(p["nx"]) * int(p["ny"]) * int(p["nz"])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        lat.step(1)
+        b.record(stream)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_stop)
+    kern_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    avg_kernel_ms = sum(kern_ms) / len(kern_ms)
+    # same steps back to back, without per-step events
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    lat.step(steps)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = t_start.elapsed_time(t_stop)
+    r = lat.reduce()
+    lat.close()
+    return dict(n=n, total_ms=total_ms, plain_ms=plain_ms, avg_kernel_ms=avg_kernel_ms,
+                median_kernel_ms=kern_ms[len(kern_ms) // 2], reduce=r)
+
+
+def cpu_baseline(w, seconds=15.0):
+    """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
+    a fixed number of steps sized to ~10-30 s of CPU work."""
+    from oracle import ref
+    o = ref.Oracle(w["params"])
+    o.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    n = int(w["params"]["nx"]) * int(w["params"]["ny"]) * int(w["params"]["nz"])
+    t0 = time.perf_counter()
+    o.step(2)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / 2
+    steps = max(2, min(400, int(seconds / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} steps of {w['name']} ({n} nodes) on the FP64 C oracle, "
+                      f"OpenMP over {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="rising_bubble_256x1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the step is "
+              "single-GPU by design, see DESIGN.md for how it would shard", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+
+    w = make_workload(args.workload)
+    p = w["params"]
+    res = time_gpu(w, args.steps, args.warmup)
+    n = res["n"]
+    mlups = n * args.steps / (res["total_ms"] * 1e-3) / 1e6
+    mlups_plain = n * args.steps / (res["plain_ms"] * 1e-3) / 1e6
+    bpn = alg_bytes_per_node(p)
+    achieved = bpn * n / (res["avg_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["total_ms"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if p["precision"] != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "lattice": p["lattice"],
+                   "grid": [p["nx"], p["ny"], p["nz"]], "precision": p["precision"],
+                   "boundaries": "periodic x, bounce-back walls y" if p["lattice"] == "d2q9"
+                   else "periodic x y, bounce-back walls z"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "kernel": {"avg_ms": round(res["avg_kernel_ms"], 5),
+                   "median_ms": round(res["median_kernel_ms"], 5),
+                   "alg_bytes_per_node": bpn,
+                   "mlups_back_to_back": round(mlups_plain, 2)},
+    }
+    r = res["reduce"]
+    out["check"] = {"nonfinite": r["nonfinite"], "sum_phi": r["sum_phi"], "step": r["step"]}
+    if not args.no_extra and args.workload == "rising_bubble_256x1024":
+        extra = {}
+        for prec in ("f32", "f32_s16f", "f32_s16b"):
+            w3 = make_workload(f"rising_droplet_256c_{prec}")
+            r3 = time_gpu(w3, 100, 10)
+            b3 = alg_bytes_per_node(w3["params"])
+            a3 = b3 * r3["n"] / (r3["avg_kernel_ms"] * 1e-3) / 1e9
+            extra[w3["name"]] = {
+                "mlups": round(r3["n"] * 100 / (r3["total_ms"] * 1e-3) / 1e6, 1),
+                "avg_kernel_ms": round(r3["avg_kernel_ms"], 4),
+                "alg_bytes_per_node": b3, "achieved_GBs": round(a3, 1),
+                "frac": round(a3 / HBM_PEAK_GBS, 4), "nonfinite": r3["reduce"]["nonfinite"]}
+            del w3
+        out["also_3d_256c"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

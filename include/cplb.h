@@ -1,0 +1,175 @@
+/*
+ * cplb.h -- C-ABI of the MI355X coupled phase-field lattice Boltzmann library
+ * (libcplb.so).
+ *
+ * The library advances, on one GPU, the four coupled population sets of the
+ * phase-field LB method of Chen, Zhan, Chai & Shi (arXiv 2402.15752):
+ *   f        conservative Allen-Cahn phase field          (Sec. III A)
+ *   g        pressure-based incompressible flow           (Sec. III B)
+ *   h1, h2   two-scalar concentration / temperature model
+ *            with source H_k and auxiliary source ~H_k     (Sec. III C)
+ * on D2Q9 (all four sets) or D3Q19 (g and the stencils) + D3Q7 (f, h1, h2).
+ *
+ * Units are lattice units (dx = dt = 1).  Node index n = x + nx*(y + ny*z),
+ * x fastest.  Host arrays are FP64, N = nx*ny*nz values per scalar field and
+ * d consecutive planes of N values per vector field.
+ *
+ * Conventions
+ *  - Ownership: the caller owns the device workspace and the HIP stream and
+ *    keeps both alive until cplb_destroy.  The library owns the layout of the
+ *    workspace and the launch order.  Host arrays passed in are only read
+ *    during the call; device destinations are written asynchronously.
+ *  - Ordering: every call is ordered on the stream given at create.
+ *    cplb_init_*, cplb_reduce, cplb_save_state and cplb_load_state
+ *    synchronise that stream before returning.
+ *  - Errors: calls never abort and never throw across the ABI; they return
+ *    one of the CPLB_* codes below.  cplb_last_error gives the text of the
+ *    last failure on a handle.
+ *  - Threading: a handle is not thread-safe; any number of handles may exist.
+ */
+#ifndef CPLB_H
+#define CPLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPLB_ABI_VERSION 1
+
+/* return codes */
+#define CPLB_OK 0
+#define CPLB_EINVAL (-1)    /* bad parameters or arguments                     */
+#define CPLB_ENOMEM (-2)    /* workspace or host buffer too small              */
+#define CPLB_EHIP (-3)      /* HIP runtime error (text in cplb_last_error)     */
+#define CPLB_EUNSTABLE (-4) /* a reduction saw a non-finite field value        */
+#define CPLB_ESTATE (-5)    /* checkpoint does not match this lattice          */
+
+/* lattices */
+#define CPLB_D2Q9 0       /* D2Q9 for f, g, h1, h2 and the 9-point stencils       */
+#define CPLB_D3Q19_D3Q7 1 /* D3Q19 for g and 19-point stencils, D3Q7 for f, h1, h2 */
+
+/* arithmetic and population storage */
+#define CPLB_F64 0      /* FP64 compute, FP64 populations                            */
+#define CPLB_F32 1      /* FP32 compute, FP32 populations                            */
+#define CPLB_F32_S16F 2 /* FP32 compute, populations stored as FP16 of dX_i / w_i     */
+#define CPLB_F32_S16B 3 /* FP32 compute, populations stored as BF16 of dX_i / w_i     */
+
+/* viscosity laws */
+#define CPLB_VISC_LINEAR 0 /* mu = phi (mu1 - mu2) + mu2, Eq. (1.8)            */
+#define CPLB_VISC_EXP 1    /* log mu = c1 log mu1 + c2 log mu2, Eq. (4.3)      */
+
+/* field ids for cplb_read_field */
+#define CPLB_FIELD_PHI 0
+#define CPLB_FIELD_P 1
+#define CPLB_FIELD_UX 2
+#define CPLB_FIELD_UY 3
+#define CPLB_FIELD_UZ 4
+#define CPLB_FIELD_C1 5
+#define CPLB_FIELD_C2 6
+#define CPLB_FIELD_MU 7
+#define CPLB_FIELD_PSI 8 /* c1 + Keq c2 */
+#define CPLB_NFIELDS 9
+
+/* destination types for cplb_read_field */
+#define CPLB_DTYPE_F32 0
+#define CPLB_DTYPE_F64 1
+
+typedef struct cplb_params {
+  int32_t nx, ny, nz;    /* grid; nz = 1 on CPLB_D2Q9                            */
+  int32_t lattice;       /* CPLB_D2Q9 | CPLB_D3Q19_D3Q7                          */
+  int32_t precision;     /* CPLB_F64 | CPLB_F32 | CPLB_F32_S16F | CPLB_F32_S16B  */
+  int32_t visc_law;      /* CPLB_VISC_LINEAR | CPLB_VISC_EXP                     */
+  int32_t periodic[3];   /* per axis: 1 periodic, 0 half-way bounce-back walls   */
+  int32_t reserved;      /* must be 0                                            */
+  double rho1, rho2;     /* densities of fluid 1 (phi = 1) and fluid 2 (Sec. II B) */
+  double mu1, mu2;       /* viscosities of the two fluids (or the exp-law bases) */
+  double sigma;          /* surface tension: beta = 12 sigma/W, k = 3 sigma W/2  */
+  double W;              /* interface width                                      */
+  double M;              /* Allen-Cahn mobility, M = (tau_f - 1/2) cs^2          */
+  double D1, D2;         /* diffusivities, D_k = (tau_hk - 1/2) cs^2             */
+  double Keq;            /* partition (Henry / heat-capacity) coefficient        */
+  double A;              /* exchange rate parameter, 1/length^2                  */
+  double g[3];           /* gravity; body force G = (rho - rho_ref) g            */
+  double rho_ref;        /* reference density of the body force                  */
+  double n_eps;          /* normal n = grad phi / sqrt(|grad phi|^2 + n_eps^2)   */
+  double ref[4];         /* reference state of the stored populations: f, h1, h2
+                            are held as deviations X_i - w_i ref[k] (k = 0, 2, 3:
+                            phi_ref, c1_ref, c2_ref), which keeps FP32 and 16-bit
+                            rounding relative to the deviation; ref[1] (g) must be 0 */
+} cplb_params;
+
+typedef struct cplb cplb_t; /* opaque handle */
+
+/* Device workspace, in bytes, that cplb_create needs for these parameters.
+ * Returns CPLB_EINVAL for invalid parameters (same checks as cplb_create). */
+int cplb_workspace_bytes(const cplb_params* prm, size_t* bytes);
+
+/* Validate the parameters and carve the caller's device workspace
+ * (dev_workspace, at least cplb_workspace_bytes, 256-byte aligned) into the
+ * two population lattices, the time-derivative history, the field buffer and
+ * the reduction partials.  hip_stream is a hipStream_t (NULL = null stream).
+ * Every relaxation time must exceed 1/2: M, D1, D2 > 0 (Sec. III); rho_k,
+ * mu_k, W, Keq, n_eps > 0; sigma, A >= 0; nx, ny, nz >= 1 and >= 2 on a
+ * walled axis; on CPLB_D2Q9 nz = 1 and g[2] = 0.
+ * Errors: CPLB_EINVAL, CPLB_ENOMEM (workspace too small), CPLB_EHIP. */
+int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void* hip_stream,
+                cplb_t** out);
+
+/* Initial state from host fields phi, c1, c2 (N values each), u (d planes of
+ * N, or NULL for rest) and p (N values, or NULL for 0): every population is
+ * set to its equilibrium (Sec. III A-C) and the time-derivative history to
+ * these fields; the step counter restarts at 0.  Synchronises the stream. */
+int cplb_init_fields(cplb_t* h, const double* phi, const double* c1, const double* c2,
+                     const double* u, const double* p);
+
+/* Initial state from a host signed-distance field l (N values):
+ * phi0 = 1/2 + 1/2 tanh(2 l / W) (Sec. II A), c_k = a_k + b_k phi0, u = p = 0.
+ * Synchronises the stream. */
+int cplb_init_sdf(cplb_t* h, const double* l, double c1_a, double c1_b, double c2_a,
+                  double c2_b);
+
+/* Advance nsteps >= 0 time steps (one fused collide-and-stream launch per
+ * step: moments, stencils, flow macros, viscosity law, collision of f, g,
+ * h1, h2 with F_i, G_i, H_k, ~H_k, streaming with periodic wrap or half-way
+ * bounce-back).  Asynchronous on the stream. */
+int cplb_step(cplb_t* h, int64_t nsteps);
+
+/* Write macroscopic field `field` (CPLB_FIELD_*) at the current time level --
+ * the moments of the current populations, as they enter the next collision
+ * -- to dev_dst (device memory, N values of CPLB_DTYPE_F32 or _F64).
+ * Asynchronous on the stream. */
+int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype);
+
+/* FP64 reductions over the current time level, deterministic order:
+ * out[0] sum phi, out[1] sum c1, out[2] sum c2, out[3] sum (c1 + c2),
+ * out[4] max |u|, out[5] sum rho |u|^2 / 2, out[6] number of nodes with a
+ * non-finite phi, c1, c2, u or p, out[7] step counter.
+ * Synchronises the stream; returns CPLB_EUNSTABLE if out[6] > 0. */
+int cplb_reduce(cplb_t* h, double out[8]);
+
+/* Number of steps taken since the last init or load. */
+int64_t cplb_step_count(const cplb_t* h);
+
+/* Checkpoint: raw current populations, history, step counter and a copy of
+ * the parameters, into / from a caller-owned host buffer of
+ * cplb_state_bytes bytes.  A resumed run is bitwise identical to an
+ * uninterrupted one.  Both synchronise the stream.  load returns
+ * CPLB_ESTATE if the buffer was written for other parameters. */
+size_t cplb_state_bytes(const cplb_t* h);
+int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes);
+int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes);
+
+/* Error text of the last failed call on h, and of a return code. */
+const char* cplb_last_error(const cplb_t* h);
+const char* cplb_strerror(int code);
+
+/* Release the handle (not the caller's workspace or stream). */
+void cplb_destroy(cplb_t* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,61 @@
+"""Build libcplb.so in-tree: every HIP source compiled for gfx950 (CDNA4).
+
+Packed FP32 instructions are switched off for all device code
+(-target-feature -packed-fp32-ops); the host pass warns that it does not
+know that feature, which is harmless.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libcplb.so")
+SOURCES = ["api.hip", "aux.hip", "step2d.hip", "step3d.hip"]
+ARCH = os.environ.get("CPLB_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if cand and (os.path.isabs(cand) and os.path.exists(cand) or not os.path.isabs(cand)):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose=False, jobs=None):
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmd = [hipcc(), "-c", "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include"),
+               "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        # the host pass does not know the device-only feature flag
+        lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l
+                 and "unknown target feature" not in l.lower()]
+        if p.returncode != 0 or (verbose and lines):
+            print(f"--- {src}\n" + "\n".join(lines), file=sys.stderr)
+        failed |= p.returncode != 0
+    if failed:
+        raise RuntimeError("HIP compilation failed")
+    link = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

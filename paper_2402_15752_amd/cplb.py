@@ -1,0 +1,275 @@
+"""ctypes binding of libcplb.so (the C-ABI declared in include/cplb.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies the device workspace and the HIP stream.
+There is no fallback: if the library is missing or no GPU is present the
+calls raise.
+
+The module-level functions carry the same names as the C entry points; the
+``Lattice`` class is a convenience wrapper over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcplb.so")
+
+CPLB_OK, CPLB_EINVAL, CPLB_ENOMEM, CPLB_EHIP, CPLB_EUNSTABLE, CPLB_ESTATE = 0, -1, -2, -3, -4, -5
+LATTICES = {"d2q9": 0, "d3q19_d3q7": 1}
+PRECISIONS = {"f64": 0, "f32": 1, "f32_s16f": 2, "f32_s16b": 3}
+VISC = {"linear": 0, "exp": 1}
+FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
+DTYPE_F32, DTYPE_F64 = 0, 1
+EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
+           "cplb_read_field", "cplb_reduce", "cplb_step_count", "cplb_state_bytes",
+           "cplb_save_state", "cplb_load_state", "cplb_last_error", "cplb_strerror",
+           "cplb_destroy")
+
+
+class cplb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32), ("visc_law", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+        ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
+        ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("W", ctypes.c_double), ("M", ctypes.c_double),
+        ("D1", ctypes.c_double), ("D2", ctypes.c_double), ("Keq", ctypes.c_double),
+        ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
+        ("n_eps", ctypes.c_double), ("ref", ctypes.c_double * 4),
+    ]
+
+
+class CplbError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"cplb error {code} ({_strerror(code)}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def library():
+    """Load libcplb.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t
+        P = ctypes.POINTER(cplb_params)
+        L.cplb_workspace_bytes.argtypes = [P, ctypes.POINTER(sz)]
+        L.cplb_create.argtypes = [P, vp, sz, vp, ctypes.POINTER(vp)]
+        L.cplb_init_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.cplb_init_sdf.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double]
+        L.cplb_step.argtypes = [vp, ctypes.c_int64]
+        L.cplb_read_field.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+        L.cplb_reduce.argtypes = [vp, dp]
+        L.cplb_step_count.argtypes = [vp]
+        L.cplb_step_count.restype = ctypes.c_int64
+        L.cplb_state_bytes.argtypes = [vp]
+        L.cplb_state_bytes.restype = sz
+        L.cplb_save_state.argtypes = [vp, vp, sz]
+        L.cplb_load_state.argtypes = [vp, vp, sz]
+        L.cplb_last_error.argtypes = [vp]
+        L.cplb_last_error.restype = ctypes.c_char_p
+        L.cplb_strerror.argtypes = [ctypes.c_int]
+        L.cplb_strerror.restype = ctypes.c_char_p
+        L.cplb_destroy.argtypes = [vp]
+        L.cplb_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _strerror(code):
+    try:
+        return library().cplb_strerror(code).decode()
+    except Exception:  # library not loadable while formatting an error
+        return "?"
+
+
+def make_params(p: dict) -> cplb_params:
+    """cplb_params from a parameter dict (keys as in the workloads module)."""
+    r = cplb_params()
+    r.nx, r.ny, r.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    r.lattice = LATTICES[p["lattice"]]
+    r.precision = PRECISIONS[p.get("precision", "f64")]
+    r.visc_law = VISC[p["visc_law"]]
+    for a in range(3):
+        r.periodic[a] = int(p["periodic"][a])
+        r.g[a] = float(p["g"][a])
+    r.reserved = 0
+    for k in ("rho1", "rho2", "mu1", "mu2", "sigma", "W", "M", "D1", "D2", "Keq", "A", "rho_ref",
+              "n_eps"):
+        setattr(r, k, float(p[k]))
+    for k, name in enumerate(("ref_f", "ref_g", "ref_h1", "ref_h2")):
+        r.ref[k] = float(p.get(name, 0.0))
+    return r
+
+
+# ------------------------------------------------- thin C-ABI wrappers
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def cplb_workspace_bytes(prm: cplb_params) -> int:
+    n = ctypes.c_size_t()
+    rc = library().cplb_workspace_bytes(ctypes.byref(prm), ctypes.byref(n))
+    if rc:
+        raise CplbError(rc, "cplb_workspace_bytes rejected the parameters")
+    return n.value
+
+
+def cplb_create(prm: cplb_params, ws_ptr: int, ws_bytes: int, stream_ptr: int):
+    h = ctypes.c_void_p()
+    rc = library().cplb_create(ctypes.byref(prm), ctypes.c_void_p(ws_ptr), ws_bytes,
+                               ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    if rc:
+        raise CplbError(rc, "cplb_create failed")
+    return h
+
+
+def _check(h, rc):
+    if rc:
+        raise CplbError(rc, library().cplb_last_error(h).decode())
+
+
+def cplb_init_fields(h, phi, c1, c2, u=None, p=None):
+    _check(h, library().cplb_init_fields(h, _dp(phi), _dp(c1), _dp(c2), _dp(u), _dp(p)))
+
+
+def cplb_init_sdf(h, l, c1_a, c1_b, c2_a, c2_b):
+    _check(h, library().cplb_init_sdf(h, _dp(l), c1_a, c1_b, c2_a, c2_b))
+
+
+def cplb_step(h, nsteps: int):
+    _check(h, library().cplb_step(h, int(nsteps)))
+
+
+def cplb_read_field(h, field: int, dev_ptr: int, dtype: int):
+    _check(h, library().cplb_read_field(h, int(field), ctypes.c_void_p(dev_ptr), int(dtype)))
+
+
+def cplb_reduce(h):
+    out = np.zeros(8, dtype=np.float64)
+    rc = library().cplb_reduce(h, _dp(out))
+    if rc not in (CPLB_OK, CPLB_EUNSTABLE):
+        _check(h, rc)
+    return out, rc
+
+
+def cplb_step_count(h) -> int:
+    return int(library().cplb_step_count(h))
+
+
+def cplb_state_bytes(h) -> int:
+    return int(library().cplb_state_bytes(h))
+
+
+def cplb_save_state(h) -> bytes:
+    n = cplb_state_bytes(h)
+    buf = ctypes.create_string_buffer(n)
+    _check(h, library().cplb_save_state(h, ctypes.cast(buf, ctypes.c_void_p), n))
+    return buf.raw
+
+
+def cplb_load_state(h, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(h, library().cplb_load_state(h, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+
+
+def cplb_destroy(h):
+    library().cplb_destroy(h)
+
+
+# ------------------------------------------------------- convenience class
+
+class Lattice:
+    """One lattice on one GPU.  Fields are returned as torch tensors on the
+    device, shaped (ny, nx) or (nz, ny, nx)."""
+
+    def __init__(self, p: dict, device="cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("cplb needs a GPU: torch.cuda.is_available() is False")
+        self.torch = torch
+        self.p = dict(p)
+        self.device = torch.device(device)
+        self.d = 2 if p["lattice"] == "d2q9" else 3
+        self.shape = (p["ny"], p["nx"]) if self.d == 2 else (p["nz"], p["ny"], p["nx"])
+        self.N = int(p["nx"]) * int(p["ny"]) * int(p["nz"])
+        self._prm = make_params(p)
+        nbytes = cplb_workspace_bytes(self._prm)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        self._h = cplb_create(self._prm, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            cplb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def init_sdf(self, l, c1=(0.0, 0.0), c2=(0.0, 0.0)):
+        l = np.ascontiguousarray(l, dtype=np.float64).reshape(-1)
+        assert l.size == self.N
+        cplb_init_sdf(self._h, l, float(c1[0]), float(c1[1]), float(c2[0]), float(c2[1]))
+
+    def init_fields(self, phi, c1, c2, u=None, p=None):
+        a = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1) for x in (phi, c1, c2)]
+        assert all(x.size == self.N for x in a)
+        if u is not None:
+            u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+            assert u.size == self.d * self.N
+        if p is not None:
+            p = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
+            assert p.size == self.N
+        cplb_init_fields(self._h, a[0], a[1], a[2], u, p)
+
+    def step(self, n=1):
+        cplb_step(self._h, n)
+
+    def field(self, name, dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.float64
+        out = torch.empty(self.shape, dtype=dtype, device=self.device)
+        cplb_read_field(self._h, FIELDS[name], out.data_ptr(),
+                        DTYPE_F64 if dtype == torch.float64 else DTYPE_F32)
+        return out
+
+    def fields(self, names=("phi", "c1", "c2", "ux", "uy", "p")):
+        return {k: self.field(k) for k in names}
+
+    def reduce(self):
+        out, rc = cplb_reduce(self._h)
+        keys = ("sum_phi", "sum_c1", "sum_c2", "sum_c", "max_u", "kinetic", "nonfinite", "step")
+        r = dict(zip(keys, out.tolist()))
+        r["rc"] = rc
+        return r
+
+    @property
+    def step_count(self):
+        return cplb_step_count(self._h)
+
+    def save_state(self) -> bytes:
+        return cplb_save_state(self._h)
+
+    def load_state(self, blob: bytes):
+        cplb_load_state(self._h, blob)

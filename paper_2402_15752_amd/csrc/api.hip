@@ -1,0 +1,452 @@
+// C-ABI of libcplb.so: parameter validation, workspace layout, launch order.
+// The per-step work is entirely in the HIP kernels; this layer only
+// validates, carves the caller's workspace and enqueues on the caller's
+// stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/cplb.h"
+#include "kernels.hpp"
+
+using namespace pflb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Geometry {
+  int dim, qtot, nhist;
+  long long n;       // nodes
+  long long stride;  // elements per plane
+  size_t s_pop, s_cmp;
+  size_t lat_bytes, hist_bytes, field_bytes, part_bytes, total;
+};
+
+int validate(const cplb_params* p, char* err, size_t errn) {
+  auto fail = [&](const char* m) {
+    snprintf(err, errn, "%s", m);
+    return CPLB_EINVAL;
+  };
+  if (!p) return fail("null parameters");
+  if (p->lattice != CPLB_D2Q9 && p->lattice != CPLB_D3Q19_D3Q7) return fail("unknown lattice");
+  if (p->precision < CPLB_F64 || p->precision > CPLB_F32_S16B) return fail("unknown precision");
+  if (p->visc_law != CPLB_VISC_LINEAR && p->visc_law != CPLB_VISC_EXP)
+    return fail("unknown viscosity law");
+  if (p->reserved != 0) return fail("reserved field must be 0");
+  const int d = p->lattice == CPLB_D2Q9 ? 2 : 3;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
+  if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
+  const int n3[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < d; ++a)
+    if (!p->periodic[a] && n3[a] < 2) return fail("a walled axis needs at least 2 nodes");
+  if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail("grid too large (> 2e9 nodes)");
+  if (!(p->rho1 > 0 && p->rho2 > 0 && p->mu1 > 0 && p->mu2 > 0))
+    return fail("densities and viscosities must be positive");
+  if (!(p->W > 0 && p->M > 0 && p->D1 > 0 && p->D2 > 0 && p->Keq > 0 && p->n_eps > 0))
+    return fail("W, M, D1, D2, Keq, n_eps must be positive (every tau > 1/2)");
+  if (!(p->sigma >= 0 && p->A >= 0)) return fail("sigma and A must be >= 0");
+  if (d == 2 && p->g[2] != 0.0) return fail("2-D lattice: g[2] must be 0");
+  if (p->ref[1] != 0.0) return fail("ref[1] (flow set) must be 0");
+  const double all[] = {p->rho1, p->rho2, p->mu1,  p->mu2,  p->sigma, p->W,    p->M,
+                        p->D1,   p->D2,   p->Keq,  p->A,    p->g[0],  p->g[1], p->g[2],
+                        p->rho_ref, p->n_eps, p->ref[0], p->ref[1], p->ref[2], p->ref[3]};
+  for (double v : all)
+    if (!std::isfinite(v)) return fail("non-finite parameter");
+  return CPLB_OK;
+}
+
+Geometry geometry(const cplb_params* p) {
+  Geometry G{};
+  G.dim = p->lattice == CPLB_D2Q9 ? 2 : 3;
+  G.qtot = G.dim == 2 ? Layout<D2Q9, D2Q9>::QTOT : Layout<D3Q7, D3Q19>::QTOT;
+  G.nhist = G.dim == 2 ? kHist2D : kHist3D;
+  G.n = (long long)p->nx * p->ny * p->nz;
+  // planes padded to 64 elements plus one 64-element skew, so that the
+  // same node of successive planes does not land on the same HBM channel
+  G.stride = (G.n + 63) / 64 * 64 + 64;
+  switch (p->precision) {
+    case CPLB_F64: G.s_pop = 8; G.s_cmp = 8; break;
+    case CPLB_F32: G.s_pop = 4; G.s_cmp = 4; break;
+    default: G.s_pop = 2; G.s_cmp = 4; break;
+  }
+  G.lat_bytes = align_up((size_t)G.qtot * G.stride * G.s_pop, kAlign);
+  G.hist_bytes = align_up((size_t)G.nhist * G.stride * G.s_cmp, kAlign);
+  G.field_bytes = align_up((size_t)kNumFields * G.stride * G.s_cmp, kAlign);
+  G.part_bytes = align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
+  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes;
+  return G;
+}
+
+template <class T>
+KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
+  KParams<T> K{};
+  K.nx = p->nx;
+  K.ny = p->ny;
+  K.nz = p->nz;
+  for (int a = 0; a < 3; ++a) K.wall[a] = (a < G.dim && !p->periodic[a]) ? 1 : 0;
+  K.stride = G.stride;
+  const double csf = G.dim == 2 ? D2Q9::cs2 : D3Q7::cs2;
+  // relaxation times from the transport coefficients (Sec. III)
+  const double tau_f = 0.5 + p->M / csf;
+  const double tau_h1 = 0.5 + p->D1 / csf;
+  const double tau_h2 = 0.5 + p->D2 / csf;
+  // delta = 2 - 1/tau = 2 (tau - 1/2) / tau, formed from tau - 1/2 directly
+  K.del_f = T(2.0 * (p->M / csf) / tau_f);
+  K.hdel_f = T((p->M / csf) / tau_f);
+  K.del_h1 = T(2.0 * (p->D1 / csf) / tau_h1);
+  K.hdel_h1 = T((p->D1 / csf) / tau_h1);
+  K.del_h2 = T(2.0 * (p->D2 / csf) / tau_h2);
+  K.hdel_h2 = T((p->D2 / csf) / tau_h2);
+  // beta = 12 sigma / W, k = 3 sigma W / 2 (Sec. II B)
+  K.beta4 = T(4.0 * 12.0 * p->sigma / p->W);
+  K.kappa = T(1.5 * p->sigma * p->W);
+  K.rho1 = T(p->rho1);
+  K.rho2 = T(p->rho2);
+  K.drho = T(p->rho1 - p->rho2);
+  K.rho_ref = T(p->rho_ref);
+  for (int a = 0; a < 3; ++a) K.grav[a] = T(p->g[a]);
+  K.mu1 = T(p->mu1);
+  K.mu2 = T(p->mu2);
+  K.ln_mu1 = T(std::log(p->mu1));
+  K.ln_mu2 = T(std::log(p->mu2));
+  K.visc_exp = p->visc_law == CPLB_VISC_EXP;
+  K.D1D2 = T(p->D1 * p->D2);
+  K.KD1 = T(p->Keq * p->D1);
+  K.D2 = T(p->D2);
+  K.Keq = T(p->Keq);
+  K.A = T(p->A);
+  K.half_A = T(0.5 * p->A);
+  K.four_over_W = T(4.0 / p->W);
+  K.neps2 = T(p->n_eps * p->n_eps);
+  // reference state of the stored deviations (f, h1, h2; g is stored as is)
+  K.ref_phi = T(p->ref[0]);
+  K.one_minus_ref_phi = T(1.0 - p->ref[0]);
+  K.ref_c1 = T(p->ref[2]);
+  K.ref_c2 = T(p->ref[3]);
+  return K;
+}
+
+}  // namespace
+
+struct cplb {
+  cplb_params prm;
+  Geometry G;
+  hipStream_t stream;
+  char* ws;
+  void* lat[2];
+  void* hist;
+  void* fields;
+  double* partials;
+  int cur;
+  int64_t step;
+  bool fields_valid;
+  KParams<double> k64;
+  KParams<float> k32;
+  char err[512];
+};
+
+namespace {
+
+int set_err(cplb_t* h, int code, const char* fmt, const char* a = "") {
+  if (h) snprintf(h->err, sizeof(h->err), fmt, a);
+  return code;
+}
+
+int hip_check(cplb_t* h, hipError_t e, const char* where) {
+  if (e == hipSuccess) return CPLB_OK;
+  if (h) snprintf(h->err, sizeof(h->err), "%s: %s", where, hipGetErrorString(e));
+  return CPLB_EHIP;
+}
+
+template <class S, class T>
+hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, int mode) {
+  const S* src = (const S*)h->lat[h->cur];
+  S* dst = (S*)h->lat[h->cur ^ 1];
+  if (h->G.dim == 2)
+    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->stream);
+  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->stream);
+}
+
+hipError_t run_kernel(cplb_t* h, int mode) {
+  switch (h->prm.precision) {
+    case CPLB_F64: return dispatch_step<double, double>(h, h->k64, mode);
+    case CPLB_F32: return dispatch_step<float, float>(h, h->k32, mode);
+    case CPLB_F32_S16F: return dispatch_step<__half, float>(h, h->k32, mode);
+    default: return dispatch_step<__hip_bfloat16, float>(h, h->k32, mode);
+  }
+}
+
+int ensure_fields(cplb_t* h) {
+  if (h->fields_valid) return CPLB_OK;
+  int rc = hip_check(h, run_kernel(h, kModeMacros), "macros kernel");
+  if (rc == CPLB_OK) h->fields_valid = true;
+  return rc;
+}
+
+// host FP64 arrays -> staging area (the idle lattice) -> equilibrium init
+int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, const double* u,
+            const double* p, int from_sdf, const double (&cab)[4]) {
+  const size_t nb = (size_t)h->G.n * sizeof(double);
+  const int d = h->G.dim;
+  char* stage = (char*)h->lat[1];
+  size_t need = nb * (from_sdf ? 1 : (3 + (u ? d : 0) + (p ? 1 : 0)));
+  if (need > h->G.lat_bytes) return set_err(h, CPLB_ENOMEM, "staging area too small");
+  size_t off = 0;
+  auto put = [&](const double* src, size_t bytes) -> const double* {
+    if (!src) return nullptr;
+    double* dst = (double*)(stage + off);
+    off += bytes;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+      return (const double*)-1;
+    return dst;
+  };
+  const double* da = put(a, nb);
+  const double* dc1 = from_sdf ? nullptr : put(c1, nb);
+  const double* dc2 = from_sdf ? nullptr : put(c2, nb);
+  const double* du = from_sdf ? nullptr : put(u, nb * d);
+  const double* dp = from_sdf ? nullptr : put(p, nb);
+  const double* bad = (const double*)-1;
+  if (da == bad || dc1 == bad || dc2 == bad || du == bad || dp == bad)
+    return hip_check(h, hipGetLastError(), "copy of initial fields");
+  h->cur = 0;
+  const double W = h->prm.W;
+  hipError_t e;
+  switch (h->prm.precision) {
+    case CPLB_F64:
+      e = launch_init<double, double>(d, (double*)h->lat[0], (double*)h->hist, da, dc1, dc2, du, dp,
+                                      from_sdf, W, cab, h->k64, h->stream);
+      break;
+    case CPLB_F32:
+      e = launch_init<float, float>(d, (float*)h->lat[0], (float*)h->hist, da, dc1, dc2, du, dp,
+                                    from_sdf, W, cab, h->k32, h->stream);
+      break;
+    case CPLB_F32_S16F:
+      e = launch_init<__half, float>(d, (__half*)h->lat[0], (float*)h->hist, da, dc1, dc2, du, dp,
+                                     from_sdf, W, cab, h->k32, h->stream);
+      break;
+    default:
+      e = launch_init<__hip_bfloat16, float>(d, (__hip_bfloat16*)h->lat[0], (float*)h->hist, da,
+                                             dc1, dc2, du, dp, from_sdf, W, cab, h->k32, h->stream);
+  }
+  int rc = hip_check(h, e, "init kernel");
+  if (rc) return rc;
+  rc = hip_check(h, hipStreamSynchronize(h->stream), "init synchronise");
+  if (rc) return rc;
+  h->step = 0;
+  h->fields_valid = false;
+  return CPLB_OK;
+}
+
+constexpr uint32_t kStateMagic = 0x42504C43u;  // "CLPB"
+
+struct StateHeader {
+  uint32_t magic, abi;
+  int64_t step;
+  cplb_params prm;
+};
+
+}  // namespace
+
+extern "C" {
+
+int cplb_workspace_bytes(const cplb_params* prm, size_t* bytes) {
+  char err[256];
+  if (!bytes) return CPLB_EINVAL;
+  int rc = validate(prm, err, sizeof(err));
+  if (rc) return rc;
+  *bytes = geometry(prm).total;
+  return CPLB_OK;
+}
+
+int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void* hip_stream,
+                cplb_t** out) {
+  if (!out) return CPLB_EINVAL;
+  *out = nullptr;
+  char err[256];
+  int rc = validate(prm, err, sizeof(err));
+  if (rc) return rc;
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign)) return CPLB_EINVAL;
+  Geometry G = geometry(prm);
+  if (bytes < G.total) return CPLB_ENOMEM;
+  cplb_t* h = new (std::nothrow) cplb_t();
+  if (!h) return CPLB_ENOMEM;
+  h->prm = *prm;
+  h->G = G;
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char*)dev_workspace;
+  size_t off = 0;
+  h->lat[0] = h->ws + off;
+  off += G.lat_bytes;
+  h->lat[1] = h->ws + off;
+  off += G.lat_bytes;
+  h->hist = h->ws + off;
+  off += G.hist_bytes;
+  h->fields = h->ws + off;
+  off += G.field_bytes;
+  h->partials = (double*)(h->ws + off);
+  h->cur = 0;
+  h->step = 0;
+  h->fields_valid = false;
+  h->k64 = make_kparams<double>(prm, G);
+  h->k32 = make_kparams<float>(prm, G);
+  h->err[0] = 0;
+  *out = h;
+  return CPLB_OK;
+}
+
+void cplb_destroy(cplb_t* h) { delete h; }
+
+int cplb_init_fields(cplb_t* h, const double* phi, const double* c1, const double* c2,
+                     const double* u, const double* p) {
+  if (!h) return CPLB_EINVAL;
+  if (!phi || !c1 || !c2) return set_err(h, CPLB_EINVAL, "phi, c1 and c2 are required");
+  const double cab[4] = {0, 0, 0, 0};
+  return do_init(h, phi, c1, c2, u, p, 0, cab);
+}
+
+int cplb_init_sdf(cplb_t* h, const double* l, double c1_a, double c1_b, double c2_a, double c2_b) {
+  if (!h) return CPLB_EINVAL;
+  if (!l) return set_err(h, CPLB_EINVAL, "signed distance array is required");
+  const double cab[4] = {c1_a, c1_b, c2_a, c2_b};
+  return do_init(h, l, nullptr, nullptr, nullptr, nullptr, 1, cab);
+}
+
+int cplb_step(cplb_t* h, int64_t nsteps) {
+  if (!h) return CPLB_EINVAL;
+  if (nsteps < 0) return set_err(h, CPLB_EINVAL, "nsteps must be >= 0");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    int rc = hip_check(h, run_kernel(h, kModeStep), "step kernel");
+    if (rc) return rc;
+    h->cur ^= 1;
+    h->step++;
+  }
+  if (nsteps > 0) h->fields_valid = false;
+  return CPLB_OK;
+}
+
+int64_t cplb_step_count(const cplb_t* h) { return h ? h->step : -1; }
+
+int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype) {
+  if (!h) return CPLB_EINVAL;
+  if (field < 0 || field >= CPLB_NFIELDS) return set_err(h, CPLB_EINVAL, "unknown field id");
+  if (dtype != CPLB_DTYPE_F32 && dtype != CPLB_DTYPE_F64)
+    return set_err(h, CPLB_EINVAL, "unknown destination dtype");
+  if (!dev_dst) return set_err(h, CPLB_EINVAL, "null destination");
+  int rc = ensure_fields(h);
+  if (rc) return rc;
+  hipError_t e;
+  if (h->G.s_cmp == 8)
+    e = launch_convert<double>((const double*)h->fields + field * h->G.stride, dev_dst, dtype, h->G.n,
+                               h->stream);
+  else
+    e = launch_convert<float>((const float*)h->fields + field * h->G.stride, dev_dst, dtype, h->G.n,
+                              h->stream);
+  return hip_check(h, e, "field conversion");
+}
+
+int cplb_reduce(cplb_t* h, double out[8]) {
+  if (!h || !out) return CPLB_EINVAL;
+  int rc = ensure_fields(h);
+  if (rc) return rc;
+  double* dout = h->partials + 8 * kReduceBlocks;
+  const int nparts = h->G.n < (long long)kReduceBlocks * 256 ? (int)((h->G.n + 255) / 256) : kReduceBlocks;
+  hipError_t e;
+  if (h->G.s_cmp == 8)
+    e = launch_reduce<double>((const double*)h->fields, h->G.stride, h->G.n, h->prm.rho1,
+                              h->prm.rho2, h->partials, nparts, dout, h->stream);
+  else
+    e = launch_reduce<float>((const float*)h->fields, h->G.stride, h->G.n, h->prm.rho1, h->prm.rho2,
+                             h->partials, nparts, dout, h->stream);
+  rc = hip_check(h, e, "reduction kernels");
+  if (rc) return rc;
+  double tmp[8];
+  rc = hip_check(h, hipMemcpyAsync(tmp, dout, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                 "reduction copy");
+  if (rc) return rc;
+  rc = hip_check(h, hipStreamSynchronize(h->stream), "reduction synchronise");
+  if (rc) return rc;
+  for (int k = 0; k < 7; ++k) out[k] = tmp[k];
+  out[7] = (double)h->step;
+  if (out[6] > 0) return set_err(h, CPLB_EUNSTABLE, "non-finite values in %s fields", "the");
+  return CPLB_OK;
+}
+
+size_t cplb_state_bytes(const cplb_t* h) {
+  if (!h) return 0;
+  return sizeof(StateHeader) + (size_t)h->G.qtot * h->G.n * h->G.s_pop +
+         (size_t)h->G.nhist * h->G.n * h->G.s_cmp;
+}
+
+int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes) {
+  if (!h || !host_dst) return CPLB_EINVAL;
+  if (bytes < cplb_state_bytes(h)) return set_err(h, CPLB_ENOMEM, "checkpoint buffer too small");
+  int rc = hip_check(h, hipStreamSynchronize(h->stream), "checkpoint synchronise");
+  if (rc) return rc;
+  StateHeader hd{};
+  hd.magic = kStateMagic;
+  hd.abi = CPLB_ABI_VERSION;
+  hd.step = h->step;
+  hd.prm = h->prm;
+  char* o = (char*)host_dst;
+  memcpy(o, &hd, sizeof(hd));
+  o += sizeof(hd);
+  const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
+  for (int q = 0; q < h->G.qtot; ++q, o += pb) {
+    rc = hip_check(h, hipMemcpy(o, (char*)h->lat[h->cur] + q * h->G.stride * h->G.s_pop, pb,
+                                hipMemcpyDeviceToHost), "checkpoint copy");
+    if (rc) return rc;
+  }
+  for (int k = 0; k < h->G.nhist; ++k, o += hb) {
+    rc = hip_check(h, hipMemcpy(o, (char*)h->hist + k * h->G.stride * h->G.s_cmp, hb,
+                                hipMemcpyDeviceToHost), "checkpoint copy");
+    if (rc) return rc;
+  }
+  return CPLB_OK;
+}
+
+int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
+  if (!h || !host_src) return CPLB_EINVAL;
+  if (bytes < cplb_state_bytes(h)) return set_err(h, CPLB_ESTATE, "checkpoint buffer too small");
+  StateHeader hd;
+  memcpy(&hd, host_src, sizeof(hd));
+  if (hd.magic != kStateMagic || hd.abi != CPLB_ABI_VERSION ||
+      memcmp(&hd.prm, &h->prm, sizeof(cplb_params)) != 0)
+    return set_err(h, CPLB_ESTATE, "checkpoint was written for other parameters%s", "");
+  int rc = hip_check(h, hipStreamSynchronize(h->stream), "restore synchronise");
+  if (rc) return rc;
+  const char* o = (const char*)host_src + sizeof(hd);
+  const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
+  h->cur = 0;
+  for (int q = 0; q < h->G.qtot; ++q, o += pb) {
+    rc = hip_check(h, hipMemcpy((char*)h->lat[0] + q * h->G.stride * h->G.s_pop, o, pb,
+                                hipMemcpyHostToDevice), "restore copy");
+    if (rc) return rc;
+  }
+  for (int k = 0; k < h->G.nhist; ++k, o += hb) {
+    rc = hip_check(h, hipMemcpy((char*)h->hist + k * h->G.stride * h->G.s_cmp, o, hb,
+                                hipMemcpyHostToDevice), "restore copy");
+    if (rc) return rc;
+  }
+  h->step = hd.step;
+  h->fields_valid = false;
+  return CPLB_OK;
+}
+
+const char* cplb_last_error(const cplb_t* h) { return h ? h->err : "null handle"; }
+
+const char* cplb_strerror(int code) {
+  switch (code) {
+    case CPLB_OK: return "ok";
+    case CPLB_EINVAL: return "invalid parameters or arguments";
+    case CPLB_ENOMEM: return "workspace or buffer too small";
+    case CPLB_EHIP: return "HIP runtime error";
+    case CPLB_EUNSTABLE: return "non-finite values (unstable run)";
+    case CPLB_ESTATE: return "checkpoint does not match this lattice";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

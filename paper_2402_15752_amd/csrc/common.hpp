@@ -1,0 +1,393 @@
+// Per-node arithmetic of the coupled phase-field LB step, shared by the 2-D
+// and 3-D kernels.  Everything here works on values held in registers; the
+// kernels own loads, stencils and streaming.
+//
+// Notation follows the paper: phi (order parameter), c1, c2 (two-scalar
+// concentrations), psi = c1 + Keq c2, D_m (mixed diffusivity), mu_phi
+// (chemical potential), F (total force), p, u, rho, mu.
+//
+// Deviation form.  The f, h1, h2 populations are held, stored and streamed
+// as deviations from a uniform reference state, dX_i = X_i - w_i X_ref
+// (X_ref = phi_ref, c1_ref, c2_ref; g needs none, it vanishes at rest).
+// The algebra of the method is unchanged -- X_i - X_i^eq = dX_i - dX_i^eq,
+// streaming and bounce-back move a uniform w_i X_ref onto itself -- but
+// every rounding is now relative to the deviation: phi - phi_ref,
+// 1 - phi = (1 - phi_ref) - dphi and the stencils of phi are formed from
+// small numbers, which keeps FP32 and 16-bit storage accurate in the bulk
+// phases that fill most of the domain.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace pflb {
+
+// Constants of one lattice, precomputed on the host in FP64 and rounded
+// once to the compute type T.
+template <class T>
+struct KParams {
+  int nx, ny, nz;
+  int wall[3];        // 1: half-way bounce-back walls on both faces of the axis
+  long long stride;   // elements between two population / field planes
+  // relaxation of the constant-tau sets as delta = 2 - 1/tau = 2 (tau - 1/2)/tau
+  // and delta/2 = 1 - 1/(2 tau): accurate even when tau is close to 1/2
+  T del_f, hdel_f, del_h1, hdel_h1, del_h2, hdel_h2;
+  T beta4, kappa;     // 4 beta and k of the chemical potential
+  T rho1, rho2, drho, rho_ref;
+  T grav[3];
+  T mu1, mu2, ln_mu1, ln_mu2;
+  int visc_exp;       // 1: exponential law, Eq. (4.3); 0: linear law, Eq. (1.8)
+  T D1D2, KD1, D2, Keq, A, half_A;
+  T four_over_W;
+  T neps2;            // n_eps^2 of the regularised normal
+  T ref_phi, one_minus_ref_phi, ref_c1, ref_c2;  // reference state of the deviations
+};
+
+// ------------------------------------------------------------ storage codec
+//
+// FP64 and FP32 lattices store the deviation dX_i itself.  16-bit lattices
+// store dX_i / w_i, so that every direction has the same relative precision.
+
+template <class S, class T>
+struct Codec;
+
+template <>
+struct Codec<double, double> {
+  __device__ static double ld(double s, double) { return s; }
+  __device__ static double st(double x, double) { return x; }
+};
+
+template <>
+struct Codec<float, float> {
+  __device__ static float ld(float s, float) { return s; }
+  __device__ static float st(float x, float) { return x; }
+};
+
+template <>
+struct Codec<__half, float> {
+  __device__ static float ld(__half s, float w) { return w * __half2float(s); }
+  __device__ static __half st(float x, float inv_w) { return __float2half_rn(x * inv_w); }
+};
+
+template <>
+struct Codec<__hip_bfloat16, float> {
+  __device__ static float ld(__hip_bfloat16 s, float w) { return w * __bfloat162float(s); }
+  __device__ static __hip_bfloat16 st(float x, float inv_w) { return __float2bfloat16(x * inv_w); }
+};
+
+// --------------------------------------------------------------- helpers
+
+__device__ inline double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+__device__ inline float rsqrt_t(float x) { return 1.0f / sqrtf(x); }
+__device__ inline double exp_t(double x) { return exp(x); }
+__device__ inline float exp_t(float x) { return expf(x); }
+
+template <class T>
+__device__ inline bool finite_t(T x) {
+  return x == x && x - x == T(0);
+}
+
+// Macroscopic state of one node at the current time level.
+template <class T>
+struct Node {
+  T dphi, phi, omphi;  // phi - phi_ref, phi, 1 - phi
+  T dc1, dc2, c1, c2;  // c_k - c_k,ref and c_k
+  T Dm;                // mixed diffusivity
+};
+
+// --------------------------------------------------- moments and recovery
+//
+// phi = sum f_i; S_k = sum h_k,i; D_m = D1 D2 / (Keq D1 (1-phi) + D2 phi)
+// (Sec. II C).  The implicit recovery c1 = S1 + a e, c2 = S2 - a e with
+// a = A D_m / 2 and e = Keq c2 phi - c1 (1-phi) (Sec. III C) is linear; its
+// exact solution is e = (Keq phi S2 - (1-phi) S1) / (1 + a (Keq phi + 1 - phi)).
+template <class LF, class T>
+__device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const T (&dh1)[LF::Q],
+                               const T (&dh2)[LF::Q], Node<T>& s) {
+  T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    s0 += df[i];
+    s1 += dh1[i];
+    s2 += dh2[i];
+  }
+  s.dphi = s0;
+  s.phi = P.ref_phi + s0;
+  s.omphi = P.one_minus_ref_phi - s0;
+  s.Dm = P.D1D2 / (P.KD1 * s.omphi + P.D2 * s.phi);
+  const T a = P.half_A * s.Dm;
+  const T S1 = P.ref_c1 + s1, S2 = P.ref_c2 + s2;
+  const T Kphi = P.Keq * s.phi;
+  const T e = (Kphi * S2 - s.omphi * S1) / (T(1) + a * (Kphi + s.omphi));
+  s.dc1 = s1 + a * e;
+  s.dc2 = s2 - a * e;
+  s.c1 = P.ref_c1 + s.dc1;
+  s.c2 = P.ref_c2 + s.dc2;
+}
+
+// ---------------------------------------------------------- flow macros
+//
+// rho = phi (rho1 - rho2) + rho2; F = mu_phi grad phi + (rho - rho_ref) g;
+// u = (sum c_i g_i + F/2) / rho;
+// p = cs^2/(1-w0) [sum_{i!=0} g_i + (rho1-rho2) u.grad phi / 2 + rho s_0(u)];
+// mu from Eq. (4.3) or Eq. (1.8)   (Sec. II B, III B)
+template <class T>
+struct Flow {
+  T u[3];
+  T F[3];
+  T pi;     // bracket of the pressure formula: p = cs^2 / (1 - w0) * pi
+  T p, rho, mu, mu_phi;
+};
+
+template <class LG, class T>
+__device__ inline void flow_macros(const KParams<T>& P, const T (&g)[LG::Q], const Node<T>& s,
+                                   const T (&gphi)[3], T lap, Flow<T>& fl) {
+  constexpr T cs2 = T(LG::cs2);
+  // 4 beta phi (phi-1)(phi-1/2) - k lap phi
+  fl.mu_phi = -P.beta4 * s.phi * s.omphi * (s.phi - T(0.5)) - P.kappa * lap;
+  fl.rho = s.phi * P.drho + P.rho2;
+  const T buoy = fl.rho - P.rho_ref;
+  T m[3] = {0, 0, 0};
+  T sg = 0;
+#pragma unroll
+  for (int i = 1; i < LG::Q; ++i) {
+    sg += g[i];
+    if (LG::cx[i]) m[0] += T(LG::cx[i]) * g[i];
+    if (LG::cy[i]) m[1] += T(LG::cy[i]) * g[i];
+    if (LG::cz[i]) m[2] += T(LG::cz[i]) * g[i];
+  }
+  const T inv_rho = T(1) / fl.rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    fl.F[a] = fl.mu_phi * gphi[a] + buoy * P.grav[a];
+    fl.u[a] = (m[a] + T(0.5) * fl.F[a]) * inv_rho;
+  }
+  const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
+  const T udg = fl.u[0] * gphi[0] + fl.u[1] * gphi[1] + fl.u[2] * gphi[2];
+  const T s0 = T(LG::w[0]) * (-uu / (T(2) * cs2));
+  fl.pi = sg + T(0.5) * P.drho * udg + fl.rho * s0;
+  fl.p = T(cs2 / (1.0 - LG::w[0])) * fl.pi;
+  if (P.visc_exp)
+    fl.mu = exp_t(s.c1 * P.ln_mu1 + s.c2 * P.ln_mu2);
+  else
+    fl.mu = s.phi * (P.mu1 - P.mu2) + P.mu2;
+}
+
+// ------------------------------------------------------------- collision
+//
+// SRT collision of the four sets at one node (Sec. III A-C):
+//   X_i* = X_i - (X_i - X_i^eq)/tau + (1 - 1/(2 tau)) S_i  [+ ~H_i for h1, h2]
+// with the equilibria, source terms F_i, G_i, H_k,i and ~H_k,i of the paper,
+// written on the deviations df, dh1, dh2 (g as is).  Arrays are overwritten
+// with the post-collision values.
+//
+// The same algebra is arranged so that rounding carries no bias into the
+// moments the method conserves or relaxes slowly:
+//  - with neq = X - X^eq and delta = 2 - 1/tau,
+//      X* = (X^eq - neq) + delta neq + (delta/2) S,
+//    so tau - 1/2 (hence M, D_k, nu) enters through delta, stored to full
+//    relative precision, instead of through 1 - 1/tau;
+//  - the rest-direction equilibrium closes the zeroth moment exactly
+//    (X_0^eq = X - sum_{i>0} X_i^eq), so rounded weights cannot create or
+//    destroy phase, solute or pressure;
+//  - first-moment terms use K_i ~ w_i/cs^2 chosen so that
+//    sum_i K_i c_ix^2 = 1 holds exactly in the compute type, so the momentum
+//    of g^eq is rho u without a rounded-weight factor.
+
+// Per-direction first-moment constant K_i ~ w_i / cs^2 of lattice L in type
+// T: the axis value rounded once, the other directions carrying c_x != 0
+// completing sum_i K_i c_ix^2 = 1 exactly.
+template <class L, class T>
+__device__ constexpr T kw(int i) {
+  constexpr T k_axis = T(L::w[1] / L::cs2);
+  constexpr int n_diag = L::Q == 9 ? 4 : (L::Q == 19 ? 8 : 0);
+  if (i == 0) return T(0);
+  const int nnz = (L::cx[i] != 0) + (L::cy[i] != 0) + (L::cz[i] != 0);
+  if (nnz == 1) return k_axis;
+  return (T(1) - T(2) * k_axis) / T(n_diag);
+}
+
+// Pressure weights v_i = w_i / (1 - w0) (i > 0) of lattice L in type T,
+// completed so that sum_{i>0} v_i = 1 holds exactly.  With
+// p = cs^2/(1-w0) Pi (Sec. III B) the pressure part of g_i^eq is
+// p w_i / cs^2 = v_i Pi, which sums back to Pi with no rounded-weight factor.
+template <class L, class T>
+__device__ constexpr T kp(int i) {
+  constexpr T v_axis = T(L::w[1] / (1.0 - L::w[0]));
+  constexpr int n_axis = 2 * L::D;
+  constexpr int n_other = L::Q - 1 - n_axis;
+  if (i == 0) return T(0);
+  const int nnz = (L::cx[i] != 0) + (L::cy[i] != 0) + (L::cz[i] != 0);
+  if (nnz == 1 || n_other == 0) return v_axis;
+  return (T(1) - T(n_axis) * v_axis) / T(n_other);
+}
+
+// regularised unit normal n = grad phi / sqrt(|grad phi|^2 + n_eps^2)
+template <class T>
+__device__ inline void normal(const KParams<T>& P, const T (&gphi)[3], T (&n)[3]) {
+  const T gg = gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2];
+  const T rn = rsqrt_t(gg + P.neps2);
+  n[0] = gphi[0] * rn;
+  n[1] = gphi[1] * rn;
+  n[2] = gphi[2] * rn;
+}
+
+template <class T>
+__device__ inline T relax(T x, T xeq, T del, T hdel, T src) {
+  const T neq = x - xeq;
+  return del * neq + (xeq - neq) + hdel * src;
+}
+
+// phase field: f^eq = w phi (1 + c.u/cs^2), F_i = w [c.d_t(phi u)/cs^2 + c.n 4 phi (1-phi)/W]
+template <class LF, class T>
+__device__ inline void collide_f(const KParams<T>& P, T (&df)[LF::Q], const Node<T>& s,
+                                 const T (&n)[3], const Flow<T>& fl, const T (&dJphi)[3]) {
+  const T sharp = P.four_over_W * s.phi * s.omphi;
+  T eq[LF::Q];
+  T rest = s.dphi;
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) {
+    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+    eq[i] = T(LF::w[i]) * s.dphi + kw<LF, T>(i) * s.phi * cu;
+    rest -= eq[i];
+  }
+  eq[0] = rest;
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
+    const T cj = T(LF::cx[i]) * dJphi[0] + T(LF::cy[i]) * dJphi[1] + T(LF::cz[i]) * dJphi[2];
+    const T Fi = i == 0 ? T(0) : kw<LF, T>(i) * cj + T(LF::w[i]) * cn * sharp;
+    df[i] = relax(df[i], eq[i], P.del_f, P.hdel_f, Fi);
+  }
+}
+
+// flow: g^eq = p/cs^2 (w_i - delta_i0) + rho s_i(u),
+//       G_i = w [c.F/cs^2 + (rho1-rho2)(c.u)(c.grad phi)/cs^2], tau_g = 1/2 + mu/(rho cs^2)
+template <class LG, class T>
+__device__ inline void collide_g(const KParams<T>& P, T (&g)[LG::Q], const T (&gphi)[3],
+                                 const Flow<T>& fl) {
+  constexpr T inv_csg = T(1.0 / LG::cs2);
+  constexpr T half_inv_csg2 = T(0.5 / (LG::cs2 * LG::cs2));
+  const T nu = fl.mu * inv_csg / fl.rho;  // tau_g - 1/2
+  const T tau_g = T(0.5) + nu;
+  const T del_g = T(2) * nu / tau_g;
+  const T hdel_g = T(0.5) * del_g;
+  const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
+  const T iso = uu * T(0.5) * inv_csg;
+  T eq[LG::Q];
+  T rest = T(0);
+#pragma unroll
+  for (int i = 1; i < LG::Q; ++i) {
+    const T cu = T(LG::cx[i]) * fl.u[0] + T(LG::cy[i]) * fl.u[1] + T(LG::cz[i]) * fl.u[2];
+    // p/cs^2 w_i = v_i Pi with Pi the bracket of the pressure formula
+    eq[i] = kp<LG, T>(i) * fl.pi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
+            kw<LG, T>(i) * fl.rho * cu;
+    rest -= eq[i];
+  }
+  eq[0] = rest;  // sum_i g_i^eq = 0
+#pragma unroll
+  for (int i = 0; i < LG::Q; ++i) {
+    const T cu = T(LG::cx[i]) * fl.u[0] + T(LG::cy[i]) * fl.u[1] + T(LG::cz[i]) * fl.u[2];
+    const T cF = T(LG::cx[i]) * fl.F[0] + T(LG::cy[i]) * fl.F[1] + T(LG::cz[i]) * fl.F[2];
+    const T cg = T(LG::cx[i]) * gphi[0] + T(LG::cy[i]) * gphi[1] + T(LG::cz[i]) * gphi[2];
+    const T Gi = i == 0 ? T(0) : kw<LG, T>(i) * (cF + P.drho * cu * cg);
+    g[i] = relax(g[i], eq[i], del_g, hdel_g, Gi);
+  }
+}
+
+// two-scalar sets: h_k^eq = w c_k (1 + c.u/cs^2),
+//   H_1 = w [c.d_t(c1 u)/cs^2 + c.n 4 (1-phi) c1/W + A D_m (Keq c2 phi - c1 (1-phi))],
+//   H_2 = w [c.d_t(c2 u)/cs^2 - c.n 4 phi c2/W + A D_m (c1 (1-phi) - Keq c2 phi)],
+//   ~H_1 = -w D_m grad phi . grad psi = -~H_2
+template <class LF, class T>
+__device__ inline void collide_h(const KParams<T>& P, T (&dh1)[LF::Q], T (&dh2)[LF::Q],
+                                 const Node<T>& s, const T (&n)[3], const T (&gphi)[3],
+                                 const T (&gpsi)[3], const Flow<T>& fl, const T (&dJ1)[3],
+                                 const T (&dJ2)[3]) {
+  const T M1 = P.A * s.Dm * (P.Keq * s.c2 * s.phi - s.c1 * s.omphi);
+  const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]);
+  const T fl1 = P.four_over_W * s.omphi * s.c1;
+  const T fl2 = P.four_over_W * s.phi * s.c2;
+  T e1[LF::Q], e2[LF::Q];
+  T r1 = s.dc1, r2 = s.dc2;
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) {
+    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+    e1[i] = T(LF::w[i]) * s.dc1 + kw<LF, T>(i) * s.c1 * cu;
+    e2[i] = T(LF::w[i]) * s.dc2 + kw<LF, T>(i) * s.c2 * cu;
+    r1 -= e1[i];
+    r2 -= e2[i];
+  }
+  e1[0] = r1;
+  e2[0] = r2;
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    const T w = T(LF::w[i]);
+    const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
+    const T cj1 = T(LF::cx[i]) * dJ1[0] + T(LF::cy[i]) * dJ1[1] + T(LF::cz[i]) * dJ1[2];
+    const T cj2 = T(LF::cx[i]) * dJ2[0] + T(LF::cy[i]) * dJ2[1] + T(LF::cz[i]) * dJ2[2];
+    const T k = kw<LF, T>(i);
+    const T H1 = k * cj1 + w * (cn * fl1 + M1);
+    const T H2 = k * cj2 - w * (cn * fl2 + M1);
+    dh1[i] = relax(dh1[i], e1[i], P.del_h1, P.hdel_h1, H1) - w * aux;
+    dh2[i] = relax(dh2[i], e2[i], P.del_h2, P.hdel_h2, H2) + w * aux;
+  }
+}
+
+template <class LF, class LG, class T>
+__device__ inline void collide(const KParams<T>& P, T (&df)[LF::Q], T (&g)[LG::Q],
+                               T (&dh1)[LF::Q], T (&dh2)[LF::Q], const Node<T>& s,
+                               const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
+                               const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3]) {
+  T n[3];
+  normal(P, gphi, n);
+  collide_f<LF>(P, df, s, n, fl, dJphi);
+  collide_g<LG>(P, g, gphi, fl);
+  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2);
+}
+
+// ------------------------------------------------------------- equilibria
+// Equilibrium populations of the initial fields, as deviations (init only).
+template <class LF, class LG, class T>
+__device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const T (&u)[3], T p,
+                                  T (&df)[LF::Q], T (&g)[LG::Q], T (&dh1)[LF::Q],
+                                  T (&dh2)[LF::Q]) {
+  constexpr T inv_csf = T(1.0 / LF::cs2);
+  constexpr T inv_csg = T(1.0 / LG::cs2);
+  constexpr T half_inv_csg2 = T(0.5 / (LG::cs2 * LG::cs2));
+  const T rho = phi * P.drho + P.rho2;
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T dphi = phi - P.ref_phi, dc1 = c1 - P.ref_c1, dc2 = c2 - P.ref_c2;
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    const T cu = T(LF::cx[i]) * u[0] + T(LF::cy[i]) * u[1] + T(LF::cz[i]) * u[2];
+    df[i] = T(LF::w[i]) * (dphi + phi * cu * inv_csf);
+    dh1[i] = T(LF::w[i]) * (dc1 + c1 * cu * inv_csf);
+    dh2[i] = T(LF::w[i]) * (dc2 + c2 * cu * inv_csf);
+  }
+#pragma unroll
+  for (int i = 0; i < LG::Q; ++i) {
+    const T cu = T(LG::cx[i]) * u[0] + T(LG::cy[i]) * u[1] + T(LG::cz[i]) * u[2];
+    const T si = T(LG::w[i]) * (cu * inv_csg + cu * cu * half_inv_csg2 - uu * T(0.5) * inv_csg);
+    g[i] = p * inv_csg * (i == 0 ? T(LG::w[0] - 1.0) : T(LG::w[i])) + rho * si;
+  }
+}
+
+// ------------------------------------------------- population load / store
+
+template <class L, class S, class T>
+__device__ inline void load_set(const S* __restrict__ src, long long stride, long long node,
+                                int plane0, T (&x)[L::Q]) {
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) x[i] = Codec<S, T>::ld(src[(plane0 + i) * stride + node], T(L::w[i]));
+}
+
+template <class L, class S, class T>
+__device__ inline void store_one(S* __restrict__ dst, long long idx, int i, T x) {
+  dst[idx] = Codec<S, T>::st(x, T(1.0 / L::w[i]));
+}
+
+}  // namespace pflb

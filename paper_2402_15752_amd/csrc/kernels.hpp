@@ -1,0 +1,48 @@
+// Launch entry points of the GPU kernels, called by the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace pflb {
+
+constexpr int kModeStep = 0;    // collide and stream into the other lattice
+constexpr int kModeMacros = 1;  // write the macroscopic fields, no update
+
+// planes of the field buffer (same ids as the CPLB_FIELD_* constants)
+constexpr int kFieldPhi = 0, kFieldP = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz = 4, kFieldC1 = 5,
+              kFieldC2 = 6, kFieldMu = 7, kFieldPsi = 8, kNumFields = 9;
+
+// history planes: u (d of them, stored as 3), phi, c1, c2 of the previous step
+constexpr int kHist2D = 5;  // ux, uy, phi, c1, c2
+constexpr int kHist3D = 6;  // ux, uy, uz, phi, c1, c2
+
+template <class S, class T>
+hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
+                         hipStream_t stream);
+
+template <class S, class T>
+hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
+                         hipStream_t stream);
+
+// equilibrium initialisation from FP64 staging arrays in device memory:
+// phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,
+// each N values; u / p may be null.
+template <class S, class T>
+hipError_t launch_init(int dim, S* lat, T* hist, const double* phi_or_l, const double* c1,
+                       const double* c2, const double* u, const double* p, int from_sdf,
+                       double W, const double (&cab)[4], const KParams<T>& P, hipStream_t stream);
+
+// convert one field plane to FP32 / FP64
+template <class T>
+hipError_t launch_convert(const T* src, void* dst, int dtype, long long n, hipStream_t stream);
+
+// deterministic two-stage FP64 reduction of the field buffer into out[0..6]
+template <class T>
+hipError_t launch_reduce(const T* fields, long long stride, long long n, double rho1, double rho2,
+                         double* partials, int nparts, double* out, hipStream_t stream);
+
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace pflb

@@ -1,0 +1,91 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/cplb.h declares, the binding's struct matches the
+header byte for byte, and parameter validation rejects what it must."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cplb.h")
+
+
+@pytest.fixture(scope="module")
+def cplb():
+    from paper_2402_15752_amd import cplb as C
+    if not os.path.exists(C.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return C
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cplb_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(cplb):
+    names = declared_functions()
+    assert len(names) >= 14
+    lib = cplb.library()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(cplb.EXPORTS) == names
+
+
+def test_params_struct_matches_header(cplb, tmp_path):
+    fields = [f for f, _ in cplb.cplb_params._fields_]
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){",
+             'printf("%zu\\n", sizeof(cplb_params));']
+    for f in fields:
+        lines.append(f'printf("%zu\\n", offsetof(cplb_params, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(cplb.cplb_params)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(cplb.cplb_params, f).offset == off, f
+
+
+def test_workspace_bytes_cover_two_lattices(cplb):
+    for w, qtot, s in ((W.static_drop_64(), 36, 8), (W.rising_bubble_2d(), 36, 4),
+                       (W.rising_droplet_3d(n=64), 40, 4)):
+        n = W.n_nodes(w["params"])
+        b = cplb.cplb_workspace_bytes(cplb.make_params(w["params"]))
+        assert b >= 2 * qtot * n * s
+        assert b < 2 * qtot * n * s * 1.5
+
+
+@pytest.mark.parametrize("bad", [dict(D2=0.0), dict(Keq=0.0), dict(M=-1.0), dict(nx=0),
+                                 dict(rho1=0.0), dict(g=(0, 0, 1e-5)), dict(n_eps=0.0),
+                                 dict(periodic=(1, 0, 1), ny=1), dict(nz=2),
+                                 dict(precision="f32", sigma=float("nan"))])
+def test_validation_rejects(cplb, bad):
+    p = W.params(**bad)
+    with pytest.raises(cplb.CplbError) as e:
+        cplb.cplb_workspace_bytes(cplb.make_params(p))
+    assert e.value.code == cplb.CPLB_EINVAL
+
+
+def test_create_rejects_bad_workspace(cplb):
+    prm = cplb.make_params(W.params())
+    n = cplb.cplb_workspace_bytes(prm)
+    h = ctypes.c_void_p()
+    lib = cplb.library()
+    # null and misaligned workspaces are refused before any device call
+    assert lib.cplb_create(ctypes.byref(prm), None, n, None, ctypes.byref(h)) == cplb.CPLB_EINVAL
+    assert lib.cplb_create(ctypes.byref(prm), ctypes.c_void_p(4096 + 8), n, None,
+                           ctypes.byref(h)) == cplb.CPLB_EINVAL
+    # a workspace smaller than required is refused
+    assert lib.cplb_create(ctypes.byref(prm), ctypes.c_void_p(4096), n - 1, None,
+                           ctypes.byref(h)) == cplb.CPLB_ENOMEM
+    assert lib.cplb_strerror(cplb.CPLB_ENOMEM).decode().startswith("workspace")

@@ -15,8 +15,9 @@ Parameter dictionaries use the keys
     g (3-vector), rho_ref, n_eps
 
 plus, for the GPU library only, ``precision`` ('f64' | 'f32' | 'f32_s16f' |
-'f32_s16b') and the 16-bit storage shifts ``shift_f``, ``shift_g``,
-``shift_h1``, ``shift_h2``.
+'f32_s16b') and the reference state of its stored population deviations,
+``ref_f`` (phi_ref), ``ref_g`` (always 0), ``ref_h1``, ``ref_h2`` (c1_ref,
+c2_ref): the values that fill most of the domain.
 
 Every field array is a numpy float64 array of shape (ny, nx) in 2-D or
 (nz, ny, nx) in 3-D (x fastest in memory).
@@ -31,7 +32,7 @@ DEFAULTS = dict(
     nx=64, ny=64, nz=1, lattice="d2q9", visc_law="linear", periodic=(1, 1, 1),
     rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1, sigma=0.01, W=4.0, M=0.01,
     D1=0.1, D2=0.1, Keq=1.0, A=0.1, g=(0.0, 0.0, 0.0), rho_ref=0.0, n_eps=1e-3,
-    precision="f64", shift_f=0.5, shift_g=0.0, shift_h1=0.0, shift_h2=0.0,
+    precision="f64", ref_f=0.0, ref_g=0.0, ref_h1=0.0, ref_h2=0.0,
 )
 
 
@@ -105,7 +106,7 @@ def static_drop_64():
     p = params(nx=64, ny=64, nz=1, lattice="d2q9", visc_law="linear", periodic=(1, 1, 1),
                rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1, sigma=0.01, W=4.0, M=0.01,
                D1=0.1, D2=0.01, Keq=0.5, A=0.1, g=(0, 0, 0), rho_ref=0.0, precision="f64",
-               shift_f=0.5, shift_g=0.0, shift_h1=0.0, shift_h2=0.0)
+               ref_f=0.0, ref_h1=0.0, ref_h2=0.0)
     l = sdf_sphere(p, (32.0, 32.0), 16.0, inside_positive=True)
     return dict(name="static_drop_64x64_f64", params=p, sdf=l,
                 init=dict(c1=(0.0, 1.0), c2=(0.0, 0.0)), steps=2000)
@@ -123,7 +124,7 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32"):
     p = params(nx=nx, ny=ny, nz=1, lattice="d2q9", visc_law="exp", periodic=(1, 0, 1),
                rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
                D1=1e-3, D2=0.1, Keq=0.2, A=0.1, g=(0.0, -gmag, 0.0), rho_ref=rho1,
-               precision=precision, shift_f=0.5, shift_g=0.0, shift_h1=0.0, shift_h2=0.5)
+               precision=precision, ref_f=1.0, ref_h1=0.0, ref_h2=0.0)
     l = sdf_sphere(p, (nx / 2.0, 3.0 * nx / 8.0), R, inside_positive=False)
     return dict(name=f"rising_bubble_{nx}x{ny}_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=20000)
@@ -141,7 +142,7 @@ def rising_droplet_3d(n=256, precision="f32"):
     p = params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", visc_law="exp", periodic=(1, 1, 0),
                rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
                D1=0.05, D2=0.01, Keq=10.0, A=0.1, g=(0.0, 0.0, -gmag), rho_ref=rho1,
-               precision=precision, shift_f=0.5, shift_g=0.0, shift_h1=0.0, shift_h2=0.5)
+               precision=precision, ref_f=1.0, ref_h1=0.0, ref_h2=0.0)
     l = sdf_sphere(p, (n / 2.0, n / 2.0, 3.0 * R), R, inside_positive=False)
     return dict(name=f"rising_droplet_{n}c_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=5000)
