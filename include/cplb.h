@@ -162,6 +162,20 @@ size_t cplb_state_bytes(const cplb_t* h);
 int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes);
 int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes);
 
+/* Step-kernel variants (tile shape, non-temporal population traffic).
+ * Every variant computes the same step; they differ only in how the work is
+ * tiled and how the population streams are hinted to the caches.
+ * cplb_tune times each compiled variant for probe_steps launches on the
+ * current state and keeps the fastest; the state is left as it was (the
+ * probes write only the idle lattice, the history is saved and restored).
+ * It synchronises the stream; *ms_per_step (may be NULL) receives the best
+ * time per step.  cplb_set_variant returns CPLB_EINVAL for an unknown id. */
+int cplb_num_variants(const cplb_t* h);
+int cplb_get_variant(const cplb_t* h);
+int cplb_set_variant(cplb_t* h, int variant);
+const char* cplb_variant_name(const cplb_t* h, int variant);
+int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step);
+
 /* Error text of the last failed call on h, and of a return code. */
 const char* cplb_last_error(const cplb_t* h);
 const char* cplb_strerror(int code);

@@ -27,7 +27,8 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
            "cplb_read_field", "cplb_reduce", "cplb_step_count", "cplb_state_bytes",
            "cplb_save_state", "cplb_load_state", "cplb_last_error", "cplb_strerror",
-           "cplb_destroy")
+           "cplb_destroy", "cplb_num_variants", "cplb_get_variant", "cplb_set_variant",
+           "cplb_variant_name", "cplb_tune")
 
 
 class cplb_params(ctypes.Structure):
@@ -82,6 +83,12 @@ def library():
         L.cplb_strerror.restype = ctypes.c_char_p
         L.cplb_destroy.argtypes = [vp]
         L.cplb_destroy.restype = None
+        L.cplb_num_variants.argtypes = [vp]
+        L.cplb_get_variant.argtypes = [vp]
+        L.cplb_set_variant.argtypes = [vp, ctypes.c_int]
+        L.cplb_variant_name.argtypes = [vp, ctypes.c_int]
+        L.cplb_variant_name.restype = ctypes.c_char_p
+        L.cplb_tune.argtypes = [vp, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -188,6 +195,28 @@ def cplb_destroy(h):
     library().cplb_destroy(h)
 
 
+def cplb_num_variants(h) -> int:
+    return int(library().cplb_num_variants(h))
+
+
+def cplb_get_variant(h) -> int:
+    return int(library().cplb_get_variant(h))
+
+
+def cplb_set_variant(h, v: int):
+    _check(h, library().cplb_set_variant(h, int(v)))
+
+
+def cplb_variant_name(h, v: int) -> str:
+    return library().cplb_variant_name(h, int(v)).decode()
+
+
+def cplb_tune(h, probe_steps: int) -> float:
+    ms = ctypes.c_double()
+    _check(h, library().cplb_tune(h, int(probe_steps), ctypes.byref(ms)))
+    return ms.value
+
+
 # ------------------------------------------------------- convenience class
 
 class Lattice:
@@ -267,6 +296,21 @@ class Lattice:
     @property
     def step_count(self):
         return cplb_step_count(self._h)
+
+    @property
+    def variant(self):
+        return cplb_get_variant(self._h)
+
+    @variant.setter
+    def variant(self, v):
+        cplb_set_variant(self._h, v)
+
+    def variant_names(self):
+        return [cplb_variant_name(self._h, v) for v in range(cplb_num_variants(self._h))]
+
+    def tune(self, probe_steps=20):
+        """Pick the fastest compiled step-kernel variant; returns ms/step."""
+        return cplb_tune(self._h, probe_steps)
 
     def save_state(self) -> bytes:
         return cplb_save_state(self._h)

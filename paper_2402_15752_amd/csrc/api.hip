@@ -143,6 +143,7 @@ struct cplb {
   int cur;
   int64_t step;
   bool fields_valid;
+  int variant;  // compiled step-kernel variant in use
   KParams<double> k64;
   KParams<float> k32;
   char err[512];
@@ -166,8 +167,22 @@ hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, int mode) {
   const S* src = (const S*)h->lat[h->cur];
   S* dst = (S*)h->lat[h->cur ^ 1];
   if (h->G.dim == 2)
-    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->stream);
-  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->stream);
+    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
+                               h->stream);
+  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
+                             h->stream);
+}
+
+int num_variants(const cplb_t* h) { return h->G.dim == 2 ? kVariants2D : kVariants3D; }
+
+// default variant per lattice and storage width (set from measurements;
+// cplb_tune can pick another for a given grid)
+// Fastest variant measured on MI355X for the rising-bubble (256x1024 D2Q9) and
+// rising-droplet (256^3 D3Q19+D3Q7) workloads; cplb_tune re-checks on the
+// caller's own state.
+int default_variant(const cplb_params* p) {
+  if (p->lattice == CPLB_D2Q9) return 3;  // 128x4
+  return 1;                               // 64x4
 }
 
 hipError_t run_kernel(cplb_t* h, int mode) {
@@ -290,6 +305,7 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->cur = 0;
   h->step = 0;
   h->fields_valid = false;
+  h->variant = default_variant(prm);
   h->k64 = make_kparams<double>(prm, G);
   h->k32 = make_kparams<float>(prm, G);
   h->err[0] = 0;
@@ -432,6 +448,76 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
   }
   h->step = hd.step;
   h->fields_valid = false;
+  return CPLB_OK;
+}
+
+int cplb_num_variants(const cplb_t* h) { return h ? num_variants(h) : 0; }
+
+int cplb_get_variant(const cplb_t* h) { return h ? h->variant : -1; }
+
+const char* cplb_variant_name(const cplb_t* h, int v) {
+  if (!h) return "?";
+  return h->G.dim == 2 ? step2d_variant_name(v) : step3d_variant_name(v);
+}
+
+int cplb_set_variant(cplb_t* h, int v) {
+  if (!h) return CPLB_EINVAL;
+  if (v < 0 || v >= num_variants(h)) return set_err(h, CPLB_EINVAL, "no such kernel variant%s", "");
+  h->variant = v;
+  return CPLB_OK;
+}
+
+int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step) {
+  if (!h) return CPLB_EINVAL;
+  if (probe_steps < 1) return set_err(h, CPLB_EINVAL, "probe_steps must be >= 1%s", "");
+  // The probes read the current lattice and write the idle one, which is
+  // scratch; they also overwrite the history, so it is parked in the field
+  // buffer (at least as many planes, same type) and put back afterwards.
+  const size_t hb = (size_t)h->G.nhist * h->G.stride * h->G.s_cmp;
+  int rc = hip_check(h, hipMemcpyAsync(h->fields, h->hist, hb, hipMemcpyDeviceToDevice, h->stream),
+                     "tune: park history");
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  rc = hip_check(h, hipEventCreate(&e0), "tune: event");
+  if (rc) return rc;
+  rc = hip_check(h, hipEventCreate(&e1), "tune: event");
+  if (rc) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  const int keep = h->variant;
+  int best = keep;
+  float best_ms = 0;
+  for (int v = 0; v < num_variants(h) && rc == CPLB_OK; ++v) {
+    h->variant = v;
+    rc = hip_check(h, run_kernel(h, kModeStep), "tune: warm-up");  // first launch loads code
+    if (rc) break;
+    rc = hip_check(h, hipEventRecord(e0, h->stream), "tune: record");
+    for (int k = 0; k < probe_steps && rc == CPLB_OK; ++k)
+      rc = hip_check(h, run_kernel(h, kModeStep), "tune: probe");
+    if (rc) break;
+    rc = hip_check(h, hipEventRecord(e1, h->stream), "tune: record");
+    if (rc) break;
+    rc = hip_check(h, hipEventSynchronize(e1), "tune: wait");
+    if (rc) break;
+    float ms = 0;
+    rc = hip_check(h, hipEventElapsedTime(&ms, e0, e1), "tune: time");
+    if (rc) break;
+    if (v == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->variant = rc == CPLB_OK ? best : keep;
+  int rc2 = hip_check(h, hipMemcpyAsync(h->hist, h->fields, hb, hipMemcpyDeviceToDevice, h->stream),
+                      "tune: restore history");
+  if (rc2 == CPLB_OK) rc2 = hip_check(h, hipStreamSynchronize(h->stream), "tune: synchronise");
+  h->fields_valid = false;
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (ms_per_step) *ms_per_step = best_ms / probe_steps;
   return CPLB_OK;
 }
 

@@ -241,34 +241,39 @@ __device__ inline T relax(T x, T xeq, T del, T hdel, T src) {
   return del * neq + (xeq - neq) + hdel * src;
 }
 
+// The collisions below hand each post-collision population to emit(i, X_i*)
+// as soon as it is formed, so a kernel can stream it out at once and keep
+// few values live.  The rest-direction equilibrium needs the sum of the
+// others; that sum is formed in a first, cheap pass instead of holding all
+// equilibria in registers.
+
 // phase field: f^eq = w phi (1 + c.u/cs^2), F_i = w [c.d_t(phi u)/cs^2 + c.n 4 phi (1-phi)/W]
-template <class LF, class T>
-__device__ inline void collide_f(const KParams<T>& P, T (&df)[LF::Q], const Node<T>& s,
-                                 const T (&n)[3], const Flow<T>& fl, const T (&dJphi)[3]) {
+template <class LF, class T, class Emit>
+__device__ inline void collide_f(const KParams<T>& P, const T (&df)[LF::Q], const Node<T>& s,
+                                 const T (&n)[3], const Flow<T>& fl, const T (&dJphi)[3],
+                                 Emit&& emit) {
   const T sharp = P.four_over_W * s.phi * s.omphi;
-  T eq[LF::Q];
+  auto eq = [&](int i) {
+    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+    return T(LF::w[i]) * s.dphi + kw<LF, T>(i) * s.phi * cu;
+  };
   T rest = s.dphi;
 #pragma unroll
-  for (int i = 1; i < LF::Q; ++i) {
-    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
-    eq[i] = T(LF::w[i]) * s.dphi + kw<LF, T>(i) * s.phi * cu;
-    rest -= eq[i];
-  }
-  eq[0] = rest;
+  for (int i = 1; i < LF::Q; ++i) rest -= eq(i);
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
     const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
     const T cj = T(LF::cx[i]) * dJphi[0] + T(LF::cy[i]) * dJphi[1] + T(LF::cz[i]) * dJphi[2];
     const T Fi = i == 0 ? T(0) : kw<LF, T>(i) * cj + T(LF::w[i]) * cn * sharp;
-    df[i] = relax(df[i], eq[i], P.del_f, P.hdel_f, Fi);
+    emit(i, relax(df[i], i == 0 ? rest : eq(i), P.del_f, P.hdel_f, Fi));
   }
 }
 
 // flow: g^eq = p/cs^2 (w_i - delta_i0) + rho s_i(u),
 //       G_i = w [c.F/cs^2 + (rho1-rho2)(c.u)(c.grad phi)/cs^2], tau_g = 1/2 + mu/(rho cs^2)
-template <class LG, class T>
-__device__ inline void collide_g(const KParams<T>& P, T (&g)[LG::Q], const T (&gphi)[3],
-                                 const Flow<T>& fl) {
+template <class LG, class T, class Emit>
+__device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const T (&gphi)[3],
+                                 const Flow<T>& fl, Emit&& emit) {
   constexpr T inv_csg = T(1.0 / LG::cs2);
   constexpr T half_inv_csg2 = T(0.5 / (LG::cs2 * LG::cs2));
   const T nu = fl.mu * inv_csg / fl.rho;  // tau_g - 1/2
@@ -277,24 +282,22 @@ __device__ inline void collide_g(const KParams<T>& P, T (&g)[LG::Q], const T (&g
   const T hdel_g = T(0.5) * del_g;
   const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
   const T iso = uu * T(0.5) * inv_csg;
-  T eq[LG::Q];
-  T rest = T(0);
-#pragma unroll
-  for (int i = 1; i < LG::Q; ++i) {
-    const T cu = T(LG::cx[i]) * fl.u[0] + T(LG::cy[i]) * fl.u[1] + T(LG::cz[i]) * fl.u[2];
-    // p/cs^2 w_i = v_i Pi with Pi the bracket of the pressure formula
-    eq[i] = kp<LG, T>(i) * fl.pi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
-            kw<LG, T>(i) * fl.rho * cu;
-    rest -= eq[i];
-  }
-  eq[0] = rest;  // sum_i g_i^eq = 0
+  // p/cs^2 w_i = v_i Pi with Pi the bracket of the pressure formula
+  auto eq = [&](int i, T cu) {
+    return kp<LG, T>(i) * fl.pi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
+           kw<LG, T>(i) * fl.rho * cu;
+  };
+  // g_0^eq = p/cs^2 (w0 - 1) + rho s_0 = -Pi - rho w0 u.u/(2 cs^2): its
+  // pressure part is exactly -sum_{i>0} v_i Pi, the rounded-weight residue
+  // is left only in the O(u^2) term
+  const T rest = -fl.pi - T(LG::w[0]) * fl.rho * iso;
 #pragma unroll
   for (int i = 0; i < LG::Q; ++i) {
     const T cu = T(LG::cx[i]) * fl.u[0] + T(LG::cy[i]) * fl.u[1] + T(LG::cz[i]) * fl.u[2];
     const T cF = T(LG::cx[i]) * fl.F[0] + T(LG::cy[i]) * fl.F[1] + T(LG::cz[i]) * fl.F[2];
     const T cg = T(LG::cx[i]) * gphi[0] + T(LG::cy[i]) * gphi[1] + T(LG::cz[i]) * gphi[2];
     const T Gi = i == 0 ? T(0) : kw<LG, T>(i) * (cF + P.drho * cu * cg);
-    g[i] = relax(g[i], eq[i], del_g, hdel_g, Gi);
+    emit(i, relax(g[i], i == 0 ? rest : eq(i, cu), del_g, hdel_g, Gi));
   }
 }
 
@@ -302,51 +305,77 @@ __device__ inline void collide_g(const KParams<T>& P, T (&g)[LG::Q], const T (&g
 //   H_1 = w [c.d_t(c1 u)/cs^2 + c.n 4 (1-phi) c1/W + A D_m (Keq c2 phi - c1 (1-phi))],
 //   H_2 = w [c.d_t(c2 u)/cs^2 - c.n 4 phi c2/W + A D_m (c1 (1-phi) - Keq c2 phi)],
 //   ~H_1 = -w D_m grad phi . grad psi = -~H_2
-template <class LF, class T>
-__device__ inline void collide_h(const KParams<T>& P, T (&dh1)[LF::Q], T (&dh2)[LF::Q],
+template <class LF, class T, class Emit>
+__device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], const T (&dh2)[LF::Q],
                                  const Node<T>& s, const T (&n)[3], const T (&gphi)[3],
                                  const T (&gpsi)[3], const Flow<T>& fl, const T (&dJ1)[3],
-                                 const T (&dJ2)[3]) {
+                                 const T (&dJ2)[3], Emit&& emit) {
   const T M1 = P.A * s.Dm * (P.Keq * s.c2 * s.phi - s.c1 * s.omphi);
   const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]);
   const T fl1 = P.four_over_W * s.omphi * s.c1;
   const T fl2 = P.four_over_W * s.phi * s.c2;
-  T e1[LF::Q], e2[LF::Q];
+  auto cu_of = [&](int i) {
+    return T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+  };
   T r1 = s.dc1, r2 = s.dc2;
 #pragma unroll
   for (int i = 1; i < LF::Q; ++i) {
-    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
-    e1[i] = T(LF::w[i]) * s.dc1 + kw<LF, T>(i) * s.c1 * cu;
-    e2[i] = T(LF::w[i]) * s.dc2 + kw<LF, T>(i) * s.c2 * cu;
-    r1 -= e1[i];
-    r2 -= e2[i];
+    const T cu = cu_of(i);
+    r1 -= T(LF::w[i]) * s.dc1 + kw<LF, T>(i) * s.c1 * cu;
+    r2 -= T(LF::w[i]) * s.dc2 + kw<LF, T>(i) * s.c2 * cu;
   }
-  e1[0] = r1;
-  e2[0] = r2;
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
     const T w = T(LF::w[i]);
+    const T cu = cu_of(i);
+    const T e1 = i == 0 ? r1 : w * s.dc1 + kw<LF, T>(i) * s.c1 * cu;
+    const T e2 = i == 0 ? r2 : w * s.dc2 + kw<LF, T>(i) * s.c2 * cu;
     const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
     const T cj1 = T(LF::cx[i]) * dJ1[0] + T(LF::cy[i]) * dJ1[1] + T(LF::cz[i]) * dJ1[2];
     const T cj2 = T(LF::cx[i]) * dJ2[0] + T(LF::cy[i]) * dJ2[1] + T(LF::cz[i]) * dJ2[2];
     const T k = kw<LF, T>(i);
     const T H1 = k * cj1 + w * (cn * fl1 + M1);
     const T H2 = k * cj2 - w * (cn * fl2 + M1);
-    dh1[i] = relax(dh1[i], e1[i], P.del_h1, P.hdel_h1, H1) - w * aux;
-    dh2[i] = relax(dh2[i], e2[i], P.del_h2, P.hdel_h2, H2) + w * aux;
+    emit(i, relax(dh1[i], e1, P.del_h1, P.hdel_h1, H1) - w * aux,
+         relax(dh2[i], e2, P.del_h2, P.hdel_h2, H2) + w * aux);
   }
 }
 
+// All four sets at one node, post-collision values handed to the emitters.
+template <class LF, class LG, class T, class EF, class EG, class EH>
+__device__ inline void collide(const KParams<T>& P, const T (&df)[LF::Q], const T (&g)[LG::Q],
+                               const T (&dh1)[LF::Q], const T (&dh2)[LF::Q], const Node<T>& s,
+                               const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
+                               const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3],
+                               EF&& emit_f, EG&& emit_g, EH&& emit_h) {
+  T n[3];
+  normal(P, gphi, n);
+  collide_g<LG>(P, g, gphi, fl, emit_g);
+  collide_f<LF>(P, df, s, n, fl, dJphi, emit_f);
+  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h);
+}
+
+// In-place form (post-collision values written back into the arrays).
 template <class LF, class LG, class T>
 __device__ inline void collide(const KParams<T>& P, T (&df)[LF::Q], T (&g)[LG::Q],
                                T (&dh1)[LF::Q], T (&dh2)[LF::Q], const Node<T>& s,
                                const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
                                const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3]) {
-  T n[3];
-  normal(P, gphi, n);
-  collide_f<LF>(P, df, s, n, fl, dJphi);
-  collide_g<LG>(P, g, gphi, fl);
-  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2);
+  T of[LF::Q], og[LG::Q], o1[LF::Q], o2[LF::Q];
+  collide<LF, LG>(P, df, g, dh1, dh2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
+                  [&](int i, T v) { of[i] = v; }, [&](int i, T v) { og[i] = v; },
+                  [&](int i, T a, T b) {
+                    o1[i] = a;
+                    o2[i] = b;
+                  });
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    df[i] = of[i];
+    dh1[i] = o1[i];
+    dh2[i] = o2[i];
+  }
+#pragma unroll
+  for (int i = 0; i < LG::Q; ++i) g[i] = og[i];
 }
 
 // ------------------------------------------------------------- equilibria
@@ -377,17 +406,44 @@ __device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const 
 }
 
 // ------------------------------------------------- population load / store
+//
+// NTS selects non-temporal loads and stores for the population streams:
+// each value is read once and written once per step, so they need not
+// displace the halo and history lines in the caches.
 
-template <class L, class S, class T>
+template <bool NTS, class S>
+__device__ inline S ld_pop(const S* p) {
+  if constexpr (!NTS) {
+    return *p;
+  } else if constexpr (sizeof(S) == 2) {
+    return __builtin_bit_cast(S, __builtin_nontemporal_load((const unsigned short*)p));
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+}
+
+template <bool NTS, class S>
+__device__ inline void st_pop(S* p, S v) {
+  if constexpr (!NTS) {
+    *p = v;
+  } else if constexpr (sizeof(S) == 2) {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
+  } else {
+    __builtin_nontemporal_store(v, p);
+  }
+}
+
+template <class L, bool NTS = false, class S, class T>
 __device__ inline void load_set(const S* __restrict__ src, long long stride, long long node,
                                 int plane0, T (&x)[L::Q]) {
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) x[i] = Codec<S, T>::ld(src[(plane0 + i) * stride + node], T(L::w[i]));
+  for (int i = 0; i < L::Q; ++i)
+    x[i] = Codec<S, T>::ld(ld_pop<NTS>(src + (plane0 + i) * stride + node), T(L::w[i]));
 }
 
-template <class L, class S, class T>
+template <class L, bool NTS = false, class S, class T>
 __device__ inline void store_one(S* __restrict__ dst, long long idx, int i, T x) {
-  dst[idx] = Codec<S, T>::st(x, T(1.0 / L::w[i]));
+  st_pop<NTS>(dst + idx, Codec<S, T>::st(x, T(1.0 / L::w[i])));
 }
 
 }  // namespace pflb

@@ -18,13 +18,20 @@ constexpr int kFieldPhi = 0, kFieldP = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz =
 constexpr int kHist2D = 5;  // ux, uy, phi, c1, c2
 constexpr int kHist3D = 6;  // ux, uy, uz, phi, c1, c2
 
+// step kernels; `variant` picks a compiled tile shape / streaming hint
+// (0 is the default; the macros mode always uses variant 0)
+constexpr int kVariants2D = 8;
+constexpr int kVariants3D = 8;
+const char* step2d_variant_name(int v);
+const char* step3d_variant_name(int v);
+
 template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         hipStream_t stream);
+                         int variant, hipStream_t stream);
 
 template <class S, class T>
 hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         hipStream_t stream);
+                         int variant, hipStream_t stream);
 
 // equilibrium initialisation from FP64 staging arrays in device memory:
 // phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,

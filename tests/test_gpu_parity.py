@@ -261,3 +261,70 @@ def test_fp32_field_readout_matches_fp64_readout(cplb):
     a = g.field("phi", dtype=torch.float32).cpu().numpy()
     b = g.field("phi", dtype=torch.float64).cpu().numpy()
     assert np.array_equal(a.astype(np.float64), b)
+
+
+# ------------------------------------------------------ kernel variants
+
+VARIANT_CASES = [
+    ("d2q9 f64", dict(nx=67, ny=37, periodic=(1, 0, 1), precision="f64")),
+    ("d2q9 f32", dict(nx=130, ny=9, periodic=(0, 1, 1), precision="f32")),
+    ("d2q9 s16f", dict(nx=67, ny=37, periodic=(1, 1, 1), precision="f32_s16f")),
+    ("d3 f64", dict(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=(1, 0, 0),
+                    precision="f64")),
+    ("d3 f32", dict(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=(0, 1, 0),
+                    precision="f32")),
+    ("d3 s16b", dict(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=(1, 1, 0),
+                     precision="f32_s16b")),
+]
+
+
+@pytest.mark.parametrize("label,kw", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_every_variant_is_bitwise_identical(cplb, label, kw):
+    """Variants only retile the same per-node arithmetic, so every one of them
+    must give the default variant's fields bit for bit (ragged tiles, walls)."""
+    p = W.params(sigma=2e-3, rho1=3.0, rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07,
+                 D2=0.02, Keq=0.6, A=0.4, rho_ref=1.5,
+                 g=(1e-5, -2e-5, 3e-5 if "nz" in kw else 0.0), **kw)
+    f = W.random_fields(p, seed=11)
+    names = ALL3 if "nz" in kw else ALL2
+    out = {}
+    g = cplb.Lattice(p)
+    nv = len(g.variant_names())
+    assert nv >= 2
+    for v in range(nv):
+        g.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+        g.variant = v
+        g.step(5)
+        out[v] = {k: g.field(k).cpu().numpy() for k in names}
+    say(f"  {label}: {nv} variants {g.variant_names()}")
+    for v in range(1, nv):
+        for k in names:
+            assert np.array_equal(out[0][k], out[v][k]), (label, g.variant_names()[v], k)
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19_d3q7"])
+def test_tune_leaves_the_state_unchanged(cplb, lattice):
+    """cplb_tune probes every variant on the idle lattice and restores the
+    history: the run it interrupts continues bit for bit."""
+    w = W.rising_bubble_2d(nx=64, ny=128) if lattice == "d2q9" else W.rising_droplet_3d(n=48)
+    a = cplb.Lattice(w["params"])
+    a.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    b = cplb.Lattice(w["params"])
+    b.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    a.step(7)
+    b.step(7)
+    ms = a.tune(3)
+    assert ms > 0 and 0 <= a.variant < len(a.variant_names())
+    assert a.step_count == 7
+    a.step(9)
+    b.step(9)
+    names = ALL3 if lattice != "d2q9" else ALL2
+    for k in names:
+        assert np.array_equal(a.field(k).cpu().numpy(), b.field(k).cpu().numpy()), k
+
+
+def test_set_variant_rejects_unknown_id(cplb):
+    g = cplb.Lattice(W.params(nx=16, ny=16, precision="f32"))
+    with pytest.raises(cplb.CplbError) as e:
+        g.variant = len(g.variant_names())
+    assert e.value.code == cplb.CPLB_EINVAL
