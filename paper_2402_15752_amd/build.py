@@ -3,6 +3,12 @@
 Packed FP32 instructions are switched off for all device code
 (-target-feature -packed-fp32-ops); the host pass warns that it does not
 know that feature, which is harmless.
+
+Floating-point contraction is limited to single source expressions
+(-ffp-contract=on): a multiply and an add are fused where one expression
+writes them, never across statements, so every step-kernel variant (tile
+shape, caching hint) performs the same roundings and gives bit-identical
+results.
 """
 import os
 import subprocess
@@ -28,6 +34,7 @@ def build(verbose=False, jobs=None):
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmd = [hipcc(), "-c", "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+               "-ffp-contract=on",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include"),
                "-o", obj, os.path.join(CSRC, src)]

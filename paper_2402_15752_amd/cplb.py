@@ -223,7 +223,10 @@ class Lattice:
     """One lattice on one GPU.  Fields are returned as torch tensors on the
     device, shaped (ny, nx) or (nz, ny, nx)."""
 
-    def __init__(self, p: dict, device="cuda:0"):
+    def __init__(self, p: dict, device="cuda:0", stream=None):
+        """stream: the torch.cuda.Stream every call of this lattice is ordered
+        on (default: the current stream of `device`).  A stream of its own is
+        needed to capture steps in a graph."""
         import torch
 
         if not torch.cuda.is_available():
@@ -238,7 +241,7 @@ class Lattice:
         nbytes = cplb_workspace_bytes(self._prm)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream(self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = cplb_create(self._prm, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
 
     def close(self):
@@ -279,8 +282,15 @@ class Lattice:
         torch = self.torch
         dtype = dtype or torch.float64
         out = torch.empty(self.shape, dtype=dtype, device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        other = cur != self.stream
+        if other:  # the new tensor is used on the library stream, then by the caller
+            self.stream.wait_stream(cur)
         cplb_read_field(self._h, FIELDS[name], out.data_ptr(),
                         DTYPE_F64 if dtype == torch.float64 else DTYPE_F32)
+        if other:
+            cur.wait_stream(self.stream)
+            out.record_stream(self.stream)
         return out
 
     def fields(self, names=("phi", "c1", "c2", "ux", "uy", "p")):

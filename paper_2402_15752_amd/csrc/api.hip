@@ -22,7 +22,7 @@ struct Geometry {
   long long n;       // nodes
   long long stride;  // elements per plane
   size_t s_pop, s_cmp;
-  size_t lat_bytes, hist_bytes, field_bytes, part_bytes, total;
+  size_t lat_bytes, hist_bytes, field_bytes, part_bytes, kp_bytes, total;
 };
 
 int validate(const cplb_params* p, char* err, size_t errn) {
@@ -76,7 +76,8 @@ Geometry geometry(const cplb_params* p) {
   G.hist_bytes = align_up((size_t)G.nhist * G.stride * G.s_cmp, kAlign);
   G.field_bytes = align_up((size_t)kNumFields * G.stride * G.s_cmp, kAlign);
   G.part_bytes = align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
-  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes;
+  G.kp_bytes = align_up(sizeof(KParams<double>), kAlign) + align_up(sizeof(KParams<float>), kAlign);
+  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes + G.kp_bytes;
   return G;
 }
 
@@ -144,8 +145,10 @@ struct cplb {
   int64_t step;
   bool fields_valid;
   int variant;  // compiled step-kernel variant in use
-  KParams<double> k64;
+  KParams<double> k64;  // lattice constants (host copies)
   KParams<float> k32;
+  KParams<double>* k64_dev;  // the same, in the workspace, read by the 3-D kernels
+  KParams<float>* k32_dev;
   char err[512];
 };
 
@@ -163,13 +166,13 @@ int hip_check(cplb_t* h, hipError_t e, const char* where) {
 }
 
 template <class S, class T>
-hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, int mode) {
+hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, const KParams<T>* Kdev, int mode) {
   const S* src = (const S*)h->lat[h->cur];
   S* dst = (S*)h->lat[h->cur ^ 1];
   if (h->G.dim == 2)
     return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
                                h->stream);
-  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
+  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
                              h->stream);
 }
 
@@ -182,15 +185,17 @@ int num_variants(const cplb_t* h) { return h->G.dim == 2 ? kVariants2D : kVarian
 // caller's own state.
 int default_variant(const cplb_params* p) {
   if (p->lattice == CPLB_D2Q9) return 3;  // 128x4
-  return 1;                               // 64x4
+  // 16-bit storage: 64x4, f / h re-read before their collision (fewer
+  // registers, 3 waves per SIMD); FP32 / FP64: 64x4, registers carried
+  return p->precision >= CPLB_F32_S16F ? 0 : 3;
 }
 
 hipError_t run_kernel(cplb_t* h, int mode) {
   switch (h->prm.precision) {
-    case CPLB_F64: return dispatch_step<double, double>(h, h->k64, mode);
-    case CPLB_F32: return dispatch_step<float, float>(h, h->k32, mode);
-    case CPLB_F32_S16F: return dispatch_step<__half, float>(h, h->k32, mode);
-    default: return dispatch_step<__hip_bfloat16, float>(h, h->k32, mode);
+    case CPLB_F64: return dispatch_step<double, double>(h, h->k64, h->k64_dev, mode);
+    case CPLB_F32: return dispatch_step<float, float>(h, h->k32, h->k32_dev, mode);
+    case CPLB_F32_S16F: return dispatch_step<__half, float>(h, h->k32, h->k32_dev, mode);
+    default: return dispatch_step<__hip_bfloat16, float>(h, h->k32, h->k32_dev, mode);
   }
 }
 
@@ -302,6 +307,10 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->fields = h->ws + off;
   off += G.field_bytes;
   h->partials = (double*)(h->ws + off);
+  off += G.part_bytes;
+  h->k64_dev = (KParams<double>*)(h->ws + off);
+  off += align_up(sizeof(KParams<double>), kAlign);
+  h->k32_dev = (KParams<float>*)(h->ws + off);
   h->cur = 0;
   h->step = 0;
   h->fields_valid = false;
@@ -309,6 +318,16 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->k64 = make_kparams<double>(prm, G);
   h->k32 = make_kparams<float>(prm, G);
   h->err[0] = 0;
+  rc = hip_check(h, hipMemcpyAsync(h->k64_dev, &h->k64, sizeof(h->k64), hipMemcpyHostToDevice,
+                                   h->stream), "upload of lattice constants");
+  if (!rc)
+    rc = hip_check(h, hipMemcpyAsync(h->k32_dev, &h->k32, sizeof(h->k32), hipMemcpyHostToDevice,
+                                     h->stream), "upload of lattice constants");
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "upload of lattice constants");
+  if (rc) {
+    delete h;
+    return rc;
+  }
   *out = h;
   return CPLB_OK;
 }

@@ -90,6 +90,26 @@ __device__ inline bool finite_t(T x) {
   return x == x && x - x == T(0);
 }
 
+// c_i . v over the nonzero components of direction i only.  The lattice
+// components are 0 or +-1 and i is a constant after unrolling, so this is
+// one to three adds; written as the full sum, the 0 * v terms could not be
+// dropped by the compiler (0 * inf is not 0) and would cost an FMA each.
+template <class L, class T>
+__device__ inline T cdot(int i, const T (&v)[3]) {
+  T r = T(0);
+  bool have = false;
+  auto add = [&](int c, T x) {
+    if (!c) return;
+    const T t = c > 0 ? x : -x;
+    r = have ? r + t : t;
+    have = true;
+  };
+  add(L::cx[i], v[0]);
+  add(L::cy[i], v[1]);
+  add(L::cz[i], v[2]);
+  return r;
+}
+
 // Macroscopic state of one node at the current time level.
 template <class T>
 struct Node {
@@ -107,9 +127,9 @@ struct Node {
 template <class LF, class T>
 __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const T (&dh1)[LF::Q],
                                const T (&dh2)[LF::Q], Node<T>& s) {
-  T s0 = 0, s1 = 0, s2 = 0;
+  T s0 = df[0], s1 = dh1[0], s2 = dh2[0];
 #pragma unroll
-  for (int i = 0; i < LF::Q; ++i) {
+  for (int i = 1; i < LF::Q; ++i) {
     s0 += df[i];
     s1 += dh1[i];
     s2 += dh2[i];
@@ -254,7 +274,7 @@ __device__ inline void collide_f(const KParams<T>& P, const T (&df)[LF::Q], cons
                                  Emit&& emit) {
   const T sharp = P.four_over_W * s.phi * s.omphi;
   auto eq = [&](int i) {
-    const T cu = T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+    const T cu = cdot<LF>(i, fl.u);
     return T(LF::w[i]) * s.dphi + kw<LF, T>(i) * s.phi * cu;
   };
   T rest = s.dphi;
@@ -262,8 +282,8 @@ __device__ inline void collide_f(const KParams<T>& P, const T (&df)[LF::Q], cons
   for (int i = 1; i < LF::Q; ++i) rest -= eq(i);
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
-    const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
-    const T cj = T(LF::cx[i]) * dJphi[0] + T(LF::cy[i]) * dJphi[1] + T(LF::cz[i]) * dJphi[2];
+    const T cn = cdot<LF>(i, n);
+    const T cj = cdot<LF>(i, dJphi);
     const T Fi = i == 0 ? T(0) : kw<LF, T>(i) * cj + T(LF::w[i]) * cn * sharp;
     emit(i, relax(df[i], i == 0 ? rest : eq(i), P.del_f, P.hdel_f, Fi));
   }
@@ -293,9 +313,9 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
   const T rest = -fl.pi - T(LG::w[0]) * fl.rho * iso;
 #pragma unroll
   for (int i = 0; i < LG::Q; ++i) {
-    const T cu = T(LG::cx[i]) * fl.u[0] + T(LG::cy[i]) * fl.u[1] + T(LG::cz[i]) * fl.u[2];
-    const T cF = T(LG::cx[i]) * fl.F[0] + T(LG::cy[i]) * fl.F[1] + T(LG::cz[i]) * fl.F[2];
-    const T cg = T(LG::cx[i]) * gphi[0] + T(LG::cy[i]) * gphi[1] + T(LG::cz[i]) * gphi[2];
+    const T cu = cdot<LG>(i, fl.u);
+    const T cF = cdot<LG>(i, fl.F);
+    const T cg = cdot<LG>(i, gphi);
     const T Gi = i == 0 ? T(0) : kw<LG, T>(i) * (cF + P.drho * cu * cg);
     emit(i, relax(g[i], i == 0 ? rest : eq(i, cu), del_g, hdel_g, Gi));
   }
@@ -315,7 +335,7 @@ __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], con
   const T fl1 = P.four_over_W * s.omphi * s.c1;
   const T fl2 = P.four_over_W * s.phi * s.c2;
   auto cu_of = [&](int i) {
-    return T(LF::cx[i]) * fl.u[0] + T(LF::cy[i]) * fl.u[1] + T(LF::cz[i]) * fl.u[2];
+    return cdot<LF>(i, fl.u);
   };
   T r1 = s.dc1, r2 = s.dc2;
 #pragma unroll
@@ -330,9 +350,9 @@ __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], con
     const T cu = cu_of(i);
     const T e1 = i == 0 ? r1 : w * s.dc1 + kw<LF, T>(i) * s.c1 * cu;
     const T e2 = i == 0 ? r2 : w * s.dc2 + kw<LF, T>(i) * s.c2 * cu;
-    const T cn = T(LF::cx[i]) * n[0] + T(LF::cy[i]) * n[1] + T(LF::cz[i]) * n[2];
-    const T cj1 = T(LF::cx[i]) * dJ1[0] + T(LF::cy[i]) * dJ1[1] + T(LF::cz[i]) * dJ1[2];
-    const T cj2 = T(LF::cx[i]) * dJ2[0] + T(LF::cy[i]) * dJ2[1] + T(LF::cz[i]) * dJ2[2];
+    const T cn = cdot<LF>(i, n);
+    const T cj1 = cdot<LF>(i, dJ1);
+    const T cj2 = cdot<LF>(i, dJ2);
     const T k = kw<LF, T>(i);
     const T H1 = k * cj1 + w * (cn * fl1 + M1);
     const T H2 = k * cj2 - w * (cn * fl2 + M1);
@@ -392,14 +412,14 @@ __device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const 
   const T dphi = phi - P.ref_phi, dc1 = c1 - P.ref_c1, dc2 = c2 - P.ref_c2;
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
-    const T cu = T(LF::cx[i]) * u[0] + T(LF::cy[i]) * u[1] + T(LF::cz[i]) * u[2];
+    const T cu = cdot<LF>(i, u);
     df[i] = T(LF::w[i]) * (dphi + phi * cu * inv_csf);
     dh1[i] = T(LF::w[i]) * (dc1 + c1 * cu * inv_csf);
     dh2[i] = T(LF::w[i]) * (dc2 + c2 * cu * inv_csf);
   }
 #pragma unroll
   for (int i = 0; i < LG::Q; ++i) {
-    const T cu = T(LG::cx[i]) * u[0] + T(LG::cy[i]) * u[1] + T(LG::cz[i]) * u[2];
+    const T cu = cdot<LG>(i, u);
     const T si = T(LG::w[i]) * (cu * inv_csg + cu * cu * half_inv_csg2 - uu * T(0.5) * inv_csg);
     g[i] = p * inv_csg * (i == 0 ? T(LG::w[0] - 1.0) : T(LG::w[i])) + rho * si;
   }

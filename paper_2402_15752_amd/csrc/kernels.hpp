@@ -29,9 +29,11 @@ template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
                          int variant, hipStream_t stream);
 
+// P: host copy of the lattice constants (grid, launch shape); Pdev: the same
+// constants in device memory, read by the kernel
 template <class S, class T>
-hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, hipStream_t stream);
+hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+                         const KParams<T>* Pdev, int mode, int variant, hipStream_t stream);
 
 // equilibrium initialisation from FP64 staging arrays in device memory:
 // phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,

@@ -2,15 +2,14 @@
 // D3Q7 for f, h1, h2.
 //
 // One launch = one time step.  A work-group owns a TX x TY column tile and
-// marches along z over a chunk of LZ planes.  LDS holds a ring of four
+// marches along z over a chunk of planes.  LDS holds a ring of four
 // planes of the deviations of phi and psi = c1 + Keq c2 over the tile and
 // its one-node halo.  Per plane z the group
 //   1. loads f, h1, h2 (21 values) of its own nodes at z+1 -- kept in
 //      registers for the next plane -- and of at most one halo node at z+1
 //      (re-read from L2: neighbouring tiles march the same planes on the
 //      same XCD); the prefetching variants also load g and history of plane
-//      z here, before the barrier (more loads in flight per wave, fewer
-//      waves: it doubles the registers);
+//      z here, before the barrier;
 //   2. puts the moments of plane z+1 in the ring, then one barrier;
 //   3. collides plane z: 19-point stencils from ring planes z-1, z, z+1,
 //      all four sets collided and pushed to x + c_i of the other lattice
@@ -19,6 +18,23 @@
 // reader, so one barrier per plane suffices.  Interior moments are computed
 // once per node; only the halo ring and the first two planes of a chunk are
 // recomputed.
+//
+// Addressing.  Each population set (f, g, h1, h2), the history and the
+// field buffer has a 64-bit base; a value is reached by an Off-typed byte
+// offset plane * stride + node.  With Off = uint32_t (every set below
+// 4 GiB, the usual case) the loads and stores take the scalar-base +
+// 32-bit-vector-offset form and each address costs one VGPR.  Push targets
+// come from per-lane x/y neighbour deltas and per-plane z deltas computed
+// once; bounce-back is a per-lane select, not a branch.
+//
+// Scalar registers.  The loop body reads the lattice constants through a
+// pointer and the plane stride through values that the compiler must treat
+// as new on every use (opaque()), so it rematerialises them where they are
+// needed instead of keeping ~80 loop-invariant scalars live across the
+// z loop, which overflows the scalar file and spills into vector lanes.
+#include <atomic>
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace pflb {
@@ -28,6 +44,48 @@ namespace {
 using LF = D3Q7;
 using LG = D3Q19;
 using Lay = Layout<D3Q7, D3Q19>;
+
+template <class Off>
+struct Geo3 {
+  int nx, ny, nz;
+  int wall_x, wall_y, wall_z;
+  int tiles_x, tiles_xy, ntiles;
+  int nchunks;  // z chunks per column tile
+  Off sS;   // bytes between two population planes
+  Off sT;   // bytes between two history / field planes
+  Off nxy;  // bytes between two z-planes of a population plane (nx ny sizeof(S))
+};
+
+// a uniform value the optimiser may not hoist or merge across uses
+template <class X>
+__device__ inline X opaque(X v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// the lattice constants as seen by the kernel: the constant address space
+// makes every read a scalar load of memory no store of the kernel touches
+template <class T>
+using KPtr = const __attribute__((address_space(4))) KParams<T>*;
+
+template <class T>
+__device__ inline const KParams<T>& params(KPtr<T> p) {
+  return *(const KParams<T>*)opaque(p);
+}
+
+// byte offset of plane k from a set base, formed on the scalar unit at each
+// use (a product the compiler may neither hoist nor fold into a 64-bit
+// vector multiply-add)
+template <class Off>
+__device__ inline Off plane(int k, Off stride) {
+  return k == 0 ? Off(0) : opaque(Off(k) * opaque(stride));
+}
+
+template <class P, class Off>
+__device__ inline P* at(P* base, Off off) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
+}
 
 __device__ inline int fold(int v, int n, int wall) {
   if (v < 0) return wall ? 0 : v + n;
@@ -55,61 +113,90 @@ __device__ inline void halo_pos(int k, int& hx, int& hy) {
   }
 }
 
-template <bool NTS, class S, class T>
-__device__ inline void load_fh(const S* __restrict__ src, long long st, long long node, T (&f)[7],
-                               T (&h1)[7], T (&h2)[7]) {
-  load_set<LF, NTS>(src, st, node, Lay::F0, f);
-  load_set<LF, NTS>(src, st, node, Lay::H10, h1);
-  load_set<LF, NTS>(src, st, node, Lay::H20, h2);
-}
-
 template <class T, int TX, int TY>
 struct Ring {
   T phi[4][TY + 2][TX + 2];
   T psi[4][TY + 2][TX + 2];
 };
 
-template <class S, class T, int TX, int TY, int LZ, bool NTS, bool PREF, int MODE>
-__global__ __launch_bounds__(TX* TY) void step3d_kernel(const S* __restrict__ src,
+// one D3Q7 set of the node at byte offset `node` of a set base
+template <bool NTS, class S, class T, class Off>
+__device__ inline void load7(const S* __restrict__ base, Off sS, Off node, T (&x)[7]) {
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+    x[i] = Codec<S, T>::ld(ld_pop<NTS>(at(base, plane(i, sS) + node)), T(LF::w[i]));
+}
+
+template <class S, class T, int TX, int TY, bool NTS, bool PREF, bool LATE, int WPE, int MODE, class Off>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
-                                                        T* __restrict__ fields, KParams<T> P,
-                                                        int tiles_x, int tiles_xy, int ntiles) {
+                                                        T* __restrict__ fields,
+                                                        KPtr<T> Pg, Geo3<Off> G) {
   constexpr int NT = TX * TY, LX = TX + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
+  constexpr Off BS = sizeof(S);
+  constexpr Off BT = sizeof(T);
   __shared__ Ring<T, TX, TY> R;
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
-  const int per = (ntiles + 7) / 8;
+  const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;
-  const int txy = tile % tiles_xy;
-  const int z0 = (tile / tiles_xy) * LZ;
-  const int x0 = (txy % tiles_x) * TX;
-  const int y0 = (txy / tiles_x) * TY;
-  const int z1 = z0 + LZ < P.nz ? z0 + LZ : P.nz;
+  if (tile >= G.ntiles) return;
+  const int txy = tile % G.tiles_xy;
+  const int zc = tile / G.tiles_xy;  // z chunk: planes [z0, z1), balanced to one plane
+  const int z0 = (int)((long long)zc * G.nz / G.nchunks);
+  const int x0 = (txy % G.tiles_x) * TX;
+  const int y0 = (txy / G.tiles_x) * TY;
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int z1 = (int)((long long)(zc + 1) * G.nz / G.nchunks);
+
+  // set bases (64-bit scalar arithmetic, once)
+  const S* __restrict__ sF = at(src, (size_t)Lay::F0 * G.sS);
+  const S* __restrict__ sG = at(src, (size_t)Lay::G0 * G.sS);
+  const S* __restrict__ sH1 = at(src, (size_t)Lay::H10 * G.sS);
+  const S* __restrict__ sH2 = at(src, (size_t)Lay::H20 * G.sS);
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int x = x0 + tx, y = y0 + ty;
   const bool active = x < nx && y < ny;
   const bool own_slot = x <= nx && y <= ny;  // ragged tile: fill the slot past the end
-  const long long nxy = (long long)nx * ny;
-  const long long st = P.stride;
-  const long long own_col = (long long)fold(y, ny, P.wall[1]) * nx + fold(x, nx, P.wall[0]);
+  const Off own_col = Off(fold(y, ny, G.wall_y) * nx + fold(x, nx, G.wall_x)) * BS;
 
   int hx = 0, hy = 0;
   bool halo = false;
-  long long halo_col = 0;
+  Off halo_col = 0;
   if (tid < NHALO) {
     halo_pos<TX, TY>(tid, hx, hy);
     const int gx = x0 + hx, gy = y0 + hy;
     halo = gx <= nx && gy <= ny;
-    halo_col = (long long)fold(gy, ny, P.wall[1]) * nx + fold(gx, nx, P.wall[0]);
+    halo_col = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
+  }
+
+  // x / y push deltas (bytes, modular) and bounce bits of this lane:
+  // bit 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+
+  const Off rowb = Off(nx) * BS;
+  Off dxm = Off(0) - BS, dxp = BS, dym = Off(0) - rowb, dyp = rowb;
+  int lane_bits = 0;
+  if (x == 0) {
+    if (G.wall_x) lane_bits |= 1;
+    dxm = Off(nx - 1) * BS;
+  }
+  if (x == nx - 1) {
+    if (G.wall_x) lane_bits |= 2;
+    dxp = Off(0) - Off(nx - 1) * BS;
+  }
+  if (y == 0) {
+    if (G.wall_y) lane_bits |= 4;
+    dym = Off(ny - 1) * rowb;
+  }
+  if (y == ny - 1) {
+    if (G.wall_y) lane_bits |= 8;
+    dyp = Off(0) - Off(ny - 1) * rowb;
   }
 
   // moments of plane zp for the own slot and the halo slot of the ring
-  auto put = [&](int zp, const T (&f)[7], const T (&h1)[7], const T (&h2)[7], Node<T>& s,
-                 const T (&hf)[7], const T (&hh1)[7], const T (&hh2)[7]) {
+  auto put = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7], const T (&h2)[7],
+                 Node<T>& s, const T (&hf)[7], const T (&hh1)[7], const T (&hh2)[7]) {
     const int sl = slot_of(zp);
     if (own_slot) {
       moments<LF>(P, f, h1, h2, s);
@@ -123,39 +210,55 @@ __global__ __launch_bounds__(TX* TY) void step3d_kernel(const S* __restrict__ sr
       R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
     }
   };
+  auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
+    load7<NTS>(sF, G.sS, node, f);
+    load7<NTS>(sH1, G.sS, node, h1);
+    load7<NTS>(sH2, G.sS, node, h2);
+  };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
   Node<T> s{};
   {
     // prologue: planes z0-1 and z0
+    const KParams<T>& P = params(Pg);
     T af[7], ah1[7], ah2[7], hf[7], hh1[7], hh2[7];
-    const long long pm = (long long)fold(z0 - 1, nz, P.wall[2]) * nxy;
-    const long long p0 = (long long)z0 * nxy;
-    if (own_slot) load_fh<NTS>(src, st, pm + own_col, af, ah1, ah2);
-    if (halo) load_fh<NTS>(src, st, pm + halo_col, hf, hh1, hh2);
+    const Off pm = Off(fold(z0 - 1, nz, G.wall_z)) * G.nxy;
+    const Off p0 = Off(z0) * G.nxy;
+    if (own_slot) load_fh(pm + own_col, af, ah1, ah2);
+    if (halo) load_fh(pm + halo_col, hf, hh1, hh2);
     Node<T> tmp;
-    put(z0 - 1, af, ah1, ah2, tmp, hf, hh1, hh2);
-    if (own_slot) load_fh<NTS>(src, st, p0 + own_col, f, h1, h2);
-    if (halo) load_fh<NTS>(src, st, p0 + halo_col, hf, hh1, hh2);
-    put(z0, f, h1, h2, s, hf, hh1, hh2);
+    put(P, z0 - 1, af, ah1, ah2, tmp, hf, hh1, hh2);
+    if (own_slot) load_fh(p0 + own_col, f, h1, h2);
+    if (halo) load_fh(p0 + halo_col, hf, hh1, hh2);
+    put(P, z0, f, h1, h2, s, hf, hh1, hh2);
   }
+  // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits: the
+  // same lines were read for the moments one plane earlier) right before
+  // collide_f and collide_h, instead of being held in registers from the
+  // previous plane through the whole g collision.  21 more loads per node
+  // that HBM does not see; only the 8 values of the node state are carried.
 
   for (int z = z0; z < z1; ++z) {
-    const long long node = (long long)z * nxy + (long long)y * nx + x;
-    const long long pn = (long long)fold(z + 1, nz, P.wall[2]) * nxy;
+    const KParams<T>& P = params(Pg);
+    const Off zoff = Off(z) * G.nxy;
+    const Off node = zoff + own_col;                       // bytes, population arrays
+    const Off nodeT = node * Off(sizeof(T) / sizeof(S));   // bytes, history / fields
+    const Off pn = Off(fold(z + 1, nz, G.wall_z)) * G.nxy;
     // ---- 1. global loads of this plane
     T g[19], hs[kHist3D], nf[7], nh1[7], nh2[7], hf[7], hh1[7], hh2[7];
     auto load_g = [&] {
-      load_set<LG, NTS>(src, st, node, Lay::G0, g);
 #pragma unroll
-      for (int k = 0; k < kHist3D; ++k) hs[k] = hist[k * st + node];
+      for (int i = 0; i < 19; ++i)
+        g[i] = Codec<S, T>::ld(ld_pop<NTS>(at(sG, plane(i, G.sS) + node)), T(LG::w[i]));
+#pragma unroll
+      for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane(k, G.sT) + nodeT);
     };
     if (PREF && active) load_g();
-    if (own_slot) load_fh<NTS>(src, st, pn + own_col, nf, nh1, nh2);
-    if (halo) load_fh<NTS>(src, st, pn + halo_col, hf, hh1, hh2);
+    if (own_slot) load_fh(pn + own_col, nf, nh1, nh2);
+    if (halo) load_fh(pn + halo_col, hf, hh1, hh2);
     // ---- 2. moments of plane z+1 into the ring
     Node<T> ns{};
-    put(z + 1, nf, nh1, nh2, ns, hf, hh1, hh2);
+    put(P, z + 1, nf, nh1, nh2, ns, hf, hh1, hh2);
     __syncthreads();
     // ---- 3. collide plane z
     if (active) {
@@ -186,15 +289,16 @@ __global__ __launch_bounds__(TX* TY) void step3d_kernel(const S* __restrict__ sr
       Flow<T> fl;
       flow_macros<LG>(P, g, s, gphi, lap, fl);
       if (MODE == kModeMacros) {
-        fields[kFieldPhi * st + node] = s.phi;
-        fields[kFieldP * st + node] = fl.p;
-        fields[kFieldUx * st + node] = fl.u[0];
-        fields[kFieldUy * st + node] = fl.u[1];
-        fields[kFieldUz * st + node] = fl.u[2];
-        fields[kFieldC1 * st + node] = s.c1;
-        fields[kFieldC2 * st + node] = s.c2;
-        fields[kFieldMu * st + node] = fl.mu;
-        fields[kFieldPsi * st + node] = s.c1 + P.Keq * s.c2;
+        auto put_field = [&](int k, T v) { *at(fields, plane(k, G.sT) + nodeT) = v; };
+        put_field(kFieldPhi, s.phi);
+        put_field(kFieldP, fl.p);
+        put_field(kFieldUx, fl.u[0]);
+        put_field(kFieldUy, fl.u[1]);
+        put_field(kFieldUz, fl.u[2]);
+        put_field(kFieldC1, s.c1);
+        put_field(kFieldC2, s.c2);
+        put_field(kFieldMu, fl.mu);
+        put_field(kFieldPsi, s.c1 + P.Keq * s.c2);
       } else {
         // backward-difference time derivatives against the history (R1)
         T dJphi[3], dJ1[3], dJ2[3];
@@ -203,111 +307,206 @@ __global__ __launch_bounds__(TX* TY) void step3d_kernel(const S* __restrict__ sr
           dJphi[a] = s.phi * fl.u[a] - hs[3] * hs[a];
           dJ1[a] = s.c1 * fl.u[a] - hs[4] * hs[a];
           dJ2[a] = s.c2 * fl.u[a] - hs[5] * hs[a];
-          hist[a * st + node] = fl.u[a];
         }
-        hist[3 * st + node] = s.phi;
-        hist[4 * st + node] = s.c1;
-        hist[5 * st + node] = s.c2;
+#pragma unroll
+        for (int k = 0; k < kHist3D; ++k) {
+          const T v = k < 3 ? fl.u[k] : (k == 3 ? s.phi : (k == 4 ? s.c1 : s.c2));
+          *at(hist, plane(k, G.sT) + nodeT) = v;
+        }
 
-        // push streaming with periodic wrap or half-way bounce-back; each
-        // post-collision value is stored as soon as it is formed
-        auto dest = [&](int cx, int cy, int cz, bool& bounce) -> long long {
-          int xt = x + cx, yt = y + cy, zt = z + cz;
-          bounce = false;
-          if (xt < 0 || xt >= nx) {
-            if (P.wall[0]) bounce = true;
-            else xt = xt < 0 ? xt + nx : xt - nx;
-          }
-          if (yt < 0 || yt >= ny) {
-            if (P.wall[1]) bounce = true;
-            else yt = yt < 0 ? yt + ny : yt - ny;
-          }
-          if (zt < 0 || zt >= nz) {
-            if (P.wall[2]) bounce = true;
-            else zt = zt < 0 ? zt + nz : zt - nz;
-          }
-          return bounce ? node : (long long)zt * nxy + (long long)yt * nx + xt;
+        // z push deltas and bounce bits of this plane (uniform)
+        Off dzm = Off(0) - G.nxy, dzp = G.nxy;
+        int bits = lane_bits;
+        if (z == 0) {
+          if (G.wall_z) bits |= 16;
+          dzm = Off(nz - 1) * G.nxy;
+        }
+        if (z == nz - 1) {
+          if (G.wall_z) bits |= 32;
+          dzp = Off(0) - Off(nz - 1) * G.nxy;
+        }
+        // byte offset of the push target of direction i (plane i of its set),
+        // or of the bounce-back target (plane opp(i), this node)
+        auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
+          const int m = (cx < 0 ? 1 : 0) | (cx > 0 ? 2 : 0) | (cy < 0 ? 4 : 0) |
+                        (cy > 0 ? 8 : 0) | (cz < 0 ? 16 : 0) | (cz > 0 ? 32 : 0);
+          Off t = node;
+          if (cx) t += cx < 0 ? dxm : dxp;
+          if (cy) t += cy < 0 ? dym : dyp;
+          if (cz) t += cz < 0 ? dzm : dzp;
+          return (bits & m) ? plane(o, G.sS) + node : plane(i, G.sS) + t;
         };
-        collide<LF, LG>(
-            P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
-            [&](int i, T v) {
-              bool b;
-              const long long t = dest(LF::cx[i], LF::cy[i], LF::cz[i], b);
-              store_one<LF, NTS>(dst, (Lay::F0 + (b ? LF::opp[i] : i)) * st + t, i, v);
-            },
-            [&](int i, T v) {
-              bool b;
-              const long long t = dest(LG::cx[i], LG::cy[i], LG::cz[i], b);
-              store_one<LG, NTS>(dst, (Lay::G0 + (b ? LG::opp[i] : i)) * st + t, i, v);
-            },
-            [&](int i, T a, T c) {
-              bool b;
-              const long long t = dest(LF::cx[i], LF::cy[i], LF::cz[i], b);
-              const int j = b ? LF::opp[i] : i;
-              store_one<LF, NTS>(dst, (Lay::H10 + j) * st + t, i, a);
-              store_one<LF, NTS>(dst, (Lay::H20 + j) * st + t, i, c);
-            });
+        S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
+        S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
+        S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
+        S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
+        T n[3];
+        normal(P, gphi, n);
+        collide_g<LG>(P, g, gphi, fl, [&](int i, T v) {
+          const Off t = target(i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
+          st_pop<NTS>(at(dG, t), Codec<S, T>::st(v, T(1.0 / LG::w[i])));
+        });
+        if (LATE) load7<NTS>(sF, G.sS, node, f);
+        collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
+          const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          st_pop<NTS>(at(dF, t), Codec<S, T>::st(v, T(1.0 / LF::w[i])));
+        });
+        if (LATE) {
+          load7<NTS>(sH1, G.sS, node, h1);
+          load7<NTS>(sH2, G.sS, node, h2);
+        }
+        collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
+          const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
+          st_pop<NTS>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
+        });
       }
     }
+    if (!LATE) {
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-      f[i] = nf[i];
-      h1[i] = nh1[i];
-      h2[i] = nh2[i];
+      for (int i = 0; i < 7; ++i) {
+        f[i] = nf[i];
+        h1[i] = nh1[i];
+        h2[i] = nh2[i];
+      }
     }
     s = ns;
   }
 }
 
-template <class S, class T, int TX, int TY, int LZ, bool NTS, bool PREF, int MODE>
+// true when every set, the history and the field buffer span < 4 GiB, so
+// that 32-bit byte offsets reach every value
+bool fits_u32(long long stride, size_t sS, size_t sT) {
+  const unsigned long long lim = 1ull << 32;
+  return (unsigned long long)LG::Q * stride * sS < lim &&
+         (unsigned long long)kNumFields * stride * sT < lim;
+}
+
+// Work-groups the device holds at once for a kernel (groups per CU x CUs),
+// from the compiled resource usage; cached per kernel and device.
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+    n = 256;
+  cache[dev].store(n, std::memory_order_relaxed);
+  return n;
+}
+
+// Number of z chunks per column tile.  Every tile is one work-group, and a
+// launch runs in rounds of `slots` resident groups; a last round that is
+// only partly filled leaves CUs idle for a whole chunk.  Pick the chunk
+// count whose tiles fill their rounds best, weighted by the two extra
+// planes of moments each chunk loads at its start.
+int choose_chunks(int tiles_xy, int nz, int slots) {
+  int best = 1;
+  double best_eff = -1.0;
+  const int max_chunks = nz / 8 > 1 ? nz / 8 : 1;
+  for (int c = 1; c <= max_chunks; ++c) {
+    const double rounds = (double)tiles_xy * c / slots;
+    const double fill = rounds / std::ceil(rounds);
+    const double len = (double)nz / c;
+    const double eff = fill * len / (len + 2.0);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = c;
+    }
+  }
+  return best;
+}
+
+template <class S, class T, int TX, int TY, bool NTS, bool PREF, bool LATE, int WPE, int MODE,
+          class Off>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
-                          hipStream_t stream) {
-  const int tiles_x = (P.nx + TX - 1) / TX;
+                          const KParams<T>* Pdev, hipStream_t stream) {
+  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NTS, PREF, LATE, WPE, MODE, Off>;
+  static std::atomic<int> per_cu{0};
+  int groups = per_cu.load(std::memory_order_relaxed);
+  if (groups < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&groups, reinterpret_cast<const void*>(kernel),
+                                                     TX * TY, 0) != hipSuccess ||
+        groups < 1)
+      groups = 1;
+    per_cu.store(groups, std::memory_order_relaxed);
+  }
+  Geo3<Off> G;
+  G.nx = P.nx;
+  G.ny = P.ny;
+  G.nz = P.nz;
+  G.wall_x = P.wall[0];
+  G.wall_y = P.wall[1];
+  G.wall_z = P.wall[2];
+  G.tiles_x = (P.nx + TX - 1) / TX;
   const int tiles_y = (P.ny + TY - 1) / TY;
-  const int tiles_z = (P.nz + LZ - 1) / LZ;
-  const int tiles_xy = tiles_x * tiles_y;
-  const int ntiles = tiles_xy * tiles_z;
-  const int nblocks = ((ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((step3d_kernel<S, T, TX, TY, LZ, NTS, PREF, MODE>), dim3(nblocks), dim3(TX * TY),
-                     0, stream, src, dst, hist, fields, P, tiles_x, tiles_xy, ntiles);
+  G.tiles_xy = G.tiles_x * tiles_y;
+  G.nchunks = choose_chunks(G.tiles_xy, P.nz, groups * device_cus());
+  G.ntiles = G.tiles_xy * G.nchunks;
+  G.sS = Off(P.stride * (long long)sizeof(S));
+  G.sT = Off(P.stride * (long long)sizeof(T));
+  G.nxy = Off((long long)P.nx * P.ny * (long long)sizeof(S));
+  const int nblocks = ((G.ntiles + 7) / 8) * 8;
+  hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(TX * TY), 0, stream, src, dst, hist, fields,
+                     (KPtr<T>)Pdev, G);
   return hipGetLastError();
 }
 
 }  // namespace
 
 const char* step3d_variant_name(int v) {
-  static const char* names[kVariants3D] = {"32x8",    "64x4",    "32x4",         "32x8 nt",
-                                          "64x4 nt", "32x4 nt", "32x8 prefetch", "32x8 prefetch nt"};
+  static const char* names[kVariants3D] = {"64x4 late",   "64x4 late w4",       "32x8 late",
+                                          "64x4",        "16x16 late",         "64x4 late prefetch",
+                                          "64x4 late nt", "32x4 late"};
   return v >= 0 && v < kVariants3D ? names[v] : "?";
 }
 
 template <class S, class T>
-hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, hipStream_t stream) {
+hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+                         const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
   constexpr int M = kModeStep;
-  if (mode == kModeMacros)
-    return launch_variant<S, T, 32, 8, 64, false, false, kModeMacros>(src, dst, hist, fields, P,
-                                                                      stream);
-  switch (variant) {
-    case 1: return launch_variant<S, T, 64, 4, 64, false, false, M>(src, dst, hist, fields, P, stream);
-    case 2: return launch_variant<S, T, 32, 4, 64, false, false, M>(src, dst, hist, fields, P, stream);
-    case 3: return launch_variant<S, T, 32, 8, 64, true, false, M>(src, dst, hist, fields, P, stream);
-    case 4: return launch_variant<S, T, 64, 4, 64, true, false, M>(src, dst, hist, fields, P, stream);
-    case 5: return launch_variant<S, T, 32, 4, 64, true, false, M>(src, dst, hist, fields, P, stream);
-    case 6: return launch_variant<S, T, 32, 8, 64, false, true, M>(src, dst, hist, fields, P, stream);
-    case 7: return launch_variant<S, T, 32, 8, 64, true, true, M>(src, dst, hist, fields, P, stream);
-    default: return launch_variant<S, T, 32, 8, 64, false, false, M>(src, dst, hist, fields, P, stream);
+  using U = uint32_t;
+  if (!fits_u32(P.stride, sizeof(S), sizeof(T))) {
+    // very large grids: 64-bit offsets, one tile shape
+    if (mode == kModeMacros)
+      return launch_variant<S, T, 64, 4, false, false, false, 1, kModeMacros, uint64_t>(
+          src, dst, hist, fields, P, Pdev, stream);
+    return launch_variant<S, T, 64, 4, false, false, true, 1, M, uint64_t>(
+        src, dst, hist, fields, P, Pdev, stream);
   }
+  if (mode == kModeMacros)
+    return launch_variant<S, T, 64, 4, false, false, false, 1, kModeMacros, U>(
+        src, dst, hist, fields, P, Pdev, stream);
+#define PFLB_V3(TX, TY, NTS, PREF, LATE, WPE) \
+  launch_variant<S, T, TX, TY, NTS, PREF, LATE, WPE, M, U>(src, dst, hist, fields, P, Pdev, \
+                                                               stream)
+  // WPE: minimum waves per SIMD the register allocator must allow (1: free)
+  switch (variant) {
+    case 1: return PFLB_V3(64, 4, false, false, true, 4);
+    case 2: return PFLB_V3(32, 8, false, false, true, 1);
+    case 3: return PFLB_V3(64, 4, false, false, false, 1);
+    case 4: return PFLB_V3(16, 16, false, false, true, 1);
+    case 5: return PFLB_V3(64, 4, false, true, true, 1);
+    case 6: return PFLB_V3(64, 4, true, false, true, 1);
+    case 7: return PFLB_V3(32, 4, false, false, true, 1);
+    default: return PFLB_V3(64, 4, false, false, true, 1);
+  }
+#undef PFLB_V3
 }
 
 template hipError_t launch_step3d<double, double>(const double*, double*, double*, double*,
-                                                  const KParams<double>&, int, int, hipStream_t);
+                                                  const KParams<double>&, const KParams<double>*,
+                                                  int, int, hipStream_t);
 template hipError_t launch_step3d<float, float>(const float*, float*, float*, float*,
-                                                const KParams<float>&, int, int, hipStream_t);
+                                                const KParams<float>&, const KParams<float>*, int,
+                                                int, hipStream_t);
 template hipError_t launch_step3d<__half, float>(const __half*, __half*, float*, float*,
-                                                 const KParams<float>&, int, int, hipStream_t);
+                                                 const KParams<float>&, const KParams<float>*, int,
+                                                 int, hipStream_t);
 template hipError_t launch_step3d<__hip_bfloat16, float>(const __hip_bfloat16*, __hip_bfloat16*,
-                                                         float*, float*, const KParams<float>&, int,
-                                                         int, hipStream_t);
+                                                         float*, float*, const KParams<float>&,
+                                                         const KParams<float>*, int, int,
+                                                         hipStream_t);
 
 }  // namespace pflb

@@ -79,6 +79,7 @@ def pair_workload(cplb, w, steps, precision=None):
     p = dict(w["params"])
     if precision:
         p["precision"] = precision
+        p["ref_f"] = W.phase_reference(precision)
     g = cplb.Lattice(p)
     g.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
     o = ref.Oracle(p)

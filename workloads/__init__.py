@@ -17,7 +17,16 @@ Parameter dictionaries use the keys
 plus, for the GPU library only, ``precision`` ('f64' | 'f32' | 'f32_s16f' |
 'f32_s16b') and the reference state of its stored population deviations,
 ``ref_f`` (phi_ref), ``ref_g`` (always 0), ``ref_h1``, ``ref_h2`` (c1_ref,
-c2_ref): the values that fill most of the domain.
+c2_ref).  ``ref_h1`` / ``ref_h2`` are the concentrations that fill most of
+the domain.  ``ref_f`` sets where the stored phase populations resolve phi
+best.  Both tails matter: the scalar sources carry phi c2 in the core of
+fluid 2 (phi -> 0) and the buoyancy (rho - rho_ref) g carries 1 - phi in
+the bulk of fluid 1 (phi -> 1); a reference at either end leaves the other
+tail at the absolute FP32 resolution of a deviation of size 1 (~6e-8).
+FP32 storage therefore takes ref_f = 1/2 (both tails at ~3e-8); 16-bit
+storage takes the bulk phase (ref_f = 1), whose deviations are then exactly
+zero -- a deviation of size 1/2 would leave FP16's ~5e-4 resolution in the
+bulk.  See ``phase_reference``.
 
 Every field array is a numpy float64 array of shape (ny, nx) in 2-D or
 (nz, ny, nx) in 3-D (x fastest in memory).
@@ -34,6 +43,13 @@ DEFAULTS = dict(
     D1=0.1, D2=0.1, Keq=1.0, A=0.1, g=(0.0, 0.0, 0.0), rho_ref=0.0, n_eps=1e-3,
     precision="f64", ref_f=0.0, ref_g=0.0, ref_h1=0.0, ref_h2=0.0,
 )
+
+
+def phase_reference(precision: str, bulk_phi: float = 1.0) -> float:
+    """Reference phi of the stored phase populations for a storage precision
+    (see the module docstring): 1/2 for FP64 / FP32, the bulk phase for
+    16-bit storage."""
+    return bulk_phi if precision.startswith("f32_s16") else 0.5
 
 
 def params(**kw) -> dict:
@@ -124,7 +140,7 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32"):
     p = params(nx=nx, ny=ny, nz=1, lattice="d2q9", visc_law="exp", periodic=(1, 0, 1),
                rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
                D1=1e-3, D2=0.1, Keq=0.2, A=0.1, g=(0.0, -gmag, 0.0), rho_ref=rho1,
-               precision=precision, ref_f=1.0, ref_h1=0.0, ref_h2=0.0)
+               precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0)
     l = sdf_sphere(p, (nx / 2.0, 3.0 * nx / 8.0), R, inside_positive=False)
     return dict(name=f"rising_bubble_{nx}x{ny}_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=20000)
@@ -142,7 +158,7 @@ def rising_droplet_3d(n=256, precision="f32"):
     p = params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", visc_law="exp", periodic=(1, 1, 0),
                rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
                D1=0.05, D2=0.01, Keq=10.0, A=0.1, g=(0.0, 0.0, -gmag), rho_ref=rho1,
-               precision=precision, ref_f=1.0, ref_h1=0.0, ref_h2=0.0)
+               precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0)
     l = sdf_sphere(p, (n / 2.0, n / 2.0, 3.0 * R), R, inside_positive=False)
     return dict(name=f"rising_droplet_{n}c_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=5000)
