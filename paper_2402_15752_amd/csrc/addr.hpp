@@ -1,0 +1,135 @@
+// Addressing helpers shared by the step kernels.
+//
+// Every population set (f, g, h1, h2), the history and the field buffer is
+// reached from a 64-bit set base held in scalar registers plus an Off-typed
+// byte offset plane * stride + node.  With Off = uint32_t (each set below
+// 4 GiB) a load or store takes the scalar-base + 32-bit-vector-offset form
+// and an address costs one VGPR; Off = uint64_t serves larger sets.
+#pragma once
+
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace pflb {
+
+// a uniform value the optimiser may not hoist or merge across uses
+template <class X>
+__device__ inline X opaque(X v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// the lattice constants as seen by a kernel: the constant address space
+// makes every read a scalar load of memory no store of the kernel touches
+template <class T>
+using KPtr = const __attribute__((address_space(4))) KParams<T>*;
+
+template <class T>
+__device__ inline const KParams<T>& params(KPtr<T> p) {
+  return *(const KParams<T>*)opaque(p);
+}
+
+// byte offset of plane k from a set base.  PIN (for kernels with a loop):
+// formed on the scalar unit at each use, a product the compiler may neither
+// hoist out of the loop -- ~40 loop-invariant offsets overflow the scalar
+// file -- nor fold into a 64-bit vector multiply-add.  Without a loop the
+// plain product is cheaper (no scheduling barrier per use).
+template <bool PIN, class Off>
+__device__ inline Off plane(int k, Off stride) {
+  if constexpr (PIN)
+    return k == 0 ? Off(0) : opaque(Off(k) * opaque(stride));
+  else
+    return Off(k) * stride;
+}
+
+template <class P, class Off>
+__device__ inline P* at(P* base, Off off) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
+}
+
+// map a (possibly out of range) coordinate onto the node whose moments the
+// stencil reads there: periodic wrap, or the mirror ghost at a wall
+__device__ inline int fold(int v, int n, int wall) {
+  if (v < 0) return wall ? 0 : v + n;
+  if (v >= n) return wall ? n - 1 : v - n;
+  return v;
+}
+
+// halo ring of a TX x TY tile: top row, bottom row, left column, right column
+template <int TX, int TY>
+__device__ inline void halo_pos(int k, int& hx, int& hy) {
+  constexpr int LX = TX + 2;
+  if (k < LX) {
+    hx = k - 1;
+    hy = -1;
+  } else if (k < 2 * LX) {
+    hx = k - LX - 1;
+    hy = TY;
+  } else if (k < 2 * LX + TY) {
+    hx = -1;
+    hy = k - 2 * LX;
+  } else {
+    hx = TX;
+    hy = k - 2 * LX - TY;
+  }
+}
+
+// one set of Q populations of the node at byte offset `node` of a set base
+template <class L, bool NTS, bool PIN, class S, class T, class Off>
+__device__ inline void load_q(const S* __restrict__ base, Off sS, Off node, T (&x)[L::Q]) {
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    x[i] = Codec<S, T>::ld(ld_pop<NTS>(at(base, plane<PIN>(i, sS) + node)), T(L::w[i]));
+}
+
+// Push deltas of one lane (bytes, modular arithmetic in Off) and its
+// bounce-back bits: bit 0 x-, 1 x+, 2 y-, 3 y+ (4 z-, 5 z+ are per plane).
+// A periodic axis wraps to the far side; a walled axis sets the bit and the
+// link bounces back into the opposite slot of the own node.
+template <class Off>
+struct PushXY {
+  Off dxm, dxp, dym, dyp;
+  int bits;
+  __device__ PushXY(int x, int y, int nx, int ny, int wall_x, int wall_y, Off bs) {
+    const Off row = Off(nx) * bs;
+    dxm = Off(0) - bs;
+    dxp = bs;
+    dym = Off(0) - row;
+    dyp = row;
+    bits = 0;
+    if (x == 0) {
+      if (wall_x) bits |= 1;
+      dxm = Off(nx - 1) * bs;
+    }
+    if (x == nx - 1) {
+      if (wall_x) bits |= 2;
+      dxp = Off(0) - Off(nx - 1) * bs;
+    }
+    if (y == 0) {
+      if (wall_y) bits |= 4;
+      dym = Off(ny - 1) * row;
+    }
+    if (y == ny - 1) {
+      if (wall_y) bits |= 8;
+      dyp = Off(0) - Off(ny - 1) * row;
+    }
+  }
+};
+
+// bounce-back mask of direction (cx, cy, cz)
+__device__ constexpr int link_mask(int cx, int cy, int cz) {
+  return (cx < 0 ? 1 : 0) | (cx > 0 ? 2 : 0) | (cy < 0 ? 4 : 0) | (cy > 0 ? 8 : 0) |
+         (cz < 0 ? 16 : 0) | (cz > 0 ? 32 : 0);
+}
+
+// true when every population set (at most qset planes), the history and the
+// field buffer span < 4 GiB, so 32-bit byte offsets reach every value
+inline bool fits_u32(int qset, long long stride, size_t s_pop, size_t s_cmp, int nfields) {
+  const unsigned long long lim = 1ull << 32;
+  return (unsigned long long)qset * stride * s_pop < lim &&
+         (unsigned long long)nfields * stride * s_cmp < lim;
+}
+
+}  // namespace pflb

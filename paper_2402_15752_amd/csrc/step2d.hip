@@ -17,6 +17,7 @@
 //
 // Variants (tile shape, non-temporal population traffic) are template
 // parameters; the host picks one per lattice (cplb_tune times them all).
+#include "addr.hpp"
 #include "kernels.hpp"
 
 namespace pflb {
@@ -26,93 +27,79 @@ namespace {
 using L = D2Q9;
 using Lay = Layout<D2Q9, D2Q9>;
 
-// map a (possibly out of range) coordinate onto the node whose moments the
-// stencil reads there: periodic wrap, or the mirror ghost at a wall
-__device__ inline int fold(int v, int n, int wall) {
-  if (v < 0) return wall ? 0 : v + n;
-  if (v >= n) return wall ? n - 1 : v - n;
-  return v;
-}
+template <class Off>
+struct Geo2 {
+  int nx, ny;
+  int wall_x, wall_y;
+  int tiles_x, ntiles;
+  Off sS;  // bytes between two population planes
+  Off sT;  // bytes between two history / field planes
+};
 
-// halo ring of a TX x TY tile: top row, bottom row, left column, right column
-template <int TX, int TY>
-__device__ inline void halo_pos(int k, int& hx, int& hy) {
-  constexpr int LX = TX + 2;
-  if (k < LX) {
-    hx = k - 1;
-    hy = -1;
-  } else if (k < 2 * LX) {
-    hx = k - LX - 1;
-    hy = TY;
-  } else if (k < 2 * LX + TY) {
-    hx = -1;
-    hy = k - 2 * LX;
-  } else {
-    hx = TX;
-    hy = k - 2 * LX - TY;
-  }
-}
-
-template <bool NTS, class S, class T>
-__device__ inline void load_fh(const S* __restrict__ src, long long st, long long node, T (&f)[9],
-                               T (&h1)[9], T (&h2)[9]) {
-  load_set<L, NTS>(src, st, node, Lay::F0, f);
-  load_set<L, NTS>(src, st, node, Lay::H10, h1);
-  load_set<L, NTS>(src, st, node, Lay::H20, h2);
-}
-
-template <class S, class T, int TX, int TY, bool NTS, int MODE>
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
 __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
                                                         T* __restrict__ fields, KParams<T> P,
-                                                        int tiles_x, int ntiles) {
+                                                        Geo2<Off> G) {
   constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
+  constexpr Off BS = sizeof(S);
   __shared__ T sphi[LY][LX];
   __shared__ T spsi[LY][LX];
 
   // XCD-aware tile order: work-groups are dealt round-robin to the 8 XCDs
   // (group b runs on XCD b % 8), so XCD k gets the contiguous tile run
   // [k*per, (k+1)*per).  Groups past the last tile exit before any barrier.
-  const int per = (ntiles + 7) / 8;
+  const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;
-  const int x0 = (tile % tiles_x) * TX;
-  const int y0 = (tile / tiles_x) * TY;
+  if (tile >= G.ntiles) return;
+  const int x0 = (tile % G.tiles_x) * TX;
+  const int y0 = (tile / G.tiles_x) * TY;
+
+  const S* __restrict__ sF = at(src, (size_t)Lay::F0 * G.sS);
+  const S* __restrict__ sG = at(src, (size_t)Lay::G0 * G.sS);
+  const S* __restrict__ sH1 = at(src, (size_t)Lay::H10 * G.sS);
+  const S* __restrict__ sH2 = at(src, (size_t)Lay::H20 * G.sS);
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  const int nx = P.nx, ny = P.ny;
-  const long long st = P.stride;
+  const int nx = G.nx, ny = G.ny;
   const int x = x0 + tx, y = y0 + ty;
   const bool active = x < nx && y < ny;
   // a ragged tile: the slot one past the last node is read by that node's
   // stencil, so its thread fills it with the wrapped or mirrored node
   const bool own_slot = x <= nx && y <= ny;
-  const long long node = (long long)y * nx + x;
-  const long long own_src =
-      active ? node : (long long)fold(y, ny, P.wall[1]) * nx + fold(x, nx, P.wall[0]);
+  const Off node = Off(fold(y, ny, G.wall_y) * nx + fold(x, nx, G.wall_x)) * BS;
+  const Off nodeT = node * Off(sizeof(T) / sizeof(S));  // bytes, history / fields
 
   int hx = 0, hy = 0;
   bool halo = false;
-  long long halo_src = 0;
+  Off halo_node = 0;
   if (tid < NHALO) {
     halo_pos<TX, TY>(tid, hx, hy);
     const int gx = x0 + hx, gy = y0 + hy;
     halo = gx <= nx && gy <= ny;  // beyond a ragged tile no node reads it
-    halo_src = (long long)fold(gy, ny, P.wall[1]) * nx + fold(gx, nx, P.wall[0]);
+    halo_node = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
   }
 
   // ---- 1. all global loads first
   T f[9], h1[9], h2[9], g[9], hf[9], hh1[9], hh2[9];
   T hs[kHist2D];
-  if (own_slot) load_fh<NTS>(src, st, own_src, f, h1, h2);
-  if (active) {
-    load_set<L, NTS>(src, st, node, Lay::G0, g);
-#pragma unroll
-    for (int k = 0; k < kHist2D; ++k) hs[k] = hist[k * st + node];
+  if (own_slot) {
+    load_q<L, NTS, false>(sF, G.sS, node, f);
+    load_q<L, NTS, false>(sH1, G.sS, node, h1);
+    load_q<L, NTS, false>(sH2, G.sS, node, h2);
   }
-  if (halo) load_fh<NTS>(src, st, halo_src, hf, hh1, hh2);
+  if (active) {
+    load_q<L, NTS, false>(sG, G.sS, node, g);
+#pragma unroll
+    for (int k = 0; k < kHist2D; ++k) hs[k] = *at(hist, plane<false>(k, G.sT) + nodeT);
+  }
+  if (halo) {
+    load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
+    load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
+    load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
+  }
 
   // ---- 2. moments to LDS (deviations: the stencils only take differences
   //         and zero-sum weighted sums)
@@ -138,10 +125,14 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
     const T a = sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
     const T b = spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
     const T wc = T(L::w[i] / L::cs2);
-    gphi[0] += wc * T(L::cx[i]) * a;
-    gphi[1] += wc * T(L::cy[i]) * a;
-    gpsi[0] += wc * T(L::cx[i]) * b;
-    gpsi[1] += wc * T(L::cy[i]) * b;
+    if (L::cx[i]) {
+      gphi[0] += wc * T(L::cx[i]) * a;
+      gpsi[0] += wc * T(L::cx[i]) * b;
+    }
+    if (L::cy[i]) {
+      gphi[1] += wc * T(L::cy[i]) * a;
+      gpsi[1] += wc * T(L::cy[i]) * b;
+    }
     lap += T(2) * wc * (a - s.dphi);
   }
 
@@ -149,15 +140,16 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
   flow_macros<L>(P, g, s, gphi, lap, fl);
 
   if (MODE == kModeMacros) {
-    fields[kFieldPhi * st + node] = s.phi;
-    fields[kFieldP * st + node] = fl.p;
-    fields[kFieldUx * st + node] = fl.u[0];
-    fields[kFieldUy * st + node] = fl.u[1];
-    fields[kFieldUz * st + node] = T(0);
-    fields[kFieldC1 * st + node] = s.c1;
-    fields[kFieldC2 * st + node] = s.c2;
-    fields[kFieldMu * st + node] = fl.mu;
-    fields[kFieldPsi * st + node] = s.c1 + P.Keq * s.c2;
+    auto put_field = [&](int k, T v) { *at(fields, plane<false>(k, G.sT) + nodeT) = v; };
+    put_field(kFieldPhi, s.phi);
+    put_field(kFieldP, fl.p);
+    put_field(kFieldUx, fl.u[0]);
+    put_field(kFieldUy, fl.u[1]);
+    put_field(kFieldUz, T(0));
+    put_field(kFieldC1, s.c1);
+    put_field(kFieldC2, s.c2);
+    put_field(kFieldMu, fl.mu);
+    put_field(kFieldPsi, s.c1 + P.Keq * s.c2);
     return;
   }
 
@@ -165,58 +157,54 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
   const T dJphi[3] = {s.phi * fl.u[0] - hs[2] * hs[0], s.phi * fl.u[1] - hs[2] * hs[1], T(0)};
   const T dJ1[3] = {s.c1 * fl.u[0] - hs[3] * hs[0], s.c1 * fl.u[1] - hs[3] * hs[1], T(0)};
   const T dJ2[3] = {s.c2 * fl.u[0] - hs[4] * hs[0], s.c2 * fl.u[1] - hs[4] * hs[1], T(0)};
-  hist[0 * st + node] = fl.u[0];
-  hist[1 * st + node] = fl.u[1];
-  hist[2 * st + node] = s.phi;
-  hist[3 * st + node] = s.c1;
-  hist[4 * st + node] = s.c2;
+#pragma unroll
+  for (int k = 0; k < kHist2D; ++k) {
+    const T v = k < 2 ? fl.u[k] : (k == 2 ? s.phi : (k == 3 ? s.c1 : s.c2));
+    *at(hist, plane<false>(k, G.sT) + nodeT) = v;
+  }
 
   // push streaming: X_i(x + c_i) <- X_i*(x), or half-way bounce-back into
   // the opposite slot of the own node when the link crosses a wall; each
   // post-collision value is stored as soon as it is formed
-  auto dest = [&](int i, int& j) -> long long {
-    int xt = x + L::cx[i], yt = y + L::cy[i];
-    bool bounce = false;
-    if (xt < 0 || xt >= nx) {
-      if (P.wall[0]) bounce = true;
-      else xt = xt < 0 ? xt + nx : xt - nx;
-    }
-    if (yt < 0 || yt >= ny) {
-      if (P.wall[1]) bounce = true;
-      else yt = yt < 0 ? yt + ny : yt - ny;
-    }
-    j = bounce ? L::opp[i] : i;
-    return bounce ? node : (long long)yt * nx + xt;
+  const PushXY<Off> push(x, y, nx, ny, G.wall_x, G.wall_y, BS);
+  auto target = [&](int i) -> Off {
+    const int cx = L::cx[i], cy = L::cy[i];
+    Off t = node;
+    if (cx) t += cx < 0 ? push.dxm : push.dxp;
+    if (cy) t += cy < 0 ? push.dym : push.dyp;
+    return (push.bits & link_mask(cx, cy, 0)) ? plane<false>(L::opp[i], G.sS) + node
+                                              : plane<false>(i, G.sS) + t;
   };
+  S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
+  S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
+  S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
+  S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
   collide<L, L>(
       P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
-      [&](int i, T v) {
-        int j;
-        const long long t = dest(i, j);
-        store_one<L, NTS>(dst, (Lay::F0 + j) * st + t, i, v);
-      },
-      [&](int i, T v) {
-        int j;
-        const long long t = dest(i, j);
-        store_one<L, NTS>(dst, (Lay::G0 + j) * st + t, i, v);
-      },
+      [&](int i, T v) { st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
+      [&](int i, T v) { st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
       [&](int i, T a, T b) {
-        int j;
-        const long long t = dest(i, j);
-        store_one<L, NTS>(dst, (Lay::H10 + j) * st + t, i, a);
-        store_one<L, NTS>(dst, (Lay::H20 + j) * st + t, i, b);
+        const Off t = target(i);
+        st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
+        st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
       });
 }
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE>
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                           hipStream_t stream) {
-  const int tiles_x = (P.nx + TX - 1) / TX;
-  const int tiles_y = (P.ny + TY - 1) / TY;
-  const int ntiles = tiles_x * tiles_y;
-  const int nblocks = ((ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE>), dim3(nblocks), dim3(TX * TY), 0,
-                     stream, src, dst, hist, fields, P, tiles_x, ntiles);
+  Geo2<Off> G;
+  G.nx = P.nx;
+  G.ny = P.ny;
+  G.wall_x = P.wall[0];
+  G.wall_y = P.wall[1];
+  G.tiles_x = (P.nx + TX - 1) / TX;
+  G.ntiles = G.tiles_x * ((P.ny + TY - 1) / TY);
+  G.sS = Off(P.stride * (long long)sizeof(S));
+  G.sT = Off(P.stride * (long long)sizeof(T));
+  const int nblocks = ((G.ntiles + 7) / 8) * 8;
+  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off>), dim3(nblocks), dim3(TX * TY),
+                     0, stream, src, dst, hist, fields, P, G);
   return hipGetLastError();
 }
 
@@ -232,17 +220,26 @@ const char* step2d_variant_name(int v) {
 template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
                          int variant, hipStream_t stream) {
+  constexpr int M = kModeStep;
+  using U = uint32_t;
+  if (!fits_u32(L::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
+    // very large grids: 64-bit offsets, one tile shape
+    if (mode == kModeMacros)
+      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t>(src, dst, hist, fields, P,
+                                                                      stream);
+    return launch_variant<S, T, 128, 4, false, M, uint64_t>(src, dst, hist, fields, P, stream);
+  }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, kModeMacros>(src, dst, hist, fields, P, stream);
+    return launch_variant<S, T, 64, 4, false, kModeMacros, U>(src, dst, hist, fields, P, stream);
   switch (variant) {
-    case 1: return launch_variant<S, T, 32, 8, false, kModeStep>(src, dst, hist, fields, P, stream);
-    case 2: return launch_variant<S, T, 32, 4, false, kModeStep>(src, dst, hist, fields, P, stream);
-    case 3: return launch_variant<S, T, 128, 4, false, kModeStep>(src, dst, hist, fields, P, stream);
-    case 4: return launch_variant<S, T, 64, 4, true, kModeStep>(src, dst, hist, fields, P, stream);
-    case 5: return launch_variant<S, T, 32, 8, true, kModeStep>(src, dst, hist, fields, P, stream);
-    case 6: return launch_variant<S, T, 32, 4, true, kModeStep>(src, dst, hist, fields, P, stream);
-    case 7: return launch_variant<S, T, 128, 4, true, kModeStep>(src, dst, hist, fields, P, stream);
-    default: return launch_variant<S, T, 64, 4, false, kModeStep>(src, dst, hist, fields, P, stream);
+    case 1: return launch_variant<S, T, 32, 8, false, M, U>(src, dst, hist, fields, P, stream);
+    case 2: return launch_variant<S, T, 32, 4, false, M, U>(src, dst, hist, fields, P, stream);
+    case 3: return launch_variant<S, T, 128, 4, false, M, U>(src, dst, hist, fields, P, stream);
+    case 4: return launch_variant<S, T, 64, 4, true, M, U>(src, dst, hist, fields, P, stream);
+    case 5: return launch_variant<S, T, 32, 8, true, M, U>(src, dst, hist, fields, P, stream);
+    case 6: return launch_variant<S, T, 32, 4, true, M, U>(src, dst, hist, fields, P, stream);
+    case 7: return launch_variant<S, T, 128, 4, true, M, U>(src, dst, hist, fields, P, stream);
+    default: return launch_variant<S, T, 64, 4, false, M, U>(src, dst, hist, fields, P, stream);
   }
 }
 

@@ -35,6 +35,7 @@
 #include <atomic>
 #include <cmath>
 
+#include "addr.hpp"
 #include "kernels.hpp"
 
 namespace pflb {
@@ -56,76 +57,13 @@ struct Geo3 {
   Off nxy;  // bytes between two z-planes of a population plane (nx ny sizeof(S))
 };
 
-// a uniform value the optimiser may not hoist or merge across uses
-template <class X>
-__device__ inline X opaque(X v) {
-  asm volatile("" : "+s"(v));
-  return v;
-}
-
-// the lattice constants as seen by the kernel: the constant address space
-// makes every read a scalar load of memory no store of the kernel touches
-template <class T>
-using KPtr = const __attribute__((address_space(4))) KParams<T>*;
-
-template <class T>
-__device__ inline const KParams<T>& params(KPtr<T> p) {
-  return *(const KParams<T>*)opaque(p);
-}
-
-// byte offset of plane k from a set base, formed on the scalar unit at each
-// use (a product the compiler may neither hoist nor fold into a 64-bit
-// vector multiply-add)
-template <class Off>
-__device__ inline Off plane(int k, Off stride) {
-  return k == 0 ? Off(0) : opaque(Off(k) * opaque(stride));
-}
-
-template <class P, class Off>
-__device__ inline P* at(P* base, Off off) {
-  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
-  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
-}
-
-__device__ inline int fold(int v, int n, int wall) {
-  if (v < 0) return wall ? 0 : v + n;
-  if (v >= n) return wall ? n - 1 : v - n;
-  return v;
-}
-
 __device__ inline int slot_of(int z) { return (z + 4) & 3; }
-
-template <int TX, int TY>
-__device__ inline void halo_pos(int k, int& hx, int& hy) {
-  constexpr int LX = TX + 2;
-  if (k < LX) {
-    hx = k - 1;
-    hy = -1;
-  } else if (k < 2 * LX) {
-    hx = k - LX - 1;
-    hy = TY;
-  } else if (k < 2 * LX + TY) {
-    hx = -1;
-    hy = k - 2 * LX;
-  } else {
-    hx = TX;
-    hy = k - 2 * LX - TY;
-  }
-}
 
 template <class T, int TX, int TY>
 struct Ring {
   T phi[4][TY + 2][TX + 2];
   T psi[4][TY + 2][TX + 2];
 };
-
-// one D3Q7 set of the node at byte offset `node` of a set base
-template <bool NTS, class S, class T, class Off>
-__device__ inline void load7(const S* __restrict__ base, Off sS, Off node, T (&x)[7]) {
-#pragma unroll
-  for (int i = 0; i < 7; ++i)
-    x[i] = Codec<S, T>::ld(ld_pop<NTS>(at(base, plane(i, sS) + node)), T(LF::w[i]));
-}
 
 template <class S, class T, int TX, int TY, bool NTS, bool PREF, bool LATE, int WPE, int MODE, class Off>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
@@ -135,7 +73,6 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr int NT = TX * TY, LX = TX + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
   constexpr Off BS = sizeof(S);
-  constexpr Off BT = sizeof(T);
   __shared__ Ring<T, TX, TY> R;
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
   const int per = (G.ntiles + 7) / 8;
@@ -172,27 +109,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     halo_col = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
   }
 
-  // x / y push deltas (bytes, modular) and bounce bits of this lane:
-  // bit 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+
-  const Off rowb = Off(nx) * BS;
-  Off dxm = Off(0) - BS, dxp = BS, dym = Off(0) - rowb, dyp = rowb;
-  int lane_bits = 0;
-  if (x == 0) {
-    if (G.wall_x) lane_bits |= 1;
-    dxm = Off(nx - 1) * BS;
-  }
-  if (x == nx - 1) {
-    if (G.wall_x) lane_bits |= 2;
-    dxp = Off(0) - Off(nx - 1) * BS;
-  }
-  if (y == 0) {
-    if (G.wall_y) lane_bits |= 4;
-    dym = Off(ny - 1) * rowb;
-  }
-  if (y == ny - 1) {
-    if (G.wall_y) lane_bits |= 8;
-    dyp = Off(0) - Off(ny - 1) * rowb;
-  }
+  const PushXY<Off> push(x, y, nx, ny, G.wall_x, G.wall_y, BS);
 
   // moments of plane zp for the own slot and the halo slot of the ring
   auto put = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7], const T (&h2)[7],
@@ -211,9 +128,9 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
   };
   auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
-    load7<NTS>(sF, G.sS, node, f);
-    load7<NTS>(sH1, G.sS, node, h1);
-    load7<NTS>(sH2, G.sS, node, h2);
+    load_q<LF, NTS, true>(sF, G.sS, node, f);
+    load_q<LF, NTS, true>(sH1, G.sS, node, h1);
+    load_q<LF, NTS, true>(sH2, G.sS, node, h2);
   };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
@@ -249,9 +166,9 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     auto load_g = [&] {
 #pragma unroll
       for (int i = 0; i < 19; ++i)
-        g[i] = Codec<S, T>::ld(ld_pop<NTS>(at(sG, plane(i, G.sS) + node)), T(LG::w[i]));
+        g[i] = Codec<S, T>::ld(ld_pop<NTS>(at(sG, plane<true>(i, G.sS) + node)), T(LG::w[i]));
 #pragma unroll
-      for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane(k, G.sT) + nodeT);
+      for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane<true>(k, G.sT) + nodeT);
     };
     if (PREF && active) load_g();
     if (own_slot) load_fh(pn + own_col, nf, nh1, nh2);
@@ -289,7 +206,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       Flow<T> fl;
       flow_macros<LG>(P, g, s, gphi, lap, fl);
       if (MODE == kModeMacros) {
-        auto put_field = [&](int k, T v) { *at(fields, plane(k, G.sT) + nodeT) = v; };
+        auto put_field = [&](int k, T v) { *at(fields, plane<true>(k, G.sT) + nodeT) = v; };
         put_field(kFieldPhi, s.phi);
         put_field(kFieldP, fl.p);
         put_field(kFieldUx, fl.u[0]);
@@ -311,12 +228,12 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
         for (int k = 0; k < kHist3D; ++k) {
           const T v = k < 3 ? fl.u[k] : (k == 3 ? s.phi : (k == 4 ? s.c1 : s.c2));
-          *at(hist, plane(k, G.sT) + nodeT) = v;
+          *at(hist, plane<true>(k, G.sT) + nodeT) = v;
         }
 
         // z push deltas and bounce bits of this plane (uniform)
         Off dzm = Off(0) - G.nxy, dzp = G.nxy;
-        int bits = lane_bits;
+        int bits = push.bits;
         if (z == 0) {
           if (G.wall_z) bits |= 16;
           dzm = Off(nz - 1) * G.nxy;
@@ -328,13 +245,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         // byte offset of the push target of direction i (plane i of its set),
         // or of the bounce-back target (plane opp(i), this node)
         auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
-          const int m = (cx < 0 ? 1 : 0) | (cx > 0 ? 2 : 0) | (cy < 0 ? 4 : 0) |
-                        (cy > 0 ? 8 : 0) | (cz < 0 ? 16 : 0) | (cz > 0 ? 32 : 0);
           Off t = node;
-          if (cx) t += cx < 0 ? dxm : dxp;
-          if (cy) t += cy < 0 ? dym : dyp;
+          if (cx) t += cx < 0 ? push.dxm : push.dxp;
+          if (cy) t += cy < 0 ? push.dym : push.dyp;
           if (cz) t += cz < 0 ? dzm : dzp;
-          return (bits & m) ? plane(o, G.sS) + node : plane(i, G.sS) + t;
+          return (bits & link_mask(cx, cy, cz)) ? plane<true>(o, G.sS) + node : plane<true>(i, G.sS) + t;
         };
         S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
         S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
@@ -346,14 +261,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
           const Off t = target(i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
           st_pop<NTS>(at(dG, t), Codec<S, T>::st(v, T(1.0 / LG::w[i])));
         });
-        if (LATE) load7<NTS>(sF, G.sS, node, f);
+        if (LATE) load_q<LF, NTS, true>(sF, G.sS, node, f);
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
           st_pop<NTS>(at(dF, t), Codec<S, T>::st(v, T(1.0 / LF::w[i])));
         });
         if (LATE) {
-          load7<NTS>(sH1, G.sS, node, h1);
-          load7<NTS>(sH2, G.sS, node, h2);
+          load_q<LF, NTS, true>(sH1, G.sS, node, h1);
+          load_q<LF, NTS, true>(sH2, G.sS, node, h2);
         }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
@@ -372,14 +287,6 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
     s = ns;
   }
-}
-
-// true when every set, the history and the field buffer span < 4 GiB, so
-// that 32-bit byte offsets reach every value
-bool fits_u32(long long stride, size_t sS, size_t sT) {
-  const unsigned long long lim = 1ull << 32;
-  return (unsigned long long)LG::Q * stride * sS < lim &&
-         (unsigned long long)kNumFields * stride * sT < lim;
 }
 
 // Work-groups the device holds at once for a kernel (groups per CU x CUs),
@@ -467,7 +374,7 @@ hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
   constexpr int M = kModeStep;
   using U = uint32_t;
-  if (!fits_u32(P.stride, sizeof(S), sizeof(T))) {
+  if (!fits_u32(LG::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
       return launch_variant<S, T, 64, 4, false, false, false, 1, kModeMacros, uint64_t>(
