@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 49254684, "write": 43001204, "src": "ab400b69a2ad6851"},
-    "rising_droplet_256c_f32": {"read": 3662771985, "write": 3201350789, "src": "ab400b69a2ad6851"},
-    "rising_droplet_256c_f32_s16f": {"read": 2475823174, "write": 1755833136,
-                                     "src": "ab400b69a2ad6851"},
+    "rising_bubble_256x1024_f32": {"read": 44915524, "write": 43041543, "src": "79b503c127b86ec7"},
+    "rising_droplet_256c_f32": {"read": 3683998782, "write": 3200334112, "src": "79b503c127b86ec7"},
+    "rising_droplet_256c_f32_s16f": {"read": 2475879219, "write": 1756400432,
+                                     "src": "79b503c127b86ec7"},
 }
 
 
@@ -126,7 +126,7 @@ def time_gpu(w, steps, warmup, graph=True):
     return dict(n=n, total_ms=total_ms, avg_kernel_ms=total_ms / steps, graph=use_graph, reduce=r)
 
 
-def cpu_baseline(w, seconds=15.0):
+def cpu_baseline(w, seconds=25.0):
     """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
     a fixed number of steps sized to ~10-30 s of CPU work."""
     from oracle import ref

@@ -65,13 +65,15 @@ struct Ring {
   T psi[4][TY + 2][TX + 2];
 };
 
-template <class S, class T, int TX, int TY, bool NTS, bool PREF, bool LATE, int WPE, int MODE, class Off>
+template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
                                                         T* __restrict__ fields,
                                                         KPtr<T> Pg, Geo3<Off> G) {
-  constexpr int NT = TX * TY, LX = TX + 2, NHALO = 2 * LX + 2 * TY;
-  static_assert(NHALO <= NT, "one halo node per thread at most");
+  constexpr int NTH = TX * TY, LX = TX + 2, NHALO = 2 * LX + 2 * TY;
+  static_assert(NHALO <= NTH, "one halo node per thread at most");
+  // non-temporal hints: bit 0 f / h loads, bit 1 stores, bit 2 g loads
+  constexpr bool NTL = NT & 1, NTW = NT & 2, NTG = NT & 4;
   constexpr Off BS = sizeof(S);
   __shared__ Ring<T, TX, TY> R;
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
@@ -128,9 +130,9 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
   };
   auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
-    load_q<LF, NTS, true>(sF, G.sS, node, f);
-    load_q<LF, NTS, true>(sH1, G.sS, node, h1);
-    load_q<LF, NTS, true>(sH2, G.sS, node, h2);
+    load_q<LF, NTL, true>(sF, G.sS, node, f);
+    load_q<LF, NTL, true>(sH1, G.sS, node, h1);
+    load_q<LF, NTL, true>(sH2, G.sS, node, h2);
   };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     auto load_g = [&] {
 #pragma unroll
       for (int i = 0; i < 19; ++i)
-        g[i] = Codec<S, T>::ld(ld_pop<NTS>(at(sG, plane<true>(i, G.sS) + node)), T(LG::w[i]));
+        g[i] = Codec<S, T>::ld(ld_pop<NTG>(at(sG, plane<true>(i, G.sS) + node)), T(LG::w[i]));
 #pragma unroll
       for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane<true>(k, G.sT) + nodeT);
     };
@@ -259,21 +261,21 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         normal(P, gphi, n);
         collide_g<LG>(P, g, gphi, fl, [&](int i, T v) {
           const Off t = target(i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
-          st_pop<NTS>(at(dG, t), Codec<S, T>::st(v, T(1.0 / LG::w[i])));
+          st_pop<NTW>(at(dG, t), Codec<S, T>::st(v, T(1.0 / LG::w[i])));
         });
-        if (LATE) load_q<LF, NTS, true>(sF, G.sS, node, f);
+        if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          st_pop<NTS>(at(dF, t), Codec<S, T>::st(v, T(1.0 / LF::w[i])));
+          st_pop<NTW>(at(dF, t), Codec<S, T>::st(v, T(1.0 / LF::w[i])));
         });
         if (LATE) {
-          load_q<LF, NTS, true>(sH1, G.sS, node, h1);
-          load_q<LF, NTS, true>(sH2, G.sS, node, h2);
+          load_q<LF, NTL, true>(sH1, G.sS, node, h1);
+          load_q<LF, NTL, true>(sH2, G.sS, node, h2);
         }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
-          st_pop<NTS>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
+          st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
+          st_pop<NTW>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
         });
       }
     }
@@ -325,11 +327,11 @@ int choose_chunks(int tiles_xy, int nz, int slots) {
   return best;
 }
 
-template <class S, class T, int TX, int TY, bool NTS, bool PREF, bool LATE, int WPE, int MODE,
+template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE,
           class Off>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, hipStream_t stream) {
-  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NTS, PREF, LATE, WPE, MODE, Off>;
+  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off>;
   static std::atomic<int> per_cu{0};
   int groups = per_cu.load(std::memory_order_relaxed);
   if (groups < 1) {
@@ -363,9 +365,9 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
 }  // namespace
 
 const char* step3d_variant_name(int v) {
-  static const char* names[kVariants3D] = {"64x4 late",   "64x4 late w4",       "32x8 late",
-                                          "64x4",        "16x16 late",         "64x4 late prefetch",
-                                          "64x4 late nt", "32x4 late"};
+  static const char* names[kVariants3D] = {
+      "64x4 late",         "64x4 late nt-st", "32x8 late",          "64x4",
+      "64x4 nt-st",        "64x4 nt-g-st",    "64x4 late nt-g-st",  "64x4 late w4"};
   return v >= 0 && v < kVariants3D ? names[v] : "?";
 }
 
@@ -377,27 +379,28 @@ hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams
   if (!fits_u32(LG::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, false, false, false, 1, kModeMacros, uint64_t>(
+      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t>(
           src, dst, hist, fields, P, Pdev, stream);
-    return launch_variant<S, T, 64, 4, false, false, true, 1, M, uint64_t>(
+    return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t>(
         src, dst, hist, fields, P, Pdev, stream);
   }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, false, false, 1, kModeMacros, U>(
+    return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U>(
         src, dst, hist, fields, P, Pdev, stream);
-#define PFLB_V3(TX, TY, NTS, PREF, LATE, WPE) \
-  launch_variant<S, T, TX, TY, NTS, PREF, LATE, WPE, M, U>(src, dst, hist, fields, P, Pdev, \
-                                                               stream)
-  // WPE: minimum waves per SIMD the register allocator must allow (1: free)
+#define PFLB_V3(TX, TY, NT, PREF, LATE, WPE) \
+  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U>(src, dst, hist, fields, P, Pdev, stream)
+  // NT: non-temporal hints (bit 0 f / h loads, bit 1 stores, bit 2 g loads);
+  // LATE: f / h re-read before their collision; WPE: minimum waves per SIMD
+  // the register allocator must allow (1: free)
   switch (variant) {
-    case 1: return PFLB_V3(64, 4, false, false, true, 4);
-    case 2: return PFLB_V3(32, 8, false, false, true, 1);
-    case 3: return PFLB_V3(64, 4, false, false, false, 1);
-    case 4: return PFLB_V3(16, 16, false, false, true, 1);
-    case 5: return PFLB_V3(64, 4, false, true, true, 1);
-    case 6: return PFLB_V3(64, 4, true, false, true, 1);
-    case 7: return PFLB_V3(32, 4, false, false, true, 1);
-    default: return PFLB_V3(64, 4, false, false, true, 1);
+    case 1: return PFLB_V3(64, 4, 2, false, true, 1);
+    case 2: return PFLB_V3(32, 8, 0, false, true, 1);
+    case 3: return PFLB_V3(64, 4, 0, false, false, 1);
+    case 4: return PFLB_V3(64, 4, 2, false, false, 1);
+    case 5: return PFLB_V3(64, 4, 6, false, false, 1);
+    case 6: return PFLB_V3(64, 4, 6, false, true, 1);
+    case 7: return PFLB_V3(64, 4, 0, false, true, 4);
+    default: return PFLB_V3(64, 4, 0, false, true, 1);
   }
 #undef PFLB_V3
 }
