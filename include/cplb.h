@@ -176,6 +176,71 @@ int cplb_set_variant(cplb_t* h, int variant);
 const char* cplb_variant_name(const cplb_t* h, int variant);
 int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent 2-D lattices (CPLB_D2Q9), each with its own
+ * grid, boundaries and parameters, advanced together -- the parameter
+ * sweeps of the paper's transfer studies (Sec. IV) run as one job.  A step
+ * runs one kernel launch per size class (cases grouped by nx into
+ * CPLB_BATCH_CLASSES classes, each with its own tile-shape variant from
+ * the 2-D variant table); each launch covers every tile of every case of
+ * its class.  Every case evolves bit-identically to the same case run alone
+ * with cplb_create / cplb_step.  All cases share the precision of case 0.
+ * The caller owns the workspace and the stream as for a single lattice;
+ * icase numbers cases in the order of prm[].  Errors as above.
+ */
+#define CPLB_BATCH_CLASSES 3 /* size classes: nx <= 96, nx <= 160, larger */
+
+typedef struct cplb_batch cplb_batch_t;
+
+/* Device workspace for ncases >= 1 cases with parameters prm[0..ncases).
+ * CPLB_EINVAL for an invalid case (the checks of cplb_create, plus:
+ * CPLB_D2Q9 only, same precision as case 0). */
+int cplb_batch_workspace_bytes(const cplb_params* prm, int ncases, size_t* bytes);
+
+/* Validate every case, carve the workspace (256-byte aligned, at least
+ * cplb_batch_workspace_bytes) and upload the case tables.  Synchronises. */
+int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, size_t bytes,
+                      void* hip_stream, cplb_batch_t** out);
+
+/* Initial state of one case from a host signed-distance field (N values of
+ * that case), as cplb_init_sdf.  Synchronises the stream. */
+int cplb_batch_init_sdf(cplb_batch_t* b, int icase, const double* l, double c1_a, double c1_b,
+                        double c2_a, double c2_b);
+
+/* Advance every case nsteps >= 0 steps.  Asynchronous; a caller may capture
+ * the launches in a HIP graph. */
+int cplb_batch_step(cplb_batch_t* b, int64_t nsteps);
+
+int cplb_batch_num_cases(const cplb_batch_t* b);
+int64_t cplb_batch_step_count(const cplb_batch_t* b);
+
+/* Field of one case at the current level, as cplb_read_field. */
+int cplb_batch_read_field(cplb_batch_t* b, int icase, int field, void* dev_dst, int dtype);
+
+/* Reductions of one case, as cplb_reduce (out[7] = batch step counter). */
+int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]);
+
+/* Size classes: number, class of a case, cases in a class, and the 2-D
+ * step variant (cplb_variant_name of a D2Q9 lattice names it) each class
+ * runs; set_variant returns CPLB_EINVAL for an unknown class or variant. */
+int cplb_batch_num_classes(const cplb_batch_t* b);
+int cplb_batch_case_class(const cplb_batch_t* b, int icase);
+int cplb_batch_class_cases(const cplb_batch_t* b, int cls);
+int cplb_batch_get_variant(const cplb_batch_t* b, int cls);
+int cplb_batch_set_variant(cplb_batch_t* b, int cls, int variant);
+
+/* Autotuner: per class, time every variant for probe_steps launches on the
+ * current state and keep the fastest.  The state is left as it was (probes
+ * write only the idle lattices; histories are saved and restored).
+ * Synchronises; *ms_per_step (may be NULL) receives the sum of the classes'
+ * best times per step. */
+int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step);
+
+const char* cplb_batch_last_error(const cplb_batch_t* b);
+
+/* Release the batch (not the caller's workspace or stream). */
+void cplb_batch_destroy(cplb_batch_t* b);
+
 /* Error text of the last failed call on h, and of a return code. */
 const char* cplb_last_error(const cplb_t* h);
 const char* cplb_strerror(int code);

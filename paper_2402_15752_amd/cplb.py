@@ -28,7 +28,13 @@ EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init
            "cplb_read_field", "cplb_reduce", "cplb_step_count", "cplb_state_bytes",
            "cplb_save_state", "cplb_load_state", "cplb_last_error", "cplb_strerror",
            "cplb_destroy", "cplb_num_variants", "cplb_get_variant", "cplb_set_variant",
-           "cplb_variant_name", "cplb_tune")
+           "cplb_variant_name", "cplb_tune",
+           "cplb_batch_workspace_bytes", "cplb_batch_create", "cplb_batch_init_sdf",
+           "cplb_batch_step", "cplb_batch_num_cases", "cplb_batch_step_count",
+           "cplb_batch_read_field", "cplb_batch_reduce", "cplb_batch_num_classes",
+           "cplb_batch_case_class", "cplb_batch_class_cases", "cplb_batch_get_variant",
+           "cplb_batch_set_variant", "cplb_batch_tune", "cplb_batch_last_error",
+           "cplb_batch_destroy")
 
 
 class cplb_params(ctypes.Structure):
@@ -89,6 +95,27 @@ def library():
         L.cplb_variant_name.argtypes = [vp, ctypes.c_int]
         L.cplb_variant_name.restype = ctypes.c_char_p
         L.cplb_tune.argtypes = [vp, ctypes.c_int, dp]
+        i32 = ctypes.c_int
+        L.cplb_batch_workspace_bytes.argtypes = [P, i32, ctypes.POINTER(sz)]
+        L.cplb_batch_create.argtypes = [P, i32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.cplb_batch_init_sdf.argtypes = [vp, i32, dp, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double]
+        L.cplb_batch_step.argtypes = [vp, ctypes.c_int64]
+        L.cplb_batch_num_cases.argtypes = [vp]
+        L.cplb_batch_step_count.argtypes = [vp]
+        L.cplb_batch_step_count.restype = ctypes.c_int64
+        L.cplb_batch_read_field.argtypes = [vp, i32, i32, vp, i32]
+        L.cplb_batch_reduce.argtypes = [vp, i32, dp]
+        for f in ("cplb_batch_num_classes",):
+            getattr(L, f).argtypes = [vp]
+        for f in ("cplb_batch_case_class", "cplb_batch_class_cases", "cplb_batch_get_variant"):
+            getattr(L, f).argtypes = [vp, i32]
+        L.cplb_batch_set_variant.argtypes = [vp, i32, i32]
+        L.cplb_batch_tune.argtypes = [vp, i32, dp]
+        L.cplb_batch_last_error.argtypes = [vp]
+        L.cplb_batch_last_error.restype = ctypes.c_char_p
+        L.cplb_batch_destroy.argtypes = [vp]
+        L.cplb_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -327,3 +354,183 @@ class Lattice:
 
     def load_state(self, blob: bytes):
         cplb_load_state(self._h, blob)
+
+
+# ------------------------------------------------------------------ batches
+
+def _params_array(ps):
+    arr = (cplb_params * len(ps))()
+    for k, p in enumerate(ps):
+        arr[k] = make_params(p)
+    return arr
+
+
+def _bcheck(b, rc):
+    if rc:
+        raise CplbError(rc, library().cplb_batch_last_error(b).decode())
+
+
+def cplb_batch_workspace_bytes(prms, ncases: int) -> int:
+    n = ctypes.c_size_t()
+    rc = library().cplb_batch_workspace_bytes(prms, ncases, ctypes.byref(n))
+    if rc:
+        raise CplbError(rc, "cplb_batch_workspace_bytes rejected the parameters")
+    return n.value
+
+
+def cplb_batch_create(prms, ncases: int, ws_ptr: int, ws_bytes: int, stream_ptr: int):
+    b = ctypes.c_void_p()
+    rc = library().cplb_batch_create(prms, ncases, ctypes.c_void_p(ws_ptr), ws_bytes,
+                                     ctypes.c_void_p(stream_ptr), ctypes.byref(b))
+    if rc:
+        raise CplbError(rc, "cplb_batch_create failed")
+    return b
+
+
+def cplb_batch_init_sdf(b, icase, l, c1_a, c1_b, c2_a, c2_b):
+    _bcheck(b, library().cplb_batch_init_sdf(b, icase, _dp(l), c1_a, c1_b, c2_a, c2_b))
+
+
+def cplb_batch_step(b, nsteps: int):
+    _bcheck(b, library().cplb_batch_step(b, nsteps))
+
+
+def cplb_batch_num_cases(b) -> int:
+    return library().cplb_batch_num_cases(b)
+
+
+def cplb_batch_step_count(b) -> int:
+    return library().cplb_batch_step_count(b)
+
+
+def cplb_batch_read_field(b, icase: int, field: int, dev_ptr: int, dtype: int):
+    _bcheck(b, library().cplb_batch_read_field(b, icase, field, ctypes.c_void_p(dev_ptr), dtype))
+
+
+def cplb_batch_reduce(b, icase: int):
+    out = np.zeros(8)
+    rc = library().cplb_batch_reduce(b, icase, _dp(out))
+    if rc and rc != CPLB_EUNSTABLE:
+        _bcheck(b, rc)
+    return out, rc
+
+
+def cplb_batch_num_classes(b) -> int:
+    return library().cplb_batch_num_classes(b)
+
+
+def cplb_batch_case_class(b, icase: int) -> int:
+    return library().cplb_batch_case_class(b, icase)
+
+
+def cplb_batch_class_cases(b, cls: int) -> int:
+    return library().cplb_batch_class_cases(b, cls)
+
+
+def cplb_batch_get_variant(b, cls: int) -> int:
+    return library().cplb_batch_get_variant(b, cls)
+
+
+def cplb_batch_set_variant(b, cls: int, v: int):
+    _bcheck(b, library().cplb_batch_set_variant(b, cls, v))
+
+
+def cplb_batch_tune(b, probe_steps: int) -> float:
+    ms = ctypes.c_double()
+    _bcheck(b, library().cplb_batch_tune(b, probe_steps, ctypes.byref(ms)))
+    return ms.value
+
+
+def cplb_batch_last_error(b) -> str:
+    return library().cplb_batch_last_error(b).decode()
+
+
+def cplb_batch_destroy(b):
+    library().cplb_batch_destroy(b)
+
+
+class Batch:
+    """Independent D2Q9 lattices (one parameter dict each, same precision)
+    advanced together on one GPU.  Fields come back as torch tensors of
+    shape (ny, nx) of the case asked for."""
+
+    def __init__(self, params: list, device="cuda:0", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("cplb needs a GPU: torch.cuda.is_available() is False")
+        self.torch = torch
+        self.params = [dict(p) for p in params]
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        self._prms = _params_array(self.params)
+        nbytes = cplb_batch_workspace_bytes(self._prms, self.n)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._b = cplb_batch_create(self._prms, self.n, self.workspace.data_ptr(), nbytes,
+                                    self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            cplb_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._b
+
+    def init_sdf(self, icase, l, c1=(0.0, 0.0), c2=(0.0, 0.0)):
+        p = self.params[icase]
+        l = np.ascontiguousarray(l, dtype=np.float64).reshape(-1)
+        assert l.size == int(p["nx"]) * int(p["ny"])
+        cplb_batch_init_sdf(self._b, icase, l, float(c1[0]), float(c1[1]), float(c2[0]),
+                            float(c2[1]))
+
+    def step(self, n=1):
+        cplb_batch_step(self._b, n)
+
+    @property
+    def step_count(self):
+        return cplb_batch_step_count(self._b)
+
+    def field(self, icase, name, dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.float64
+        p = self.params[icase]
+        out = torch.empty((p["ny"], p["nx"]), dtype=dtype, device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        other = cur != self.stream
+        if other:
+            self.stream.wait_stream(cur)
+        cplb_batch_read_field(self._b, icase, FIELDS[name], out.data_ptr(),
+                              DTYPE_F64 if dtype == torch.float64 else DTYPE_F32)
+        if other:
+            cur.wait_stream(self.stream)
+            out.record_stream(self.stream)
+        return out
+
+    def reduce(self, icase):
+        out, rc = cplb_batch_reduce(self._b, icase)
+        keys = ("sum_phi", "sum_c1", "sum_c2", "sum_c", "max_u", "kinetic", "nonfinite", "step")
+        r = dict(zip(keys, out.tolist()))
+        r["rc"] = rc
+        return r
+
+    def classes(self):
+        """[(cases in class, variant index)] per size class."""
+        return [(cplb_batch_class_cases(self._b, c), cplb_batch_get_variant(self._b, c))
+                for c in range(cplb_batch_num_classes(self._b))]
+
+    def set_variant(self, cls, v):
+        cplb_batch_set_variant(self._b, cls, v)
+
+    def tune(self, probe_steps=10):
+        """Pick the fastest tile variant per size class; returns ms per batch step."""
+        return cplb_batch_tune(self._b, probe_steps)

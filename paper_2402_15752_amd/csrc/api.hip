@@ -8,129 +8,11 @@
 #include <new>
 
 #include "../../include/cplb.h"
+#include "host.hpp"
 #include "kernels.hpp"
 
 using namespace pflb;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Geometry {
-  int dim, qtot, nhist;
-  long long n;       // nodes
-  long long stride;  // elements per plane
-  size_t s_pop, s_cmp;
-  size_t lat_bytes, hist_bytes, field_bytes, part_bytes, kp_bytes, total;
-};
-
-int validate(const cplb_params* p, char* err, size_t errn) {
-  auto fail = [&](const char* m) {
-    snprintf(err, errn, "%s", m);
-    return CPLB_EINVAL;
-  };
-  if (!p) return fail("null parameters");
-  if (p->lattice != CPLB_D2Q9 && p->lattice != CPLB_D3Q19_D3Q7) return fail("unknown lattice");
-  if (p->precision < CPLB_F64 || p->precision > CPLB_F32_S16B) return fail("unknown precision");
-  if (p->visc_law != CPLB_VISC_LINEAR && p->visc_law != CPLB_VISC_EXP)
-    return fail("unknown viscosity law");
-  if (p->reserved != 0) return fail("reserved field must be 0");
-  const int d = p->lattice == CPLB_D2Q9 ? 2 : 3;
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
-  if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
-  const int n3[3] = {p->nx, p->ny, p->nz};
-  for (int a = 0; a < d; ++a)
-    if (!p->periodic[a] && n3[a] < 2) return fail("a walled axis needs at least 2 nodes");
-  if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail("grid too large (> 2e9 nodes)");
-  if (!(p->rho1 > 0 && p->rho2 > 0 && p->mu1 > 0 && p->mu2 > 0))
-    return fail("densities and viscosities must be positive");
-  if (!(p->W > 0 && p->M > 0 && p->D1 > 0 && p->D2 > 0 && p->Keq > 0 && p->n_eps > 0))
-    return fail("W, M, D1, D2, Keq, n_eps must be positive (every tau > 1/2)");
-  if (!(p->sigma >= 0 && p->A >= 0)) return fail("sigma and A must be >= 0");
-  if (d == 2 && p->g[2] != 0.0) return fail("2-D lattice: g[2] must be 0");
-  if (p->ref[1] != 0.0) return fail("ref[1] (flow set) must be 0");
-  const double all[] = {p->rho1, p->rho2, p->mu1,  p->mu2,  p->sigma, p->W,    p->M,
-                        p->D1,   p->D2,   p->Keq,  p->A,    p->g[0],  p->g[1], p->g[2],
-                        p->rho_ref, p->n_eps, p->ref[0], p->ref[1], p->ref[2], p->ref[3]};
-  for (double v : all)
-    if (!std::isfinite(v)) return fail("non-finite parameter");
-  return CPLB_OK;
-}
-
-Geometry geometry(const cplb_params* p) {
-  Geometry G{};
-  G.dim = p->lattice == CPLB_D2Q9 ? 2 : 3;
-  G.qtot = G.dim == 2 ? Layout<D2Q9, D2Q9>::QTOT : Layout<D3Q7, D3Q19>::QTOT;
-  G.nhist = G.dim == 2 ? kHist2D : kHist3D;
-  G.n = (long long)p->nx * p->ny * p->nz;
-  // planes padded to 64 elements plus one 64-element skew, so that the
-  // same node of successive planes does not land on the same HBM channel
-  G.stride = (G.n + 63) / 64 * 64 + 64;
-  switch (p->precision) {
-    case CPLB_F64: G.s_pop = 8; G.s_cmp = 8; break;
-    case CPLB_F32: G.s_pop = 4; G.s_cmp = 4; break;
-    default: G.s_pop = 2; G.s_cmp = 4; break;
-  }
-  G.lat_bytes = align_up((size_t)G.qtot * G.stride * G.s_pop, kAlign);
-  G.hist_bytes = align_up((size_t)G.nhist * G.stride * G.s_cmp, kAlign);
-  G.field_bytes = align_up((size_t)kNumFields * G.stride * G.s_cmp, kAlign);
-  G.part_bytes = align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
-  G.kp_bytes = align_up(sizeof(KParams<double>), kAlign) + align_up(sizeof(KParams<float>), kAlign);
-  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes + G.kp_bytes;
-  return G;
-}
-
-template <class T>
-KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
-  KParams<T> K{};
-  K.nx = p->nx;
-  K.ny = p->ny;
-  K.nz = p->nz;
-  for (int a = 0; a < 3; ++a) K.wall[a] = (a < G.dim && !p->periodic[a]) ? 1 : 0;
-  K.stride = G.stride;
-  const double csf = G.dim == 2 ? D2Q9::cs2 : D3Q7::cs2;
-  // relaxation times from the transport coefficients (Sec. III)
-  const double tau_f = 0.5 + p->M / csf;
-  const double tau_h1 = 0.5 + p->D1 / csf;
-  const double tau_h2 = 0.5 + p->D2 / csf;
-  // delta = 2 - 1/tau = 2 (tau - 1/2) / tau, formed from tau - 1/2 directly
-  K.del_f = T(2.0 * (p->M / csf) / tau_f);
-  K.hdel_f = T((p->M / csf) / tau_f);
-  K.del_h1 = T(2.0 * (p->D1 / csf) / tau_h1);
-  K.hdel_h1 = T((p->D1 / csf) / tau_h1);
-  K.del_h2 = T(2.0 * (p->D2 / csf) / tau_h2);
-  K.hdel_h2 = T((p->D2 / csf) / tau_h2);
-  // beta = 12 sigma / W, k = 3 sigma W / 2 (Sec. II B)
-  K.beta4 = T(4.0 * 12.0 * p->sigma / p->W);
-  K.kappa = T(1.5 * p->sigma * p->W);
-  K.rho1 = T(p->rho1);
-  K.rho2 = T(p->rho2);
-  K.drho = T(p->rho1 - p->rho2);
-  K.rho_ref = T(p->rho_ref);
-  for (int a = 0; a < 3; ++a) K.grav[a] = T(p->g[a]);
-  K.mu1 = T(p->mu1);
-  K.mu2 = T(p->mu2);
-  K.ln_mu1 = T(std::log(p->mu1));
-  K.ln_mu2 = T(std::log(p->mu2));
-  K.visc_exp = p->visc_law == CPLB_VISC_EXP;
-  K.D1D2 = T(p->D1 * p->D2);
-  K.KD1 = T(p->Keq * p->D1);
-  K.D2 = T(p->D2);
-  K.Keq = T(p->Keq);
-  K.A = T(p->A);
-  K.half_A = T(0.5 * p->A);
-  K.four_over_W = T(4.0 / p->W);
-  K.neps2 = T(p->n_eps * p->n_eps);
-  // reference state of the stored deviations (f, h1, h2; g is stored as is)
-  K.ref_phi = T(p->ref[0]);
-  K.one_minus_ref_phi = T(1.0 - p->ref[0]);
-  K.ref_c1 = T(p->ref[2]);
-  K.ref_c2 = T(p->ref[3]);
-  return K;
-}
-
-}  // namespace
 
 struct cplb {
   cplb_params prm;
@@ -143,7 +25,6 @@ struct cplb {
   double* partials;
   int cur;
   int64_t step;
-  bool fields_valid;
   int variant;  // compiled step-kernel variant in use
   KParams<double> k64;  // lattice constants (host copies)
   KParams<float> k32;
@@ -199,12 +80,10 @@ hipError_t run_kernel(cplb_t* h, int mode) {
   }
 }
 
-int ensure_fields(cplb_t* h) {
-  if (h->fields_valid) return CPLB_OK;
-  int rc = hip_check(h, run_kernel(h, kModeMacros), "macros kernel");
-  if (rc == CPLB_OK) h->fields_valid = true;
-  return rc;
-}
+// The field buffer is recomputed from the current populations on every
+// read-out: steps may also advance the state from a captured graph, which
+// the host does not see, so no host-side flag can tell whether it is stale.
+int compute_fields(cplb_t* h) { return hip_check(h, run_kernel(h, kModeMacros), "macros kernel"); }
 
 // host FP64 arrays -> staging area (the idle lattice) -> equilibrium init
 int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, const double* u,
@@ -256,7 +135,6 @@ int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, cons
   rc = hip_check(h, hipStreamSynchronize(h->stream), "init synchronise");
   if (rc) return rc;
   h->step = 0;
-  h->fields_valid = false;
   return CPLB_OK;
 }
 
@@ -313,7 +191,6 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->k32_dev = (KParams<float>*)(h->ws + off);
   h->cur = 0;
   h->step = 0;
-  h->fields_valid = false;
   h->variant = default_variant(prm);
   h->k64 = make_kparams<double>(prm, G);
   h->k32 = make_kparams<float>(prm, G);
@@ -358,7 +235,6 @@ int cplb_step(cplb_t* h, int64_t nsteps) {
     h->cur ^= 1;
     h->step++;
   }
-  if (nsteps > 0) h->fields_valid = false;
   return CPLB_OK;
 }
 
@@ -370,7 +246,7 @@ int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype) {
   if (dtype != CPLB_DTYPE_F32 && dtype != CPLB_DTYPE_F64)
     return set_err(h, CPLB_EINVAL, "unknown destination dtype");
   if (!dev_dst) return set_err(h, CPLB_EINVAL, "null destination");
-  int rc = ensure_fields(h);
+  int rc = compute_fields(h);
   if (rc) return rc;
   hipError_t e;
   if (h->G.s_cmp == 8)
@@ -384,7 +260,7 @@ int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype) {
 
 int cplb_reduce(cplb_t* h, double out[8]) {
   if (!h || !out) return CPLB_EINVAL;
-  int rc = ensure_fields(h);
+  int rc = compute_fields(h);
   if (rc) return rc;
   double* dout = h->partials + 8 * kReduceBlocks;
   const int nparts = h->G.n < (long long)kReduceBlocks * 256 ? (int)((h->G.n + 255) / 256) : kReduceBlocks;
@@ -466,7 +342,6 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
     if (rc) return rc;
   }
   h->step = hd.step;
-  h->fields_valid = false;
   return CPLB_OK;
 }
 
@@ -533,7 +408,6 @@ int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step) {
   int rc2 = hip_check(h, hipMemcpyAsync(h->hist, h->fields, hb, hipMemcpyDeviceToDevice, h->stream),
                       "tune: restore history");
   if (rc2 == CPLB_OK) rc2 = hip_check(h, hipStreamSynchronize(h->stream), "tune: synchronise");
-  h->fields_valid = false;
   if (rc) return rc;
   if (rc2) return rc2;
   if (ms_per_step) *ms_per_step = best_ms / probe_steps;

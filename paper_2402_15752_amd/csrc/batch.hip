@@ -1,0 +1,527 @@
+// C-ABI of the batch: many independent 2-D lattices advanced together.
+// Validation, workspace layout, size classes, launch order and the tuner;
+// all arithmetic is in the batched kernel (batch2d.hip), the init kernel and
+// the read-out / reduction kernels shared with the single-lattice API.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/cplb.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace pflb;
+
+namespace {
+
+// size classes by nx: the tile shape that suits a lattice depends on its width
+constexpr int kBatchClasses = CPLB_BATCH_CLASSES;
+constexpr int kClassMaxNx[kBatchClasses] = {96, 160, 1 << 30};
+
+int class_of(int nx) {
+  for (int c = 0; c < kBatchClasses; ++c)
+    if (nx <= kClassMaxNx[c]) return c;
+  return kBatchClasses - 1;
+}
+
+// measured on MI355X for lattices of 64..256 a side; cplb_batch_tune refines
+constexpr int kClassDefaultVariant[kBatchClasses] = {0, 0, 3};
+
+struct Region {
+  size_t lat, hist, fields;  // offsets in the workspace
+};
+
+struct Layout2 {
+  std::vector<Region> reg;
+  size_t partials, cases, k64, k32, ids, prefix, iota, single, total;
+};
+
+Layout2 layout(const cplb_params* prm, int n) {
+  Layout2 L;
+  L.reg.resize(n);
+  size_t off = 0;
+  for (int c = 0; c < n; ++c) {
+    const Geometry G = geometry(&prm[c]);
+    L.reg[c].lat = off;
+    off += 2 * G.lat_bytes;
+    L.reg[c].hist = off;
+    off += G.hist_bytes;
+    L.reg[c].fields = off;
+    off += G.field_bytes;
+  }
+  L.partials = off;
+  off += align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
+  L.cases = off;
+  off += align_up((size_t)n * sizeof(BatchCase), kAlign);
+  L.k64 = off;
+  off += align_up((size_t)n * sizeof(KParams<double>), kAlign);
+  L.k32 = off;
+  off += align_up((size_t)n * sizeof(KParams<float>), kAlign);
+  L.ids = off;
+  off += align_up((size_t)n * sizeof(int), kAlign);
+  L.prefix = off;
+  off += align_up((size_t)kBatchClasses * kVariants2D * (n + 1) * sizeof(int), kAlign);
+  L.iota = off;
+  off += align_up((size_t)n * sizeof(int), kAlign);
+  L.single = off;
+  off += align_up((size_t)2 * n * sizeof(int), kAlign);
+  L.total = off;
+  return L;
+}
+
+int validate_batch(const cplb_params* prm, int n, char* err, size_t errn) {
+  if (!prm || n < 1) {
+    snprintf(err, errn, "a batch needs at least one case");
+    return CPLB_EINVAL;
+  }
+  for (int c = 0; c < n; ++c) {
+    char e[256];
+    const int rc = validate(&prm[c], e, sizeof(e));
+    if (rc) {
+      snprintf(err, errn, "case %d: %s", c, e);
+      return rc;
+    }
+    if (prm[c].lattice != CPLB_D2Q9) {
+      snprintf(err, errn, "case %d: batches hold D2Q9 lattices only", c);
+      return CPLB_EINVAL;
+    }
+    if (prm[c].precision != prm[0].precision) {
+      snprintf(err, errn, "case %d: every case needs the precision of case 0", c);
+      return CPLB_EINVAL;
+    }
+    const Geometry G = geometry(&prm[c]);
+    if (!fits_u32_planes(G)) {
+      snprintf(err, errn, "case %d: lattice too large for a batch (sets over 4 GiB)", c);
+      return CPLB_EINVAL;
+    }
+  }
+  return CPLB_OK;
+}
+
+}  // namespace
+
+struct cplb_batch {
+  int n;
+  int precision;
+  std::vector<cplb_params> prm;
+  std::vector<Geometry> G;
+  std::vector<KParams<double>> k64;
+  std::vector<KParams<float>> k32;
+  std::vector<BatchCase> cases;  // host copy of the device table
+  std::vector<int> ids;          // case ids grouped by class
+  std::vector<int> prefix;       // [class][variant][n + 1]
+  std::vector<int> iota;         // 0, 1, ..., n - 1: one case as its own work list
+  std::vector<int> single;       // per case {0, tiles of the read-out shape}
+  std::vector<int> case_cls;
+  int cls_first[kBatchClasses], cls_count[kBatchClasses];
+  int total[kBatchClasses][kVariants2D];
+  int variant[kBatchClasses];
+  hipStream_t stream;
+  char* ws;
+  double* partials;
+  BatchCase* d_cases;
+  KParams<double>* d_k64;
+  KParams<float>* d_k32;
+  int* d_ids;
+  int* d_prefix;
+  int* d_iota;
+  int* d_single;
+  int cur;
+  int64_t step;
+  char err[512];
+};
+
+namespace {
+
+__attribute__((format(printf, 3, 4))) int set_err(cplb_batch_t* b, int code, const char* fmt,
+                                                   ...) {
+  if (b) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(b->err, sizeof(b->err), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+int hip_check(cplb_batch_t* b, hipError_t e, const char* where) {
+  if (e == hipSuccess) return CPLB_OK;
+  if (b) snprintf(b->err, sizeof(b->err), "%s: %s", where, hipGetErrorString(e));
+  return CPLB_EHIP;
+}
+
+size_t prefix_at(const cplb_batch_t* b, int cls, int v) {
+  return ((size_t)cls * kVariants2D + v) * (b->n + 1);
+}
+
+template <class S, class T>
+hipError_t launch_class(cplb_batch_t* b, int cls, int mode, int v, const KParams<T>* kdev) {
+  if (b->cls_count[cls] == 0) return hipSuccess;
+  const int pv = mode == kModeMacros ? 0 : v;  // the read-out uses the first tile shape
+  return launch_batch2d<S, T>(b->d_cases, b->d_ids + b->cls_first[cls],
+                              b->d_prefix + prefix_at(b, cls, pv), b->cls_count[cls],
+                              b->total[cls][pv], kdev, b->cur, mode, v, b->stream);
+}
+
+hipError_t run_class(cplb_batch_t* b, int cls, int mode, int v) {
+  switch (b->precision) {
+    case CPLB_F64: return launch_class<double, double>(b, cls, mode, v, b->d_k64);
+    case CPLB_F32: return launch_class<float, float>(b, cls, mode, v, b->d_k32);
+    case CPLB_F32_S16F: return launch_class<__half, float>(b, cls, mode, v, b->d_k32);
+    default: return launch_class<__hip_bfloat16, float>(b, cls, mode, v, b->d_k32);
+  }
+}
+
+// The field planes of one case, recomputed from its current populations on
+// every read-out (a captured graph may have advanced the state unseen): the
+// batched kernel in read-out mode over that case alone.
+int compute_fields(cplb_batch_t* b, int icase) {
+  hipError_t e;
+  const int* ids = b->d_iota + icase;
+  const int* pre = b->d_single + 2 * icase;
+  const int tiles = step2d_tiles(b->prm[icase].nx, b->prm[icase].ny, 0);
+  switch (b->precision) {
+    case CPLB_F64:
+      e = launch_batch2d<double, double>(b->d_cases, ids, pre, 1, tiles, b->d_k64, b->cur,
+                                         kModeMacros, 0, b->stream);
+      break;
+    case CPLB_F32:
+      e = launch_batch2d<float, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+                                       kModeMacros, 0, b->stream);
+      break;
+    case CPLB_F32_S16F:
+      e = launch_batch2d<__half, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+                                        kModeMacros, 0, b->stream);
+      break;
+    default:
+      e = launch_batch2d<__hip_bfloat16, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+                                                kModeMacros, 0, b->stream);
+  }
+  return hip_check(b, e, "batch macros kernel");
+}
+
+bool valid_case(const cplb_batch_t* b, int icase) { return b && icase >= 0 && icase < b->n; }
+
+// copy the history planes of every case of a class to (dir 0) or from
+// (dir 1) that case's field planes
+int park_history(cplb_batch_t* b, int cls, int dir) {
+  for (int k = 0; k < b->cls_count[cls]; ++k) {
+    const int c = b->ids[b->cls_first[cls] + k];
+    const Geometry& G = b->G[c];
+    const size_t hb = (size_t)G.nhist * G.stride * G.s_cmp;
+    void* h = b->cases[c].hist;
+    void* f = b->cases[c].fields;
+    int rc = hip_check(b, hipMemcpyAsync(dir ? h : f, dir ? f : h, hb, hipMemcpyDeviceToDevice,
+                                         b->stream), "tune: park history");
+    if (rc) return rc;
+  }
+  return CPLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cplb_batch_workspace_bytes(const cplb_params* prm, int ncases, size_t* bytes) {
+  char err[512];
+  if (!bytes) return CPLB_EINVAL;
+  const int rc = validate_batch(prm, ncases, err, sizeof(err));
+  if (rc) return rc;
+  *bytes = layout(prm, ncases).total;
+  return CPLB_OK;
+}
+
+int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, size_t bytes,
+                      void* hip_stream, cplb_batch_t** out) {
+  if (!out) return CPLB_EINVAL;
+  *out = nullptr;
+  char err[512];
+  int rc = validate_batch(prm, ncases, err, sizeof(err));
+  if (rc) return rc;
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign)) return CPLB_EINVAL;
+  const Layout2 L = layout(prm, ncases);
+  if (bytes < L.total) return CPLB_ENOMEM;
+  cplb_batch_t* b = new (std::nothrow) cplb_batch_t();
+  if (!b) return CPLB_ENOMEM;
+  b->n = ncases;
+  b->precision = prm[0].precision;
+  b->stream = (hipStream_t)hip_stream;
+  b->ws = (char*)dev_workspace;
+  b->err[0] = 0;
+  b->prm.assign(prm, prm + ncases);
+  b->G.resize(ncases);
+  b->k64.resize(ncases);
+  b->k32.resize(ncases);
+  b->cases.resize(ncases);
+  b->case_cls.resize(ncases);
+  for (int c = 0; c < ncases; ++c) {
+    const Geometry G = geometry(&prm[c]);
+    b->G[c] = G;
+    b->k64[c] = make_kparams<double>(&prm[c], G);
+    b->k32[c] = make_kparams<float>(&prm[c], G);
+    BatchCase& D = b->cases[c];
+    D.lat[0] = b->ws + L.reg[c].lat;
+    D.lat[1] = b->ws + L.reg[c].lat + G.lat_bytes;
+    D.hist = b->ws + L.reg[c].hist;
+    D.fields = b->ws + L.reg[c].fields;
+    D.nx = prm[c].nx;
+    D.ny = prm[c].ny;
+    D.wall_x = prm[c].periodic[0] ? 0 : 1;
+    D.wall_y = prm[c].periodic[1] ? 0 : 1;
+    D.sS = (unsigned)(G.stride * G.s_pop);
+    D.sT = (unsigned)(G.stride * G.s_cmp);
+    b->case_cls[c] = class_of(prm[c].nx);
+  }
+  // cases grouped by class, and every class's tile prefix for every variant
+  b->ids.clear();
+  b->prefix.assign((size_t)kBatchClasses * kVariants2D * (ncases + 1), 0);
+  for (int cls = 0; cls < kBatchClasses; ++cls) {
+    b->cls_first[cls] = (int)b->ids.size();
+    for (int c = 0; c < ncases; ++c)
+      if (b->case_cls[c] == cls) b->ids.push_back(c);
+    b->cls_count[cls] = (int)b->ids.size() - b->cls_first[cls];
+    b->variant[cls] = kClassDefaultVariant[cls];
+    for (int v = 0; v < kVariants2D; ++v) {
+      int* p = &b->prefix[prefix_at(b, cls, v)];
+      long long acc = 0;
+      for (int k = 0; k < b->cls_count[cls]; ++k) {
+        p[k] = (int)acc;
+        const int c = b->ids[b->cls_first[cls] + k];
+        acc += step2d_tiles(prm[c].nx, prm[c].ny, v);
+      }
+      if (acc > (1ll << 30)) {
+        delete b;
+        return CPLB_EINVAL;
+      }
+      p[b->cls_count[cls]] = (int)acc;
+      b->total[cls][v] = (int)acc;
+    }
+  }
+  b->iota.resize(ncases);
+  b->single.resize(2 * (size_t)ncases);
+  for (int c = 0; c < ncases; ++c) {
+    b->iota[c] = c;
+    b->single[2 * c] = 0;
+    b->single[2 * c + 1] = step2d_tiles(prm[c].nx, prm[c].ny, 0);
+  }
+  b->partials = (double*)(b->ws + L.partials);
+  b->d_cases = (BatchCase*)(b->ws + L.cases);
+  b->d_k64 = (KParams<double>*)(b->ws + L.k64);
+  b->d_k32 = (KParams<float>*)(b->ws + L.k32);
+  b->d_ids = (int*)(b->ws + L.ids);
+  b->d_prefix = (int*)(b->ws + L.prefix);
+  b->d_iota = (int*)(b->ws + L.iota);
+  b->d_single = (int*)(b->ws + L.single);
+  b->cur = 0;
+  b->step = 0;
+  struct Up {
+    void* dst;
+    const void* src;
+    size_t n;
+  } ups[] = {{b->d_cases, b->cases.data(), ncases * sizeof(BatchCase)},
+             {b->d_k64, b->k64.data(), ncases * sizeof(KParams<double>)},
+             {b->d_k32, b->k32.data(), ncases * sizeof(KParams<float>)},
+             {b->d_ids, b->ids.data(), ncases * sizeof(int)},
+             {b->d_prefix, b->prefix.data(), b->prefix.size() * sizeof(int)},
+             {b->d_iota, b->iota.data(), ncases * sizeof(int)},
+             {b->d_single, b->single.data(), 2 * (size_t)ncases * sizeof(int)}};
+  for (const Up& u : ups) {
+    rc = hip_check(b, hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, b->stream),
+                   "upload of batch tables");
+    if (rc) break;
+  }
+  if (!rc) rc = hip_check(b, hipStreamSynchronize(b->stream), "upload of batch tables");
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CPLB_OK;
+}
+
+void cplb_batch_destroy(cplb_batch_t* b) { delete b; }
+
+int cplb_batch_num_cases(const cplb_batch_t* b) { return b ? b->n : 0; }
+
+int64_t cplb_batch_step_count(const cplb_batch_t* b) { return b ? b->step : -1; }
+
+int cplb_batch_init_sdf(cplb_batch_t* b, int icase, const double* l, double c1_a, double c1_b,
+                        double c2_a, double c2_b) {
+  if (!b) return CPLB_EINVAL;
+  if (!valid_case(b, icase)) return set_err(b, CPLB_EINVAL, "no case %d in this batch", icase);
+  if (!l) return set_err(b, CPLB_EINVAL, "signed distance array is required");
+  const Geometry& G = b->G[icase];
+  BatchCase& D = b->cases[icase];
+  // stage the FP64 host array in the idle lattice of the case
+  double* stage = (double*)D.lat[b->cur ^ 1];
+  const size_t nb = (size_t)G.n * sizeof(double);
+  int rc = hip_check(b, hipMemcpyAsync(stage, l, nb, hipMemcpyHostToDevice, b->stream),
+                     "copy of the signed distance");
+  if (rc) return rc;
+  const double cab[4] = {c1_a, c1_b, c2_a, c2_b};
+  const double W = b->prm[icase].W;
+  void* lat = (void*)D.lat[b->cur];
+  hipError_t e;
+  switch (b->precision) {
+    case CPLB_F64:
+      e = launch_init<double, double>(2, (double*)lat, (double*)D.hist, stage, nullptr, nullptr,
+                                      nullptr, nullptr, 1, W, cab, b->k64[icase], b->stream);
+      break;
+    case CPLB_F32:
+      e = launch_init<float, float>(2, (float*)lat, (float*)D.hist, stage, nullptr, nullptr, nullptr,
+                                    nullptr, 1, W, cab, b->k32[icase], b->stream);
+      break;
+    case CPLB_F32_S16F:
+      e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist, stage, nullptr, nullptr,
+                                     nullptr, nullptr, 1, W, cab, b->k32[icase], b->stream);
+      break;
+    default:
+      e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist, stage, nullptr,
+                                             nullptr, nullptr, nullptr, 1, W, cab, b->k32[icase],
+                                             b->stream);
+  }
+  rc = hip_check(b, e, "init kernel");
+  if (rc) return rc;
+  rc = hip_check(b, hipStreamSynchronize(b->stream), "init synchronise");
+  if (rc) return rc;
+  return CPLB_OK;
+}
+
+int cplb_batch_step(cplb_batch_t* b, int64_t nsteps) {
+  if (!b) return CPLB_EINVAL;
+  if (nsteps < 0) return set_err(b, CPLB_EINVAL, "nsteps must be >= 0");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    for (int cls = 0; cls < kBatchClasses; ++cls) {
+      const int rc = hip_check(b, run_class(b, cls, kModeStep, b->variant[cls]), "batch step kernel");
+      if (rc) return rc;
+    }
+    b->cur ^= 1;
+    b->step++;
+  }
+  return CPLB_OK;
+}
+
+int cplb_batch_read_field(cplb_batch_t* b, int icase, int field, void* dev_dst, int dtype) {
+  if (!b) return CPLB_EINVAL;
+  if (!valid_case(b, icase)) return set_err(b, CPLB_EINVAL, "no case %d in this batch", icase);
+  if (field < 0 || field >= CPLB_NFIELDS) return set_err(b, CPLB_EINVAL, "unknown field id");
+  if (dtype != CPLB_DTYPE_F32 && dtype != CPLB_DTYPE_F64)
+    return set_err(b, CPLB_EINVAL, "unknown destination dtype");
+  if (!dev_dst) return set_err(b, CPLB_EINVAL, "null destination");
+  int rc = compute_fields(b, icase);
+  if (rc) return rc;
+  const Geometry& G = b->G[icase];
+  const char* f = (const char*)b->cases[icase].fields + (size_t)field * G.stride * G.s_cmp;
+  hipError_t e = G.s_cmp == 8
+                     ? launch_convert<double>((const double*)f, dev_dst, dtype, G.n, b->stream)
+                     : launch_convert<float>((const float*)f, dev_dst, dtype, G.n, b->stream);
+  return hip_check(b, e, "field conversion");
+}
+
+int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]) {
+  if (!b || !out) return CPLB_EINVAL;
+  if (!valid_case(b, icase)) return set_err(b, CPLB_EINVAL, "no case %d in this batch", icase);
+  int rc = compute_fields(b, icase);
+  if (rc) return rc;
+  const Geometry& G = b->G[icase];
+  double* dout = b->partials + 8 * kReduceBlocks;
+  const int nparts = G.n < (long long)kReduceBlocks * 256 ? (int)((G.n + 255) / 256) : kReduceBlocks;
+  const cplb_params& p = b->prm[icase];
+  hipError_t e = G.s_cmp == 8
+                     ? launch_reduce<double>((const double*)b->cases[icase].fields, G.stride, G.n,
+                                             p.rho1, p.rho2, b->partials, nparts, dout, b->stream)
+                     : launch_reduce<float>((const float*)b->cases[icase].fields, G.stride, G.n,
+                                            p.rho1, p.rho2, b->partials, nparts, dout, b->stream);
+  rc = hip_check(b, e, "reduction kernels");
+  if (rc) return rc;
+  double tmp[8];
+  rc = hip_check(b, hipMemcpyAsync(tmp, dout, 7 * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+                 "reduction copy");
+  if (rc) return rc;
+  rc = hip_check(b, hipStreamSynchronize(b->stream), "reduction synchronise");
+  if (rc) return rc;
+  for (int k = 0; k < 7; ++k) out[k] = tmp[k];
+  out[7] = (double)b->step;
+  if (out[6] > 0) return set_err(b, CPLB_EUNSTABLE, "non-finite values in case %d", icase);
+  return CPLB_OK;
+}
+
+int cplb_batch_num_classes(const cplb_batch_t* b) { return b ? kBatchClasses : 0; }
+
+int cplb_batch_case_class(const cplb_batch_t* b, int icase) {
+  return valid_case(b, icase) ? b->case_cls[icase] : -1;
+}
+
+int cplb_batch_class_cases(const cplb_batch_t* b, int cls) {
+  return b && cls >= 0 && cls < kBatchClasses ? b->cls_count[cls] : -1;
+}
+
+int cplb_batch_get_variant(const cplb_batch_t* b, int cls) {
+  return b && cls >= 0 && cls < kBatchClasses ? b->variant[cls] : -1;
+}
+
+int cplb_batch_set_variant(cplb_batch_t* b, int cls, int v) {
+  if (!b) return CPLB_EINVAL;
+  if (cls < 0 || cls >= kBatchClasses) return set_err(b, CPLB_EINVAL, "no size class %d", cls);
+  if (v < 0 || v >= kVariants2D) return set_err(b, CPLB_EINVAL, "no such kernel variant %d", v);
+  b->variant[cls] = v;
+  return CPLB_OK;
+}
+
+int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
+  if (!b) return CPLB_EINVAL;
+  if (probe_steps < 1) return set_err(b, CPLB_EINVAL, "probe_steps must be >= 1");
+  // Per class: the probes read the current lattices and write the idle
+  // ones (scratch), and overwrite the histories, which are parked in the
+  // field planes and put back.
+  hipEvent_t e0, e1;
+  int rc = hip_check(b, hipEventCreate(&e0), "tune: event");
+  if (rc) return rc;
+  rc = hip_check(b, hipEventCreate(&e1), "tune: event");
+  if (rc) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  double total_ms = 0;
+  for (int cls = 0; cls < kBatchClasses && rc == CPLB_OK; ++cls) {
+    if (b->cls_count[cls] == 0) continue;
+    rc = park_history(b, cls, 0);
+    if (rc) break;
+    const int keep = b->variant[cls];
+    int best = keep;
+    float best_ms = 0;
+    for (int v = 0; v < kVariants2D && rc == CPLB_OK; ++v) {
+      rc = hip_check(b, run_class(b, cls, kModeStep, v), "tune: warm-up");
+      if (rc) break;
+      rc = hip_check(b, hipEventRecord(e0, b->stream), "tune: record");
+      for (int k = 0; k < probe_steps && rc == CPLB_OK; ++k)
+        rc = hip_check(b, run_class(b, cls, kModeStep, v), "tune: probe");
+      if (rc) break;
+      rc = hip_check(b, hipEventRecord(e1, b->stream), "tune: record");
+      if (!rc) rc = hip_check(b, hipEventSynchronize(e1), "tune: wait");
+      float ms = 0;
+      if (!rc) rc = hip_check(b, hipEventElapsedTime(&ms, e0, e1), "tune: time");
+      if (rc) break;
+      if (v == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    b->variant[cls] = rc == CPLB_OK ? best : keep;
+    total_ms += best_ms;
+    const int rc2 = park_history(b, cls, 1);
+    if (!rc) rc = rc2;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int rc3 = hip_check(b, hipStreamSynchronize(b->stream), "tune: synchronise");
+  if (rc) return rc;
+  if (rc3) return rc3;
+  if (ms_per_step) *ms_per_step = total_ms / probe_steps;
+  return CPLB_OK;
+}
+
+const char* cplb_batch_last_error(const cplb_batch_t* b) { return b ? b->err : "null batch"; }
+
+}  // extern "C"

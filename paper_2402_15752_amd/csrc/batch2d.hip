@@ -1,0 +1,102 @@
+// Batched 2-D step: many independent D2Q9 lattices of different sizes and
+// parameters advanced by one launch per size class.
+//
+// The work list of a launch is the concatenation of the tile lists of the
+// class's cases.  A work-group takes global tile g (dealt XCD-aware, as in
+// the single-lattice kernel), finds its case by a binary search over the
+// class's tile prefix (scalar loads: every lane of the group agrees), reads
+// that case's geometry and lattice constants from device tables, and runs
+// the same tile body as the single-lattice kernel -- so each case of a
+// batch is bit-identical to the same case run alone.
+#include "step2d_tile.hpp"
+
+namespace pflb {
+
+namespace {
+
+template <class X>
+using CPtr = const __attribute__((address_space(4))) X*;
+
+template <class S, class T, int TX, int TY, bool NTS, int MODE>
+__global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, CPtr<int> ids,
+                                                         CPtr<int> prefix, int ncls, int total,
+                                                         KPtr<T> kps, int parity) {
+  const int per = (total + 7) / 8;
+  const int g = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (g >= total) return;
+  // last k with prefix[k] <= g
+  int lo = 0, hi = ncls;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  const int c = ids[lo];
+  CPtr<BatchCase> D = cases + c;
+  Geo2<uint32_t> G;
+  G.nx = D->nx;
+  G.ny = D->ny;
+  G.wall_x = D->wall_x;
+  G.wall_y = D->wall_y;
+  G.tiles_x = (G.nx + TX - 1) / TX;
+  G.ntiles = G.tiles_x * ((G.ny + TY - 1) / TY);
+  G.sS = D->sS;
+  G.sT = D->sT;
+  const S* src = (const S*)D->lat[parity];
+  S* dst = (S*)D->lat[parity ^ 1];
+  const KParams<T>& P = *(const KParams<T>*)(kps + c);
+  step2d_tile<S, T, TX, TY, NTS, MODE, uint32_t>(src, dst, (T*)D->hist, (T*)D->fields, P, G,
+                                                 g - prefix[lo]);
+}
+
+template <class S, class T, int TX, int TY, bool NTS, int MODE>
+hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, int ncls, int total,
+                    const KParams<T>* kps, int parity, hipStream_t stream) {
+  const int nblocks = ((total + 7) / 8) * 8;
+  hipLaunchKernelGGL((batch2d_kernel<S, T, TX, TY, NTS, MODE>), dim3(nblocks), dim3(TX * TY), 0,
+                     stream, (CPtr<BatchCase>)cases, (CPtr<int>)ids, (CPtr<int>)prefix, ncls, total,
+                     (KPtr<T>)kps, parity);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// tile shapes of the 2-D variants (the same table as the single-lattice step)
+int step2d_tiles(int nx, int ny, int variant) {
+  static const int tx[kVariants2D] = {64, 32, 32, 128, 64, 32, 32, 128};
+  static const int ty[kVariants2D] = {4, 8, 4, 4, 4, 8, 4, 4};
+  if (variant < 0 || variant >= kVariants2D) variant = 0;
+  return ((nx + tx[variant] - 1) / tx[variant]) * ((ny + ty[variant] - 1) / ty[variant]);
+}
+
+template <class S, class T>
+hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
+                          int total, const KParams<T>* kps, int parity, int mode, int variant,
+                          hipStream_t stream) {
+  if (total <= 0) return hipSuccess;
+  constexpr int M = kModeStep;
+  if (mode == kModeMacros)
+    return launch_b<S, T, 64, 4, false, kModeMacros>(cases, ids, prefix, ncls, total, kps, parity,
+                                                     stream);
+  switch (variant) {
+    case 1: return launch_b<S, T, 32, 8, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 2: return launch_b<S, T, 32, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 3: return launch_b<S, T, 128, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 4: return launch_b<S, T, 64, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 5: return launch_b<S, T, 32, 8, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 6: return launch_b<S, T, 32, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 7: return launch_b<S, T, 128, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    default: return launch_b<S, T, 64, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+  }
+}
+
+#define PFLB_BATCH_INST(S, T)                                                                    \
+  template hipError_t launch_batch2d<S, T>(const BatchCase*, const int*, const int*, int, int,   \
+                                           const KParams<T>*, int, int, int, hipStream_t);
+PFLB_BATCH_INST(double, double)
+PFLB_BATCH_INST(float, float)
+PFLB_BATCH_INST(__half, float)
+PFLB_BATCH_INST(__hip_bfloat16, float)
+#undef PFLB_BATCH_INST
+
+}  // namespace pflb

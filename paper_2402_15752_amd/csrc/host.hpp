@@ -1,0 +1,137 @@
+// Host-side helpers shared by the single-lattice and the batched C-ABI:
+// parameter validation, workspace geometry and the lattice constants.
+#pragma once
+
+#include <cmath>
+#include <cstdio>
+
+#include "../../include/cplb.h"
+#include "kernels.hpp"
+
+namespace pflb {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Geometry {
+  int dim, qtot, nhist;
+  long long n;       // nodes
+  long long stride;  // elements per plane
+  size_t s_pop, s_cmp;
+  size_t lat_bytes, hist_bytes, field_bytes, part_bytes, kp_bytes, total;
+};
+
+inline int validate(const cplb_params* p, char* err, size_t errn) {
+  auto fail = [&](const char* m) {
+    snprintf(err, errn, "%s", m);
+    return CPLB_EINVAL;
+  };
+  if (!p) return fail("null parameters");
+  if (p->lattice != CPLB_D2Q9 && p->lattice != CPLB_D3Q19_D3Q7) return fail("unknown lattice");
+  if (p->precision < CPLB_F64 || p->precision > CPLB_F32_S16B) return fail("unknown precision");
+  if (p->visc_law != CPLB_VISC_LINEAR && p->visc_law != CPLB_VISC_EXP)
+    return fail("unknown viscosity law");
+  if (p->reserved != 0) return fail("reserved field must be 0");
+  const int d = p->lattice == CPLB_D2Q9 ? 2 : 3;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
+  if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
+  const int n3[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < d; ++a)
+    if (!p->periodic[a] && n3[a] < 2) return fail("a walled axis needs at least 2 nodes");
+  if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail("grid too large (> 2e9 nodes)");
+  if (!(p->rho1 > 0 && p->rho2 > 0 && p->mu1 > 0 && p->mu2 > 0))
+    return fail("densities and viscosities must be positive");
+  if (!(p->W > 0 && p->M > 0 && p->D1 > 0 && p->D2 > 0 && p->Keq > 0 && p->n_eps > 0))
+    return fail("W, M, D1, D2, Keq, n_eps must be positive (every tau > 1/2)");
+  if (!(p->sigma >= 0 && p->A >= 0)) return fail("sigma and A must be >= 0");
+  if (d == 2 && p->g[2] != 0.0) return fail("2-D lattice: g[2] must be 0");
+  if (p->ref[1] != 0.0) return fail("ref[1] (flow set) must be 0");
+  const double all[] = {p->rho1, p->rho2, p->mu1,  p->mu2,  p->sigma, p->W,    p->M,
+                        p->D1,   p->D2,   p->Keq,  p->A,    p->g[0],  p->g[1], p->g[2],
+                        p->rho_ref, p->n_eps, p->ref[0], p->ref[1], p->ref[2], p->ref[3]};
+  for (double v : all)
+    if (!std::isfinite(v)) return fail("non-finite parameter");
+  return CPLB_OK;
+}
+
+inline Geometry geometry(const cplb_params* p) {
+  Geometry G{};
+  G.dim = p->lattice == CPLB_D2Q9 ? 2 : 3;
+  G.qtot = G.dim == 2 ? Layout<D2Q9, D2Q9>::QTOT : Layout<D3Q7, D3Q19>::QTOT;
+  G.nhist = G.dim == 2 ? kHist2D : kHist3D;
+  G.n = (long long)p->nx * p->ny * p->nz;
+  // planes padded to 64 elements plus one 64-element skew, so that the
+  // same node of successive planes does not land on the same HBM channel
+  G.stride = (G.n + 63) / 64 * 64 + 64;
+  switch (p->precision) {
+    case CPLB_F64: G.s_pop = 8; G.s_cmp = 8; break;
+    case CPLB_F32: G.s_pop = 4; G.s_cmp = 4; break;
+    default: G.s_pop = 2; G.s_cmp = 4; break;
+  }
+  G.lat_bytes = align_up((size_t)G.qtot * G.stride * G.s_pop, kAlign);
+  G.hist_bytes = align_up((size_t)G.nhist * G.stride * G.s_cmp, kAlign);
+  G.field_bytes = align_up((size_t)kNumFields * G.stride * G.s_cmp, kAlign);
+  G.part_bytes = align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
+  G.kp_bytes = align_up(sizeof(KParams<double>), kAlign) + align_up(sizeof(KParams<float>), kAlign);
+  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes + G.kp_bytes;
+  return G;
+}
+
+// every 2-D set (9 planes), the history and the field buffer below 4 GiB:
+// 32-bit byte offsets reach every value
+inline bool fits_u32_planes(const Geometry& G) {
+  const unsigned long long lim = 1ull << 32;
+  return 9ull * G.stride * G.s_pop < lim &&
+         (unsigned long long)kNumFields * G.stride * G.s_cmp < lim;
+}
+
+template <class T>
+KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
+  KParams<T> K{};
+  K.nx = p->nx;
+  K.ny = p->ny;
+  K.nz = p->nz;
+  for (int a = 0; a < 3; ++a) K.wall[a] = (a < G.dim && !p->periodic[a]) ? 1 : 0;
+  K.stride = G.stride;
+  const double csf = G.dim == 2 ? D2Q9::cs2 : D3Q7::cs2;
+  // relaxation times from the transport coefficients (Sec. III)
+  const double tau_f = 0.5 + p->M / csf;
+  const double tau_h1 = 0.5 + p->D1 / csf;
+  const double tau_h2 = 0.5 + p->D2 / csf;
+  // delta = 2 - 1/tau = 2 (tau - 1/2) / tau, formed from tau - 1/2 directly
+  K.del_f = T(2.0 * (p->M / csf) / tau_f);
+  K.hdel_f = T((p->M / csf) / tau_f);
+  K.del_h1 = T(2.0 * (p->D1 / csf) / tau_h1);
+  K.hdel_h1 = T((p->D1 / csf) / tau_h1);
+  K.del_h2 = T(2.0 * (p->D2 / csf) / tau_h2);
+  K.hdel_h2 = T((p->D2 / csf) / tau_h2);
+  // beta = 12 sigma / W, k = 3 sigma W / 2 (Sec. II B)
+  K.beta4 = T(4.0 * 12.0 * p->sigma / p->W);
+  K.kappa = T(1.5 * p->sigma * p->W);
+  K.rho1 = T(p->rho1);
+  K.rho2 = T(p->rho2);
+  K.drho = T(p->rho1 - p->rho2);
+  K.rho_ref = T(p->rho_ref);
+  for (int a = 0; a < 3; ++a) K.grav[a] = T(p->g[a]);
+  K.mu1 = T(p->mu1);
+  K.mu2 = T(p->mu2);
+  K.ln_mu1 = T(std::log(p->mu1));
+  K.ln_mu2 = T(std::log(p->mu2));
+  K.visc_exp = p->visc_law == CPLB_VISC_EXP;
+  K.D1D2 = T(p->D1 * p->D2);
+  K.KD1 = T(p->Keq * p->D1);
+  K.D2 = T(p->D2);
+  K.Keq = T(p->Keq);
+  K.A = T(p->A);
+  K.half_A = T(0.5 * p->A);
+  K.four_over_W = T(4.0 / p->W);
+  K.neps2 = T(p->n_eps * p->n_eps);
+  // reference state of the stored deviations (f, h1, h2; g is stored as is)
+  K.ref_phi = T(p->ref[0]);
+  K.one_minus_ref_phi = T(1.0 - p->ref[0]);
+  K.ref_c1 = T(p->ref[2]);
+  K.ref_c2 = T(p->ref[3]);
+  return K;
+}
+
+}  // namespace pflb

@@ -35,6 +35,31 @@ template <class S, class T>
 hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream);
 
+// One case of a batch of independent 2-D lattices, as the batched kernel
+// reads it from device memory.
+struct BatchCase {
+  const void* lat[2];  // the two population lattices (parity 0 reads lat[0])
+  void* hist;          // history planes
+  void* fields;        // field planes
+  int nx, ny;
+  int wall_x, wall_y;  // 1: half-way bounce-back walls on both faces
+  unsigned int sS;     // bytes between two population planes
+  unsigned int sT;     // bytes between two history / field planes
+};
+
+// One step (or the field read-out in kModeMacros) of every case of one size
+// class in a single launch: ids[0..ncls) are the class's case ids and
+// prefix[0..ncls] the first tile of each in the class's tile list for
+// `variant` (prefix[ncls] = total tiles); kps[c] are the constants of case
+// c.  The tile shapes are those of the 2-D step variants.
+template <class S, class T>
+hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
+                          int total_tiles, const KParams<T>* kps, int parity, int mode,
+                          int variant, hipStream_t stream);
+
+// tiles of an nx x ny lattice for a 2-D step variant
+int step2d_tiles(int nx, int ny, int variant);
+
 // equilibrium initialisation from FP64 staging arrays in device memory:
 // phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,
 // each N values; u / p may be null.

@@ -17,8 +17,7 @@
 //
 // Variants (tile shape, non-temporal population traffic) are template
 // parameters; the host picks one per lattice (cplb_tune times them all).
-#include "addr.hpp"
-#include "kernels.hpp"
+#include "step2d_tile.hpp"
 
 namespace pflb {
 
@@ -27,167 +26,19 @@ namespace {
 using L = D2Q9;
 using Lay = Layout<D2Q9, D2Q9>;
 
-template <class Off>
-struct Geo2 {
-  int nx, ny;
-  int wall_x, wall_y;
-  int tiles_x, ntiles;
-  Off sS;  // bytes between two population planes
-  Off sT;  // bytes between two history / field planes
-};
-
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
 __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
                                                         T* __restrict__ fields, KParams<T> P,
                                                         Geo2<Off> G) {
-  constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
-  static_assert(NHALO <= NT, "one halo node per thread at most");
-  constexpr Off BS = sizeof(S);
-  __shared__ T sphi[LY][LX];
-  __shared__ T spsi[LY][LX];
-
   // XCD-aware tile order: work-groups are dealt round-robin to the 8 XCDs
   // (group b runs on XCD b % 8), so XCD k gets the contiguous tile run
-  // [k*per, (k+1)*per).  Groups past the last tile exit before any barrier.
+  // [k*per, (k+1)*per) and tiles that share halo rows share an L2.  Groups
+  // past the last tile exit before any barrier.
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= G.ntiles) return;
-  const int x0 = (tile % G.tiles_x) * TX;
-  const int y0 = (tile / G.tiles_x) * TY;
-
-  const S* __restrict__ sF = at(src, (size_t)Lay::F0 * G.sS);
-  const S* __restrict__ sG = at(src, (size_t)Lay::G0 * G.sS);
-  const S* __restrict__ sH1 = at(src, (size_t)Lay::H10 * G.sS);
-  const S* __restrict__ sH2 = at(src, (size_t)Lay::H20 * G.sS);
-
-  const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int nx = G.nx, ny = G.ny;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool active = x < nx && y < ny;
-  // a ragged tile: the slot one past the last node is read by that node's
-  // stencil, so its thread fills it with the wrapped or mirrored node
-  const bool own_slot = x <= nx && y <= ny;
-  const Off node = Off(fold(y, ny, G.wall_y) * nx + fold(x, nx, G.wall_x)) * BS;
-  const Off nodeT = node * Off(sizeof(T) / sizeof(S));  // bytes, history / fields
-
-  int hx = 0, hy = 0;
-  bool halo = false;
-  Off halo_node = 0;
-  if (tid < NHALO) {
-    halo_pos<TX, TY>(tid, hx, hy);
-    const int gx = x0 + hx, gy = y0 + hy;
-    halo = gx <= nx && gy <= ny;  // beyond a ragged tile no node reads it
-    halo_node = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
-  }
-
-  // ---- 1. all global loads first
-  T f[9], h1[9], h2[9], g[9], hf[9], hh1[9], hh2[9];
-  T hs[kHist2D];
-  if (own_slot) {
-    load_q<L, NTS, false>(sF, G.sS, node, f);
-    load_q<L, NTS, false>(sH1, G.sS, node, h1);
-    load_q<L, NTS, false>(sH2, G.sS, node, h2);
-  }
-  if (active) {
-    load_q<L, NTS, false>(sG, G.sS, node, g);
-#pragma unroll
-    for (int k = 0; k < kHist2D; ++k) hs[k] = *at(hist, plane<false>(k, G.sT) + nodeT);
-  }
-  if (halo) {
-    load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
-    load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
-    load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
-  }
-
-  // ---- 2. moments to LDS (deviations: the stencils only take differences
-  //         and zero-sum weighted sums)
-  Node<T> s{};
-  if (own_slot) {
-    moments<L>(P, f, h1, h2, s);
-    sphi[ty + 1][tx + 1] = s.dphi;
-    spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
-  }
-  if (halo) {
-    Node<T> q;
-    moments<L>(P, hf, hh1, hh2, q);
-    sphi[hy + 1][hx + 1] = q.dphi;
-    spsi[hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
-  }
-  __syncthreads();
-  if (!active) return;
-
-  // ---- 3. isotropic central stencils (Sec. III C) on D2Q9 weights
-  T gphi[3] = {0, 0, 0}, gpsi[3] = {0, 0, 0}, lap = 0;
-#pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const T a = sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
-    const T b = spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
-    const T wc = T(L::w[i] / L::cs2);
-    if (L::cx[i]) {
-      gphi[0] += wc * T(L::cx[i]) * a;
-      gpsi[0] += wc * T(L::cx[i]) * b;
-    }
-    if (L::cy[i]) {
-      gphi[1] += wc * T(L::cy[i]) * a;
-      gpsi[1] += wc * T(L::cy[i]) * b;
-    }
-    lap += T(2) * wc * (a - s.dphi);
-  }
-
-  Flow<T> fl;
-  flow_macros<L>(P, g, s, gphi, lap, fl);
-
-  if (MODE == kModeMacros) {
-    auto put_field = [&](int k, T v) { *at(fields, plane<false>(k, G.sT) + nodeT) = v; };
-    put_field(kFieldPhi, s.phi);
-    put_field(kFieldP, fl.p);
-    put_field(kFieldUx, fl.u[0]);
-    put_field(kFieldUy, fl.u[1]);
-    put_field(kFieldUz, T(0));
-    put_field(kFieldC1, s.c1);
-    put_field(kFieldC2, s.c2);
-    put_field(kFieldMu, fl.mu);
-    put_field(kFieldPsi, s.c1 + P.Keq * s.c2);
-    return;
-  }
-
-  // backward-difference time derivatives against the history (R1)
-  const T dJphi[3] = {s.phi * fl.u[0] - hs[2] * hs[0], s.phi * fl.u[1] - hs[2] * hs[1], T(0)};
-  const T dJ1[3] = {s.c1 * fl.u[0] - hs[3] * hs[0], s.c1 * fl.u[1] - hs[3] * hs[1], T(0)};
-  const T dJ2[3] = {s.c2 * fl.u[0] - hs[4] * hs[0], s.c2 * fl.u[1] - hs[4] * hs[1], T(0)};
-#pragma unroll
-  for (int k = 0; k < kHist2D; ++k) {
-    const T v = k < 2 ? fl.u[k] : (k == 2 ? s.phi : (k == 3 ? s.c1 : s.c2));
-    *at(hist, plane<false>(k, G.sT) + nodeT) = v;
-  }
-
-  // push streaming: X_i(x + c_i) <- X_i*(x), or half-way bounce-back into
-  // the opposite slot of the own node when the link crosses a wall; each
-  // post-collision value is stored as soon as it is formed
-  const PushXY<Off> push(x, y, nx, ny, G.wall_x, G.wall_y, BS);
-  auto target = [&](int i) -> Off {
-    const int cx = L::cx[i], cy = L::cy[i];
-    Off t = node;
-    if (cx) t += cx < 0 ? push.dxm : push.dxp;
-    if (cy) t += cy < 0 ? push.dym : push.dyp;
-    return (push.bits & link_mask(cx, cy, 0)) ? plane<false>(L::opp[i], G.sS) + node
-                                              : plane<false>(i, G.sS) + t;
-  };
-  S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
-  S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
-  S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
-  S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
-  collide<L, L>(
-      P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
-      [&](int i, T v) { st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
-      [&](int i, T v) { st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
-      [&](int i, T a, T b) {
-        const Off t = target(i);
-        st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
-        st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
-      });
+  step2d_tile<S, T, TX, TY, NTS, MODE, Off>(src, dst, hist, fields, P, G, tile);
 }
 
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>

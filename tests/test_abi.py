@@ -89,3 +89,56 @@ def test_create_rejects_bad_workspace(cplb):
     assert lib.cplb_create(ctypes.byref(prm), ctypes.c_void_p(4096), n - 1, None,
                            ctypes.byref(h)) == cplb.CPLB_ENOMEM
     assert lib.cplb_strerror(cplb.CPLB_ENOMEM).decode().startswith("workspace")
+
+
+# ----------------------------------------------------------------- batches
+
+def test_batch_validation_and_workspace(cplb):
+    ps = [W.params(nx=40, ny=30, precision="f32"), W.params(nx=100, ny=64, precision="f32",
+                                                             periodic=(1, 0, 1))]
+    n = cplb.cplb_batch_workspace_bytes(cplb._params_array(ps), 2)
+    single = sum(cplb.cplb_workspace_bytes(cplb.make_params(p)) for p in ps)
+    assert n >= single - 2 * 70000  # per-case regions (the single API adds its own partials)
+    bad_sets = [
+        [W.params(precision="f32"), W.params(precision="f64")],                 # mixed precision
+        [W.params(precision="f32"), W.params(nx=8, ny=8, nz=8, lattice="d3q19_d3q7",
+                                             precision="f32")],                 # not D2Q9
+        [W.params(precision="f32"), W.params(precision="f32", D1=0.0)],         # invalid case
+    ]
+    for ps in bad_sets:
+        with pytest.raises(cplb.CplbError) as e:
+            cplb.cplb_batch_workspace_bytes(cplb._params_array(ps), len(ps))
+        assert e.value.code == cplb.CPLB_EINVAL
+    lib = cplb.library()
+    b = ctypes.c_void_p()
+    arr = cplb._params_array([W.params(precision="f32")])
+    assert lib.cplb_batch_create(arr, 0, ctypes.c_void_p(4096), 1 << 30, None,
+                                 ctypes.byref(b)) == cplb.CPLB_EINVAL
+    assert lib.cplb_batch_create(arr, 1, None, 1 << 30, None, ctypes.byref(b)) == cplb.CPLB_EINVAL
+    assert lib.cplb_batch_create(arr, 1, ctypes.c_void_p(4096), 1024, None,
+                                 ctypes.byref(b)) == cplb.CPLB_ENOMEM
+
+
+def test_batched_sweep_recipe():
+    a, b = W.batched_sweep(64, seed=0), W.batched_sweep(64, seed=0)
+    c = W.batched_sweep(64, seed=1)
+    assert [x["params"] for x in a["cases"]] == [x["params"] for x in b["cases"]]
+    assert [x["params"] for x in a["cases"]] != [x["params"] for x in c["cases"]]
+    full = W.batched_sweep()
+    assert len(full["cases"]) == 512 and full["nodes"] == sum(
+        x["params"]["nx"] * x["params"]["ny"] for x in full["cases"])
+    cs2 = 1.0 / 3.0
+    for x in full["cases"]:
+        p = x["params"]
+        assert 64 <= p["nx"] <= 256 and 64 <= p["ny"] <= 256
+        assert 0.1 <= p["Keq"] <= 10.0
+        for d in (p["D1"], p["D2"]):
+            tau = 0.5 + d / cs2
+            assert 0.5 + 1e-3 - 1e-12 <= tau <= 1.0 + 1e-12
+        assert p["D2"] >= p["D1"]
+        assert x["sdf"].shape == (p["ny"], p["nx"])
+    # every clamp is recorded with the value asked for and the value used
+    for k, name, asked, used in full["clamps"]:
+        assert asked != used and (used == cs2 * 1e-3 or used == cs2 * 0.5)
+    kinds = {x["params"]["periodic"][1] for x in full["cases"]}
+    assert kinds == {0, 1}  # both static (periodic) and rising (walled) cases

@@ -1,0 +1,175 @@
+"""GPU tests of the batch (many independent D2Q9 lattices in one launch per
+size class), through the C-ABI.
+
+The batched kernel runs the single-lattice kernel's tile body on each case,
+so every case must equal the same case run alone bit for bit; two small
+FP64 cases are also compared with the oracle element by element.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+FIELDS2 = ("phi", "c1", "c2", "ux", "uy", "p", "mu")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cplb():
+    import torch
+
+    from paper_2402_15752_amd import cplb as C
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    C.library()
+    return C
+
+
+def mixed_cases(precision, seed=5):
+    """Seven cases across the three size classes: ragged tiles, walls on
+    either axis, different physics per case."""
+    rng = np.random.default_rng(seed)
+    shapes = [(40, 30, (1, 1, 1)), (67, 37, (0, 1, 1)), (130, 9, (1, 0, 1)),
+              (100, 150, (1, 0, 1)), (64, 64, (1, 1, 1)), (97, 70, (0, 0, 1)),
+              (200, 33, (1, 0, 1))]
+    cases = []
+    for nx, ny, per in shapes:
+        p = W.params(nx=nx, ny=ny, periodic=per, precision=precision,
+                     ref_f=W.phase_reference(precision),
+                     sigma=float(rng.uniform(1e-3, 1e-2)), rho1=float(rng.uniform(1, 5)),
+                     rho2=1.0, visc_law="exp", mu1=float(rng.uniform(0.1, 0.5)),
+                     mu2=float(rng.uniform(0.05, 0.1)), D1=float(rng.uniform(0.01, 0.1)),
+                     D2=float(rng.uniform(0.01, 0.1)), Keq=float(rng.uniform(0.2, 5)),
+                     A=float(rng.uniform(0.05, 0.5)),
+                     g=(0.0, float(rng.uniform(-3e-5, 0)), 0.0), rho_ref=1.0)
+        R = min(nx, ny) / 4.0
+        l = W.sdf_sphere(p, (nx / 2.0 + 0.3, ny / 2.0 - 0.2), R, inside_positive=False)
+        cases.append(dict(params=p, sdf=l, init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0))))
+    return cases
+
+
+def make_batch(cplb, cases, stream=None):
+    b = cplb.Batch([c["params"] for c in cases], stream=stream)
+    for k, c in enumerate(cases):
+        b.init_sdf(k, c["sdf"], c1=c["init"]["c1"], c2=c["init"]["c2"])
+    return b
+
+
+def single(cplb, case, steps):
+    g = cplb.Lattice(case["params"])
+    g.init_sdf(case["sdf"], c1=case["init"]["c1"], c2=case["init"]["c2"])
+    g.step(steps)
+    return g
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_s16f"])
+def test_batch_cases_equal_single_lattices_bitwise(cplb, precision):
+    cases = mixed_cases(precision)
+    say(f"batch of {len(cases)} mixed cases, {precision}, 25 steps")
+    b = make_batch(cplb, cases)
+    assert [n for n, _ in b.classes()] == [3, 3, 1]
+    b.step(25)
+    assert b.step_count == 25
+    for k, c in enumerate(cases):
+        g = single(cplb, c, 25)
+        for f in FIELDS2:
+            a = b.field(k, f).cpu().numpy()
+            s = g.field(f).cpu().numpy()
+            assert np.all(np.isfinite(a)), (k, f)
+            assert np.array_equal(a, s), (precision, k, f, float(np.abs(a - s).max()))
+        r = b.reduce(k)
+        assert r["rc"] == 0 and r["step"] == 25
+        g.close()
+
+
+def test_batch_fp64_matches_oracle(cplb):
+    cases = mixed_cases("f64")[:3]
+    say("batch fp64 vs oracle, 3 cases, 10 steps")
+    b = make_batch(cplb, cases)
+    b.step(10)
+    for k, c in enumerate(cases):
+        o = ref.Oracle(c["params"])
+        o.init_sdf(c["sdf"], c1=c["init"]["c1"], c2=c["init"]["c2"])
+        o.step(10)
+        for f in ("phi", "c1", "c2", "ux", "uy", "p"):
+            a = b.field(k, f).cpu().numpy()
+            r = o.field(f)
+            scale = max(np.linalg.norm(r), np.linalg.norm(r - r.mean()), 1e-300)
+            err = np.linalg.norm(a - r) / scale
+            assert err <= 1e-12, (k, f, err)
+
+
+def test_batch_tune_leaves_state_unchanged(cplb):
+    cases = mixed_cases("f32")
+    a = make_batch(cplb, cases)
+    c = make_batch(cplb, cases)
+    a.step(6)
+    c.step(6)
+    ms = a.tune(2)
+    assert ms > 0
+    for cls, (n, v) in enumerate(a.classes()):
+        assert 0 <= v < 8
+    a.step(7)
+    c.step(7)
+    for k in range(len(cases)):
+        for f in ("phi", "c1", "c2", "ux", "uy", "p"):
+            assert np.array_equal(a.field(k, f).cpu().numpy(), c.field(k, f).cpu().numpy()), (k, f)
+    with pytest.raises(cplb.CplbError) as e:
+        a.set_variant(0, 8)
+    assert e.value.code == cplb.CPLB_EINVAL
+
+
+def test_batch_graph_replays_match_eager_steps(cplb):
+    import torch
+    cases = mixed_cases("f32")
+    s = torch.cuda.Stream()
+    a = make_batch(cplb, cases, stream=s)
+    e = make_batch(cplb, cases)
+    a.step(1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.step(4)
+    torch.cuda.synchronize()
+    e.step(1)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        e.step(4)
+        torch.cuda.synchronize()
+        for k in range(len(cases)):
+            for f in ("phi", "c1", "ux"):
+                assert np.array_equal(a.field(k, f).cpu().numpy(),
+                                      e.field(k, f).cpu().numpy()), (rep, k, f)
+
+
+def test_full_sweep_sampled_cases(cplb):
+    """The 512-case sweep at full size in the benchmarked launch
+    configuration: sampled cases equal their single-lattice runs, every case
+    stays finite and conserves its phase."""
+    sw = W.batched_sweep()
+    cases = sw["cases"]
+    say(f"full sweep: {len(cases)} cases, {sw['nodes']} nodes, 20 steps")
+    b = make_batch(cplb, cases)
+    r0 = [b.reduce(k)["sum_phi"] for k in range(len(cases))]
+    b.step(20)
+    bad = []
+    for k in range(len(cases)):
+        r = b.reduce(k)
+        if r["rc"] != 0 or abs(r["sum_phi"] - r0[k]) > 1e-5 * abs(r0[k]):
+            bad.append((k, r["rc"], r["sum_phi"], r0[k]))
+    assert not bad, bad[:5]
+    for k in (0, 1, 100, 257, 400, 511):
+        g = single(cplb, cases[k], 20)
+        for f in ("phi", "c1", "c2", "ux", "uy", "p"):
+            assert np.array_equal(b.field(k, f).cpu().numpy(), g.field(f).cpu().numpy()), (k, f)
+        g.close()

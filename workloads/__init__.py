@@ -166,6 +166,68 @@ def rising_droplet_3d(n=256, precision="f32"):
 
 # ------------------------------------------------------------ random fields
 
+def batched_sweep(ncases=512, seed=0, precision="f32", side=(64, 256), velocity=0.01):
+    """Independent 2-D interfacial-transfer cases for one batched run: each
+    side drawn uniformly from ``side`` (inclusive), Keq log-uniform in
+    [0.1, 10], diffusivity ratio D_hi/D_lo log-uniform in [1, 1000], Peclet
+    number log-uniform in [10, 1000], half static drops (periodic, matched
+    density and viscosity), half rising bubbles (walls in y, density ratio 10,
+    exponential viscosity law, Eo = 10).  The drop (fluid 2, radius
+    min(nx, ny)/8) carries the solute: c1 = 0, c2 = 1 - phi0.
+
+    The Peclet number fixes the fast diffusivity through a velocity scale:
+    D_hi = U 2R / Pe with U = ``velocity``; D_lo = D_hi / ratio.  Both are
+    clamped so that tau = 1/2 + D/cs^2 stays in [1/2 + 1e-3, 1]; every clamp
+    is listed in ``clamps`` (case, name, asked, used).
+
+    Returns dict(name, cases=[dict(params, sdf, init)], clamps, nodes)."""
+    rng = np.random.default_rng(seed)
+    cs2 = 1.0 / 3.0
+    d_lo_lim, d_hi_lim = cs2 * 1e-3, cs2 * 0.5
+    cases, clamps = [], []
+
+    def loguni(a, b):
+        return float(np.exp(rng.uniform(np.log(a), np.log(b))))
+
+    for k in range(ncases):
+        nx = int(rng.integers(side[0], side[1] + 1))
+        ny = int(rng.integers(side[0], side[1] + 1))
+        keq = loguni(0.1, 10.0)
+        ratio = loguni(1.0, 1000.0)
+        pe = loguni(10.0, 1000.0)
+        rising = bool(rng.integers(0, 2))
+        R = min(nx, ny) / 8.0
+        d_hi = velocity * 2.0 * R / pe
+        d_lo = d_hi / ratio
+        for name, d in (("D_hi", d_hi), ("D_lo", d_lo)):
+            dc = min(max(d, d_lo_lim), d_hi_lim)
+            if dc != d:
+                clamps.append((k, name, d, dc))
+            if name == "D_hi":
+                d_hi = dc
+            else:
+                d_lo = dc
+        common = dict(nx=nx, ny=ny, nz=1, lattice="d2q9", sigma=0.01, W=4.0, M=0.01, A=0.1,
+                      Keq=keq, D1=d_lo, D2=d_hi, precision=precision,
+                      ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0)
+        if rising:
+            rho1, rho2, sigma, eo = 10.0, 1.0, 0.01, 10.0
+            gmag = eo * sigma / ((rho1 - rho2) * (2 * R) ** 2)
+            p = params(**common, visc_law="exp", periodic=(1, 0, 1), rho1=rho1, rho2=rho2,
+                       mu1=2.0, mu2=0.2, g=(0.0, -gmag, 0.0), rho_ref=rho1)
+            centre = (nx / 2.0, 3.0 * R)
+        else:
+            p = params(**common, visc_law="linear", periodic=(1, 1, 1), rho1=1.0, rho2=1.0,
+                       mu1=0.1, mu2=0.1)
+            centre = (nx / 2.0, ny / 2.0)
+        l = sdf_sphere(p, centre, R, inside_positive=False)
+        cases.append(dict(name=f"case{k}_{nx}x{ny}_{'rising' if rising else 'static'}",
+                          params=p, sdf=l, init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0))))
+    nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    return dict(name=f"batched_sweep_{ncases}_{precision}", cases=cases, clamps=clamps,
+                nodes=nodes, steps=5000)
+
+
 def random_fields(p: dict, seed: int, u_amp: float = 0.02, p_amp: float = 1e-3):
     """Seeded smooth-ish random macroscopic fields for arithmetic checks:
     phi in (0.05, 0.95), c1, c2 in (0.1, 1.1), |u| <= u_amp, |p| <= p_amp."""
