@@ -1,0 +1,167 @@
+"""FP64 CPU oracle of the closure network (test infrastructure only).
+
+The closure network maps coarse-grid fields to a per-node correction of the
+interfacial scalar exchange.  Its architecture is fixed:
+
+    x (C0 = 16 input planes; unused planes are zero)
+    z1 = conv3x3(x;  W1, b1)   16 -> 32   a1 = lrelu(z1)
+    z2 = conv3x3(a1; W2, b2)   32 -> 32   a2 = lrelu(z2)
+    z3 = conv3x3(a2; W3, b3)   32 -> 32   a3 = lrelu(z3)
+    z4 = conv3x3(a3; W4, b4)   32 -> 16   output = z4[channel 0]
+
+with lrelu(z) = z for z > 0 and 0.1 z otherwise, 3x3 cross-correlation
+y[co, r, c] = b[co] + sum_{ci, dy, dx} W[co, ci, dy + 1, dx + 1] x[ci, r + dy, c + dx],
+periodic in x (columns) and zero outside the sample in y (rows), and the
+loss L = mean over nodes of (output - target)^2.
+
+The parameter vector stacks, layer by layer, W[co][ci][ky][kx] then b[co].
+
+Everything here is plain numpy in float64: the forward pass as written
+above, and its gradient by the chain rule (the adjoint of the padded
+correlation is the correlation with the flipped kernel under the same
+padding).  tests/test_closure_oracle.py pins it against a direct loop
+convolution, central finite differences and translation equivariance.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LAYERS = ((16, 32), (32, 32), (32, 32), (32, 16))  # (C_in, C_out)
+SLOPE = 0.1
+
+
+def num_params() -> int:
+    return sum(co * ci * 9 + co for ci, co in LAYERS)
+
+
+def unpack(theta):
+    """[(W[co][ci][3][3], b[co])] from the flat parameter vector."""
+    out, k = [], 0
+    for ci, co in LAYERS:
+        W = theta[k:k + co * ci * 9].reshape(co, ci, 3, 3)
+        k += co * ci * 9
+        b = theta[k:k + co]
+        k += co
+        out.append((W, b))
+    return out
+
+
+def pack(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-style normal initialisation (std sqrt(2 / (9 C_in))), zero biases;
+    the last layer starts at 1/10 of that scale."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for n, (ci, co) in enumerate(LAYERS):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if n == len(LAYERS) - 1 else 1.0)
+        layers.append((rng.normal(0.0, std, size=(co, ci, 3, 3)), np.zeros(co)))
+    return pack(layers)
+
+
+def shifted(x, dy, dx):
+    """s[..., r, c] = x[..., r + dy, (c + dx) mod W], zero where r + dy is
+    outside [0, H)."""
+    H = x.shape[-2]
+    s = np.roll(x, -dx, axis=-1)
+    out = np.zeros_like(s)
+    if dy == 0:
+        out[...] = s
+    elif dy > 0:
+        out[..., :H - dy, :] = s[..., dy:, :]
+    else:
+        out[..., -dy:, :] = s[..., :H + dy, :]
+    return out
+
+
+def conv(x, W, b):
+    """x [B, C_in, H, W] -> y [B, C_out, H, W] (the padded 3x3 correlation)."""
+    y = np.zeros((x.shape[0], W.shape[0]) + x.shape[2:])
+    for ky in range(3):
+        for kx in range(3):
+            xs = shifted(x, ky - 1, kx - 1)
+            y += np.einsum("oi,bihw->bohw", W[:, :, ky, kx], xs)
+    return y + b[None, :, None, None]
+
+
+def conv_adjoint(g, W):
+    """Adjoint of conv in x: dL/dx from dL/dy = g."""
+    dx = np.zeros((g.shape[0], W.shape[1]) + g.shape[2:])
+    for ky in range(3):
+        for kx in range(3):
+            t = np.einsum("oi,bohw->bihw", W[:, :, ky, kx], g)
+            dx += shifted(t, -(ky - 1), -(kx - 1))
+    return dx
+
+
+def conv_weight_grad(x, g):
+    """dL/dW [co, ci, 3, 3] and dL/db [co] from input x and dL/dy = g."""
+    dW = np.zeros((g.shape[1], x.shape[1], 3, 3))
+    for ky in range(3):
+        for kx in range(3):
+            xs = shifted(x, ky - 1, kx - 1)
+            dW[:, :, ky, kx] = np.einsum("bohw,bihw->oi", g, xs)
+    return dW, g.sum(axis=(0, 2, 3))
+
+
+def lrelu(z):
+    return np.where(z > 0, z, SLOPE * z)
+
+
+def lrelu_grad(z):
+    return np.where(z > 0, 1.0, SLOPE)
+
+
+def forward(theta, x):
+    """Output [B, H, W] and the pre-activations [z1..z4]."""
+    layers = unpack(np.asarray(theta, dtype=np.float64))
+    a = np.asarray(x, dtype=np.float64)
+    zs = []
+    for n, (W, b) in enumerate(layers):
+        z = conv(a, W, b)
+        zs.append(z)
+        a = lrelu(z) if n < len(layers) - 1 else z
+    return zs[-1][:, 0], zs
+
+
+def loss_and_grad(theta, x, target):
+    """Mean squared error and its gradient with respect to theta."""
+    layers = unpack(np.asarray(theta, dtype=np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    out, zs = forward(theta, x)
+    r = out - target
+    P = r.size
+    loss = float(np.sum(r * r) / P)
+    g = np.zeros_like(zs[-1])
+    g[:, 0] = 2.0 * r / P
+    grads = [None] * len(layers)
+    for n in range(len(layers) - 1, -1, -1):
+        a_in = x if n == 0 else lrelu(zs[n - 1])
+        W, _ = layers[n]
+        grads[n] = conv_weight_grad(a_in, g)
+        if n > 0:
+            g = conv_adjoint(g, W) * lrelu_grad(zs[n - 1])
+    return loss, pack(grads)
+
+
+def conv_direct(x, W, b):
+    """The same correlation by explicit loops (small inputs only)."""
+    B, Ci, H, Wd = x.shape
+    Co = W.shape[0]
+    y = np.zeros((B, Co, H, Wd))
+    for bb in range(B):
+        for o in range(Co):
+            for r in range(H):
+                for c in range(Wd):
+                    s = b[o]
+                    for i in range(Ci):
+                        for ky in range(3):
+                            rr = r + ky - 1
+                            if rr < 0 or rr >= H:
+                                continue
+                            for kx in range(3):
+                                s += W[o, i, ky, kx] * x[bb, i, rr, (c + kx - 1) % Wd]
+                    y[bb, o, r, c] = s
+    return y

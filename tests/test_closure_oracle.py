@@ -1,0 +1,76 @@
+"""Pins of the FP64 closure-network oracle (CPU): the vectorised correlation
+equals a direct loop, its adjoint satisfies <conv(x), g> = <x, adj(g)>, the
+analytic gradient equals central finite differences of the loss, and the
+network is equivariant to periodic shifts in x."""
+import numpy as np
+import pytest
+
+from oracle import cnn_ref as C
+
+
+def small_case(seed, B=2, H=5, W=6):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(B, 16, H, W))
+    t = rng.normal(size=(B, H, W)) * 0.1
+    theta = C.init_params(seed) * 3.0  # larger last layer: every layer matters
+    theta += rng.normal(size=theta.size) * 0.01  # non-zero biases
+    return x, t, theta
+
+
+def test_conv_matches_direct_loops():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 3, 4, 5))
+    W = rng.normal(size=(4, 3, 3, 3))
+    b = rng.normal(size=4)
+    np.testing.assert_allclose(C.conv(x, W, b), C.conv_direct(x, W, b), rtol=1e-13, atol=1e-13)
+
+
+def test_adjoint_identity():
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(2, 5, 6, 7))
+    g = rng.normal(size=(2, 4, 6, 7))
+    W = rng.normal(size=(4, 5, 3, 3))
+    lhs = np.sum(C.conv(x, W, np.zeros(4)) * g)
+    rhs = np.sum(x * C.conv_adjoint(g, W))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_gradient_matches_finite_differences():
+    x, t, theta = small_case(2)
+    loss, grad = C.loss_and_grad(theta, x, t)
+    rng = np.random.default_rng(3)
+    # every layer's weights and biases, including the output layer's channel 0
+    idx = list(rng.choice(theta.size, size=60, replace=False))
+    k = 0
+    for ci, co in C.LAYERS:
+        idx += [k, k + co * ci * 9]  # first weight, first bias of each layer
+        k += co * ci * 9 + co
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (C.loss_and_grad(tp, x, t)[0] - C.loss_and_grad(tm, x, t)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1e-3, abs(grad[i])) + 1e-10, (i, fd, grad[i])
+
+
+def test_periodic_shift_equivariance_in_x():
+    x, t, theta = small_case(4, W=8)
+    out, _ = C.forward(theta, x)
+    out_s, _ = C.forward(theta, np.roll(x, 3, axis=-1))
+    np.testing.assert_allclose(np.roll(out, 3, axis=-1), out_s, rtol=1e-12, atol=1e-14)
+
+
+def test_zero_padding_in_y_is_per_sample():
+    """Stacking samples along the batch axis must not couple them."""
+    x, t, theta = small_case(5, B=3)
+    out, _ = C.forward(theta, x)
+    for b in range(3):
+        ob, _ = C.forward(theta, x[b:b + 1])
+        np.testing.assert_allclose(ob[0], out[b], rtol=1e-13, atol=1e-15)
+
+
+def test_param_vector_layout():
+    assert C.num_params() == 32 * 16 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 16 * 32 * 9 + 16
+    theta = np.arange(C.num_params(), dtype=np.float64)
+    assert np.array_equal(C.pack(C.unpack(theta)), theta)
