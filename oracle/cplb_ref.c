@@ -139,6 +139,8 @@ struct cplb_ref {
   double *u_old, *phi_old, *c1_old, *c2_old;
   int64_t step;
   int macros_valid;
+  /* caller's per-node extra exchange (learned-closure extension), or NULL */
+  const double* xs;
   char err[256];
 };
 
@@ -527,7 +529,9 @@ static void collide(cplb_ref_t* h) {
     /* two-scalar sets h1, h2 with sources H_k and auxiliary sources ~H_k */
     const double M1 = P->A * Dm * (P->Keq * c2 * phi - c1 * (1.0 - phi));
     const double M2 = P->A * Dm * (c1 * (1.0 - phi) - P->Keq * c2 * phi);
-    const double aux = Dm * dot3(gphi, gpsi); /* D_m grad phi . grad(c1 + Keq c2) */
+    /* D_m grad phi . grad(c1 + Keq c2), plus the closure's extra exchange:
+       h1 loses w_i s and h2 gains it, as with ~H */
+    const double aux = Dm * dot3(gphi, gpsi) + (h->xs ? h->xs[n] : 0.0);
     for (int i = 0; i < LF->q; i++) {
       const int* c = LF->c[i];
       const double w = LF->w[i];
@@ -573,6 +577,12 @@ static void stream_set(const cplb_ref_t* h, const lattice_t* L, const double* sr
         dst[i * N + v[0] + n3[0] * (v[1] + n3[1] * v[2])] = src[i * N + n];
     }
   }
+}
+
+int cplb_ref_set_closure(cplb_ref_t* h, const double* s) {
+  if (!h) return CPLB_REF_EINVAL;
+  h->xs = s;
+  return CPLB_REF_OK;
 }
 
 int cplb_ref_step(cplb_ref_t* h, int64_t nsteps) {

@@ -70,6 +70,11 @@ int cplb_ref_init_sdf(cplb_ref_t* h, const double* l, double c1_a, double c1_b,
 
 int cplb_ref_step(cplb_ref_t* h, int64_t nsteps);
 
+/* Extra exchange per step (N values in node order, caller-owned, NULL for
+ * none), carried like the auxiliary source ~H_k: h1 loses w_i s, h2 gains
+ * it.  Used to check the learned closure's coupling into the step. */
+int cplb_ref_set_closure(cplb_ref_t* h, const double* s);
+
 /* Macroscopic field at the current time level (moments of the current
  * populations, Sec. III): writes N values. */
 int cplb_ref_field(cplb_ref_t* h, int field, double* out);

@@ -52,6 +52,7 @@ def lib():
         L.cplb_ref_init_sdf.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double]
         L.cplb_ref_step.argtypes = [vp, i64]
+        L.cplb_ref_set_closure.argtypes = [vp, dp]
         L.cplb_ref_field.argtypes = [vp, ctypes.c_int, dp]
         L.cplb_ref_reduce.argtypes = [vp, dp]
         L.cplb_ref_get_populations.argtypes = [vp, ctypes.c_int, dp]
@@ -136,6 +137,16 @@ class Oracle:
             pp = _dptr(p)
         self._check(lib().cplb_ref_init_fields(self._h, _dptr(arrs[0]), _dptr(arrs[1]),
                                                _dptr(arrs[2]), up, pp))
+
+    def set_closure(self, s):
+        """Per-node extra exchange per step (None switches it off); the array
+        is kept alive by the oracle object."""
+        if s is None:
+            self._closure = None
+            self._check(lib().cplb_ref_set_closure(self._h, None))
+            return
+        self._closure = np.ascontiguousarray(s, dtype=np.float64).reshape(-1).copy()
+        self._check(lib().cplb_ref_set_closure(self._h, _dptr(self._closure)))
 
     def step(self, n=1):
         self._check(lib().cplb_ref_step(self._h, int(n)))

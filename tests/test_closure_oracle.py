@@ -74,3 +74,35 @@ def test_param_vector_layout():
     assert C.num_params() == 32 * 16 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 16 * 32 * 9 + 16
     theta = np.arange(C.num_params(), dtype=np.float64)
     assert np.array_equal(C.pack(C.unpack(theta)), theta)
+
+
+def test_oracle_closure_term_closed_form():
+    """Uniform fields at partition equilibrium (no exchange, no gradients)
+    and a uniform closure s: one step moves S1 = c1 - s, S2 = c2 + s, and the
+    exact recovery c1' = S1 + a e', c2' = S2 - a e' with
+    e' = (Keq phi S2 - (1 - phi) S1) / (1 + a (Keq phi + 1 - phi)),
+    a = A D_m / 2, D_m = D1 D2 / (Keq D1 (1 - phi) + D2 phi) (Sec. III C)."""
+    import workloads as W
+    from oracle import ref
+    p = W.params(nx=6, ny=5, D1=0.07, D2=0.02, Keq=0.6, A=0.4)
+    phi, K = 0.3, p["Keq"]
+    c2 = 0.5
+    c1 = K * phi * c2 / (1.0 - phi)  # e = Keq phi c2 - (1 - phi) c1 = 0
+    shp = W.shape_of(p)
+    o = ref.Oracle(p)
+    o.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
+    s = 1.7e-3
+    o.set_closure(np.full(shp, s))
+    o.step(1)
+    Dm = p["D1"] * p["D2"] / (K * p["D1"] * (1 - phi) + p["D2"] * phi)
+    a = 0.5 * p["A"] * Dm
+    S1, S2 = c1 - s, c2 + s
+    e = (K * phi * S2 - (1 - phi) * S1) / (1 + a * (K * phi + 1 - phi))
+    np.testing.assert_allclose(o.field("c1"), S1 + a * e, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o.field("c2"), S2 - a * e, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o.field("phi"), phi, rtol=0, atol=1e-15)
+    # without the closure the state stays put
+    o2 = ref.Oracle(p)
+    o2.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
+    o2.step(1)
+    np.testing.assert_allclose(o2.field("c1"), c1, rtol=0, atol=1e-15)
