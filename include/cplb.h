@@ -162,6 +162,13 @@ size_t cplb_state_bytes(const cplb_t* h);
 int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes);
 int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes);
 
+/* Learned closure on a D2Q9 lattice: dev_s (device, N FP32 values in node
+ * order, owned by the caller and kept alive while set) is an extra exchange
+ * per step carried like the auxiliary source ~H_k (Sec. III C): h1 loses
+ * w_i s, h2 gains it, so c1 + c2 is conserved exactly.  NULL switches it
+ * off.  CPLB_EINVAL on a 3-D lattice. */
+int cplb_set_closure(cplb_t* h, const float* dev_s);
+
 /* Step-kernel variants (tile shape, non-temporal population traffic).
  * Every variant computes the same step; they differ only in how the work is
  * tiled and how the population streams are hinted to the caches.
@@ -240,6 +247,55 @@ const char* cplb_batch_last_error(const cplb_batch_t* b);
 
 /* Release the batch (not the caller's workspace or stream). */
 void cplb_batch_destroy(cplb_batch_t* b);
+
+/* ------------------------------------------------------------------------
+ * Closure network: the small CNN that predicts the per-node correction s of
+ * the interfacial scalar exchange on a coarse grid from its fields.  Fixed
+ * architecture: four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 channels,
+ * leaky-ReLU (slope 0.1) after the first three, output = channel 0 of the
+ * last; padding periodic along x, zero outside each sample along y.  BF16
+ * MFMA with FP32 accumulation for every convolution, FP32 master
+ * parameters, FP64 loss accumulation.  The parameter vector stacks per
+ * layer W[co][ci][ky][kx] then b[co] (cplb_cnn_num_params values).
+ * Samples are H x W planes; up to `nsamples` are processed at once.
+ */
+typedef struct cplb_cnn cplb_cnn_t;
+
+int cplb_cnn_num_params(void);
+int cplb_cnn_workspace_bytes(int nsamples, int H, int W, size_t* bytes);
+int cplb_cnn_create(int nsamples, int H, int W, void* dev_workspace, size_t bytes, void* hip_stream,
+                    cplb_cnn_t** out);
+
+/* Parameters: set from / get to a host array of cplb_cnn_num_params FP32
+ * values (setting resets the Adam state); init draws He-normal weights
+ * (std sqrt(2 / (9 C_in)), a tenth of it on the last layer) and zero biases
+ * from a seeded generator.  All synchronise. */
+int cplb_cnn_set_params(cplb_cnn_t* c, const float* host_theta);
+int cplb_cnn_init_params(cplb_cnn_t* c, uint64_t seed);
+int cplb_cnn_get_params(cplb_cnn_t* c, float* host_theta);
+
+/* Input plane k is multiplied by scale[k] before the first layer (host
+ * array of 16; default 1).  Synchronises. */
+int cplb_cnn_set_input_scale(cplb_cnn_t* c, const float scale[16]);
+
+/* Forward pass of nsamples samples: dev_planes (device) holds
+ * [nsamples][cin][H][W] FP32, cin <= 16 (missing planes are zero); dev_out
+ * (device, may be NULL) receives [nsamples][H][W] FP32.  Asynchronous. */
+int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin, float* dev_out);
+
+/* Loss mean((out - target)^2) of the last forward against dev_target
+ * ([nsamples][H][W] FP32, device), accumulated in FP64, and the gradient of
+ * every parameter (FP32).  *loss (may be NULL) receives the loss; with it
+ * the call synchronises. */
+int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss);
+int cplb_cnn_get_grads(cplb_cnn_t* c, float* host_grad);
+
+/* One Adam step on the last gradients (bias-corrected), then the BF16
+ * weight copies are refreshed.  Asynchronous. */
+int cplb_cnn_adam(cplb_cnn_t* c, float lr, float beta1, float beta2, float eps);
+
+const char* cplb_cnn_last_error(const cplb_cnn_t* c);
+void cplb_cnn_destroy(cplb_cnn_t* c);
 
 /* Error text of the last failed call on h, and of a return code. */
 const char* cplb_last_error(const cplb_t* h);

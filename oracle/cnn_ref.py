@@ -19,8 +19,10 @@ The parameter vector stacks, layer by layer, W[co][ci][ky][kx] then b[co].
 Everything here is plain numpy in float64: the forward pass as written
 above, and its gradient by the chain rule (the adjoint of the padded
 correlation is the correlation with the flipped kernel under the same
-padding).  tests/test_closure_oracle.py pins it against a direct loop
-convolution, central finite differences and translation equivariance.
+padding).  An optional storage model rounds the stored operands to BF16
+the way a mixed-precision implementation keeps them (see ``forward``).
+tests/test_closure_oracle.py pins it against a direct loop convolution,
+central finite differences and translation equivariance.
 """
 from __future__ import annotations
 
@@ -114,35 +116,58 @@ def lrelu_grad(z):
     return np.where(z > 0, 1.0, SLOPE)
 
 
-def forward(theta, x):
-    """Output [B, H, W] and the pre-activations [z1..z4]."""
+def bf16(a):
+    """Round to BF16 (8 significant bits, round to nearest, ties to even),
+    returned as float64.  Used to model a network that stores its weights,
+    activations and back-propagated gradients in BF16 (``storage="bf16"``)."""
+    a = np.asarray(a, dtype=np.float32).copy()
+    u = a.view(np.uint32)
+    u += np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))
+    u &= np.uint32(0xFFFF0000)
+    return u.view(np.float32).astype(np.float64)
+
+
+def _identity(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def forward(theta, x, storage="f64"):
+    """Output [B, H, W], the pre-activations [z1..z4] and the layer inputs.
+
+    storage="bf16" rounds what a mixed-precision network stores: the input
+    and every layer's activations and weights to BF16, the pre-activations
+    to FP32; the arithmetic itself stays FP64."""
+    rnd = bf16 if storage == "bf16" else _identity
+    f32 = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if storage == "bf16" else _identity
     layers = unpack(np.asarray(theta, dtype=np.float64))
-    a = np.asarray(x, dtype=np.float64)
-    zs = []
+    a = rnd(x)
+    zs, ins = [], []
     for n, (W, b) in enumerate(layers):
-        z = conv(a, W, b)
+        ins.append(a)
+        z = f32(conv(a, rnd(W), b))
         zs.append(z)
-        a = lrelu(z) if n < len(layers) - 1 else z
-    return zs[-1][:, 0], zs
+        a = rnd(lrelu(z) if n < len(layers) - 1 else z)
+    return zs[-1][:, 0], zs, ins
 
 
-def loss_and_grad(theta, x, target):
-    """Mean squared error and its gradient with respect to theta."""
+def loss_and_grad(theta, x, target, storage="f64"):
+    """Mean squared error and its gradient with respect to theta
+    (storage="bf16": the back-propagated gradients dL/dz are stored in BF16
+    too, as are the weights they meet)."""
+    rnd = bf16 if storage == "bf16" else _identity
     layers = unpack(np.asarray(theta, dtype=np.float64))
-    x = np.asarray(x, dtype=np.float64)
-    out, zs = forward(theta, x)
+    out, zs, ins = forward(theta, x, storage)
     r = out - target
     P = r.size
     loss = float(np.sum(r * r) / P)
     g = np.zeros_like(zs[-1])
-    g[:, 0] = 2.0 * r / P
+    g[:, 0] = rnd(2.0 * r / P)
     grads = [None] * len(layers)
     for n in range(len(layers) - 1, -1, -1):
-        a_in = x if n == 0 else lrelu(zs[n - 1])
         W, _ = layers[n]
-        grads[n] = conv_weight_grad(a_in, g)
+        grads[n] = conv_weight_grad(ins[n], g)
         if n > 0:
-            g = conv_adjoint(g, W) * lrelu_grad(zs[n - 1])
+            g = rnd(conv_adjoint(g, rnd(W)) * lrelu_grad(zs[n - 1]))
     return loss, pack(grads)
 
 

@@ -17,7 +17,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcplb.so")
-SOURCES = ["api.hip", "batch.hip", "aux.hip", "step2d.hip", "step3d.hip", "batch2d.hip"]
+SOURCES = ["api.hip", "batch.hip", "cnn_api.hip", "aux.hip", "step2d.hip", "step3d.hip",
+           "batch2d.hip", "cnn.hip"]
 ARCH = os.environ.get("CPLB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -34,7 +34,11 @@ EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init
            "cplb_batch_read_field", "cplb_batch_reduce", "cplb_batch_num_classes",
            "cplb_batch_case_class", "cplb_batch_class_cases", "cplb_batch_get_variant",
            "cplb_batch_set_variant", "cplb_batch_tune", "cplb_batch_last_error",
-           "cplb_batch_destroy")
+           "cplb_batch_destroy", "cplb_set_closure",
+           "cplb_cnn_num_params", "cplb_cnn_workspace_bytes", "cplb_cnn_create",
+           "cplb_cnn_set_params", "cplb_cnn_init_params", "cplb_cnn_get_params",
+           "cplb_cnn_set_input_scale", "cplb_cnn_forward", "cplb_cnn_backward",
+           "cplb_cnn_get_grads", "cplb_cnn_adam", "cplb_cnn_last_error", "cplb_cnn_destroy")
 
 
 class cplb_params(ctypes.Structure):
@@ -116,6 +120,24 @@ def library():
         L.cplb_batch_last_error.restype = ctypes.c_char_p
         L.cplb_batch_destroy.argtypes = [vp]
         L.cplb_batch_destroy.restype = None
+        L.cplb_set_closure.argtypes = [vp, vp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.cplb_cnn_num_params.argtypes = []
+        L.cplb_cnn_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+        L.cplb_cnn_create.argtypes = [i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.cplb_cnn_set_params.argtypes = [vp, fp]
+        L.cplb_cnn_init_params.argtypes = [vp, ctypes.c_uint64]
+        L.cplb_cnn_get_params.argtypes = [vp, fp]
+        L.cplb_cnn_set_input_scale.argtypes = [vp, fp]
+        L.cplb_cnn_forward.argtypes = [vp, i32, vp, i32, vp]
+        L.cplb_cnn_backward.argtypes = [vp, vp, dp]
+        L.cplb_cnn_get_grads.argtypes = [vp, fp]
+        L.cplb_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float]
+        L.cplb_cnn_last_error.argtypes = [vp]
+        L.cplb_cnn_last_error.restype = ctypes.c_char_p
+        L.cplb_cnn_destroy.argtypes = [vp]
+        L.cplb_cnn_destroy.restype = None
         _lib = L
     return _lib
 
@@ -220,6 +242,10 @@ def cplb_load_state(h, blob: bytes):
 
 def cplb_destroy(h):
     library().cplb_destroy(h)
+
+
+def cplb_set_closure(h, dev_ptr):
+    _check(h, library().cplb_set_closure(h, None if dev_ptr is None else ctypes.c_void_p(dev_ptr)))
 
 
 def cplb_num_variants(h) -> int:
@@ -341,6 +367,21 @@ class Lattice:
     @variant.setter
     def variant(self, v):
         cplb_set_variant(self._h, v)
+
+    def set_closure(self, s):
+        """Per-node extra exchange (a float32 device tensor of the lattice's
+        shape) applied by every following step, or None.  The tensor is kept
+        alive while set; the library stream waits for the caller's stream."""
+        if s is None:
+            cplb_set_closure(self._h, None)
+            self._closure = None
+            return
+        t = s
+        assert t.dtype == self.torch.float32 and t.is_cuda and t.is_contiguous()
+        assert t.numel() == self.N
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        cplb_set_closure(self._h, t.data_ptr())
+        self._closure = t
 
     def variant_names(self):
         return [cplb_variant_name(self._h, v) for v in range(cplb_num_variants(self._h))]
@@ -534,3 +575,155 @@ class Batch:
     def tune(self, probe_steps=10):
         """Pick the fastest tile variant per size class; returns ms per batch step."""
         return cplb_batch_tune(self._b, probe_steps)
+
+
+# ------------------------------------------------------- closure network
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _ccheck(c, rc):
+    if rc:
+        raise CplbError(rc, library().cplb_cnn_last_error(c).decode())
+
+
+def cplb_cnn_num_params() -> int:
+    return library().cplb_cnn_num_params()
+
+
+def cplb_cnn_workspace_bytes(nsamples, H, W) -> int:
+    n = ctypes.c_size_t()
+    rc = library().cplb_cnn_workspace_bytes(nsamples, H, W, ctypes.byref(n))
+    if rc:
+        raise CplbError(rc, "cplb_cnn_workspace_bytes rejected the sizes")
+    return n.value
+
+
+def cplb_cnn_create(nsamples, H, W, ws_ptr, ws_bytes, stream_ptr):
+    c = ctypes.c_void_p()
+    rc = library().cplb_cnn_create(nsamples, H, W, ctypes.c_void_p(ws_ptr), ws_bytes,
+                                   ctypes.c_void_p(stream_ptr), ctypes.byref(c))
+    if rc:
+        raise CplbError(rc, "cplb_cnn_create failed")
+    return c
+
+
+def cplb_cnn_set_params(c, theta):
+    _ccheck(c, library().cplb_cnn_set_params(c, _fp(theta)))
+
+
+def cplb_cnn_init_params(c, seed):
+    _ccheck(c, library().cplb_cnn_init_params(c, seed))
+
+
+def cplb_cnn_get_params(c, out):
+    _ccheck(c, library().cplb_cnn_get_params(c, _fp(out)))
+
+
+def cplb_cnn_set_input_scale(c, scale):
+    _ccheck(c, library().cplb_cnn_set_input_scale(c, _fp(scale)))
+
+
+def cplb_cnn_forward(c, nsamples, planes_ptr, cin, out_ptr):
+    _ccheck(c, library().cplb_cnn_forward(c, nsamples, ctypes.c_void_p(planes_ptr), cin,
+                                          None if out_ptr is None else ctypes.c_void_p(out_ptr)))
+
+
+def cplb_cnn_backward(c, target_ptr) -> float:
+    loss = ctypes.c_double()
+    _ccheck(c, library().cplb_cnn_backward(c, ctypes.c_void_p(target_ptr), ctypes.byref(loss)))
+    return loss.value
+
+
+def cplb_cnn_get_grads(c, out):
+    _ccheck(c, library().cplb_cnn_get_grads(c, _fp(out)))
+
+
+def cplb_cnn_adam(c, lr, beta1, beta2, eps):
+    _ccheck(c, library().cplb_cnn_adam(c, lr, beta1, beta2, eps))
+
+
+def cplb_cnn_last_error(c) -> str:
+    return library().cplb_cnn_last_error(c).decode()
+
+
+def cplb_cnn_destroy(c):
+    library().cplb_cnn_destroy(c)
+
+
+class ClosureNet:
+    """The closure network on one GPU: up to `nsamples` H x W samples per
+    call.  Inputs and outputs are float32 device tensors."""
+
+    def __init__(self, nsamples, H, W, device="cuda:0", stream=None, seed=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("cplb needs a GPU: torch.cuda.is_available() is False")
+        self.torch = torch
+        self.nsamples, self.H, self.W = nsamples, H, W
+        self.device = torch.device(device)
+        nbytes = cplb_cnn_workspace_bytes(nsamples, H, W)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._c = cplb_cnn_create(nsamples, H, W, self.workspace.data_ptr(), nbytes,
+                                  self.stream.cuda_stream)
+        self.n_params = cplb_cnn_num_params()
+        if seed is not None:
+            cplb_cnn_init_params(self._c, seed)
+
+    def close(self):
+        if getattr(self, "_c", None):
+            cplb_cnn_destroy(self._c)
+            self._c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _order(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def set_params(self, theta):
+        cplb_cnn_set_params(self._c, np.ascontiguousarray(theta, dtype=np.float32))
+
+    def params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        cplb_cnn_get_params(self._c, out)
+        return out
+
+    def grads(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        cplb_cnn_get_grads(self._c, out)
+        return out
+
+    def set_input_scale(self, scale):
+        sc = np.zeros(16, dtype=np.float32)
+        sc[:len(scale)] = scale
+        cplb_cnn_set_input_scale(self._c, sc)
+
+    def forward(self, planes, out=None):
+        """planes: [B, cin, H, W] float32 device tensor -> [B, H, W]."""
+        torch = self.torch
+        assert planes.dtype == torch.float32 and planes.is_contiguous()
+        B, cin = int(planes.shape[0]), int(planes.shape[1])
+        if out is None:
+            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+        self._order()
+        cplb_cnn_forward(self._c, B, planes.data_ptr(), cin, out.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def backward(self, target) -> float:
+        """Loss of the last forward against target [B, H, W] (FP64), and
+        every gradient."""
+        assert target.dtype == self.torch.float32 and target.is_contiguous()
+        self._order()
+        return cplb_cnn_backward(self._c, target.data_ptr())
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        cplb_cnn_adam(self._c, lr, beta1, beta2, eps)

@@ -26,6 +26,7 @@ struct cplb {
   int cur;
   int64_t step;
   int variant;  // compiled step-kernel variant in use
+  const float* closure;  // caller's per-node extra exchange (2-D), or null
   KParams<double> k64;  // lattice constants (host copies)
   KParams<float> k32;
   KParams<double>* k64_dev;  // the same, in the workspace, read by the 3-D kernels
@@ -52,7 +53,7 @@ hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, const KParams<T>* Kdev,
   S* dst = (S*)h->lat[h->cur ^ 1];
   if (h->G.dim == 2)
     return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
-                               h->stream);
+                               h->closure, h->stream);
   return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
                              h->stream);
 }
@@ -192,6 +193,7 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->cur = 0;
   h->step = 0;
   h->variant = default_variant(prm);
+  h->closure = nullptr;
   h->k64 = make_kparams<double>(prm, G);
   h->k32 = make_kparams<float>(prm, G);
   h->err[0] = 0;
@@ -342,6 +344,13 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
     if (rc) return rc;
   }
   h->step = hd.step;
+  return CPLB_OK;
+}
+
+int cplb_set_closure(cplb_t* h, const float* dev_s) {
+  if (!h) return CPLB_EINVAL;
+  if (h->G.dim != 2 && dev_s) return set_err(h, CPLB_EINVAL, "a closure applies to D2Q9 lattices%s", "");
+  h->closure = dev_s;
   return CPLB_OK;
 }
 

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, 
   G.ntiles = G.tiles_x * ((G.ny + TY - 1) / TY);
   G.sS = D->sS;
   G.sT = D->sT;
+  G.closure = nullptr;
   const S* src = (const S*)D->lat[parity];
   S* dst = (S*)D->lat[parity ^ 1];
   const KParams<T>& P = *(const KParams<T>*)(kps + c);

@@ -1,0 +1,360 @@
+// Closure network: forward, backward and Adam on the GPU, with BF16 MFMA
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulate) for every convolution.
+//
+// Network (fixed): four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 with
+// leaky-ReLU (slope 0.1) after the first three; the output is channel 0 of
+// the last layer.  Padding: periodic along x, zero outside the sample along
+// y (samples are stacked along y).
+//
+// Layouts.  Activations are NHWC, pixel p = (sample * H + y) * W + x.  The
+// FP32 master parameters follow W[co][ci][ky][kx], b[co] per layer.  For
+// the MFMA the weights are kept in BF16 as Wg[co][k], k = tap * C_in + ci
+// (tap = 3 ky + kx), so that the four K-consecutive values a lane needs are
+// one 8-byte load; the adjoint (input gradient) uses the flipped transpose
+// Wf[ci][tap' * C_out + co] = W[co][ci][8 - tap'], which turns the adjoint
+// of the padded correlation into a forward correlation with the same
+// padding.
+//
+// MFMA 16x16x16 operand layout (lane l, g = l / 16, j = 0..3):
+//   A[m][k]: lane holds A[l % 16][4 g + j];  B[k][n]: B[4 g + j][l % 16];
+//   D[m][n]: lane holds D[4 g + j][l % 16].
+#include <hip/hip_runtime.h>
+
+#include "../../include/cplb.h"
+#include "kernels.hpp"
+
+namespace pflb {
+
+namespace {
+
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+constexpr float kSlope = 0.1f;
+
+// FP32 -> BF16 with round to nearest, ties to even (finite inputs)
+__device__ inline unsigned short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ inline short4v load4(const unsigned short* p) {
+  return __builtin_bit_cast(short4v, *(const unsigned long long*)p);
+}
+
+__device__ inline float4v mfma(short4v a, short4v b, float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2 };
+
+// One wave: 16 consecutive pixels of a row x all COUT channels.
+// kFwdAct / kFwdLinear: Z = conv(X) + b (FP32), A = act(Z) (BF16).
+// kBwd: X is dZ of the layer above, W its flipped transpose; the result is
+// dA of the layer below, written as dZ = dA * lrelu'(Zprev) in BF16.
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restrict__ X,
+                                                   const unsigned short* __restrict__ Wg,
+                                                   const float* __restrict__ bias,
+                                                   float* __restrict__ Z,
+                                                   unsigned short* __restrict__ A,
+                                                   const float* __restrict__ Zprev, int H, int W,
+                                                   int rows) {
+  constexpr int NT = COUT / 16, K = 9 * CIN;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = blockIdx.y;  // global row (sample * H + y)
+  if (R >= rows) return;
+  const int x0 = blockIdx.x * 64 + wave * 16;
+  if (x0 >= W) return;
+  const int m = lane & 15, g = lane >> 4;
+  const int y = R % H;
+  const int x = x0 + m;  // pixel of this lane's A row
+  float4v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const bool ok = x < W && y + dy >= 0 && y + dy < H;
+    int xs = x + dx;
+    xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+    const long long ps = (long long)(R + dy) * W + xs;
+#pragma unroll
+    for (int cg = 0; cg < CIN / 16; ++cg) {
+      const short4v a = ok ? load4(X + ps * CIN + cg * 16 + 4 * g) : short4v{0, 0, 0, 0};
+      const int k = tap * CIN + cg * 16 + 4 * g;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const short4v b = load4(Wg + (long long)(t * 16 + m) * K + k);
+        acc[t] = mfma(a, b, acc[t]);
+      }
+    }
+  }
+  // D[pixel 4 g + j][channel l % 16]
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + m;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int xp = x0 + 4 * g + j;
+      if (xp >= W) continue;
+      const long long p = (long long)R * W + xp;
+      float v = acc[t][j];
+      if (MODE == kBwd) {
+        const float zp = Zprev[p * COUT + co];
+        v *= zp > 0.f ? 1.f : kSlope;
+        A[p * COUT + co] = to_bf16(v);
+      } else {
+        v += bias[co];
+        Z[p * COUT + co] = v;
+        A[p * COUT + co] = to_bf16(MODE == kFwdAct ? (v > 0.f ? v : kSlope * v) : v);
+      }
+    }
+  }
+}
+
+// Weight gradient: partial[chunk][co][k] = sum over the chunk's pixels p of
+// dZ[p][co] * X(p shifted by tap(k))[ci(k)].  One wave per 16 x 16 tile of
+// (co, k) and chunk; the pixel sum is the MFMA's K dimension.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void wgrad_kernel(const unsigned short* __restrict__ X,
+                                                    const unsigned short* __restrict__ dZ,
+                                                    float* __restrict__ partial, int H, int W,
+                                                    long long P, int chunk) {
+  constexpr int K = 9 * CIN, MT = COUT / 16, NTL = K / 16;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= MT * NTL) return;
+  const int mt = tile / NTL, nt = tile % NTL;
+  const int c = blockIdx.y;
+  const int m = lane & 15, g = lane >> 4;
+  const int co = mt * 16 + m;      // A row of this lane
+  const int kk = nt * 16 + m;      // B column of this lane
+  const int tap = kk / CIN, ci = kk % CIN;
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const long long p0 = (long long)c * chunk;
+  const long long p1 = p0 + chunk < P ? p0 + chunk : P;
+  float4v acc = {0.f, 0.f, 0.f, 0.f};
+  for (long long pb = p0; pb < p1; pb += 16) {
+    short4v a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long p = pb + 4 * g + j;
+      unsigned short av = 0, bv = 0;
+      if (p < p1) {
+        av = dZ[p * COUT + co];
+        const long long R = p / W;
+        const int x = (int)(p - R * W), y = (int)(R % H);
+        if (y + dy >= 0 && y + dy < H) {
+          int xs = x + dx;
+          xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+          bv = X[((R + dy) * W + xs) * CIN + ci];
+        }
+      }
+      a[j] = (short)av;
+      b[j] = (short)bv;
+    }
+    acc = mfma(a, b, acc);
+  }
+  // D[co row 4 g + j][k column l % 16]
+  float* out = partial + (long long)c * COUT * K;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[(long long)(mt * 16 + 4 * g + j) * K + nt * 16 + m] = acc[j];
+}
+
+// grad W[co][ci][ky][kx] = sum over chunks of partial[chunk][co][tap * CIN + ci]
+__global__ void wgrad_reduce(const float* __restrict__ partial, int nchunks, int cin, int cout,
+                             float* __restrict__ grad) {
+  const int K = 9 * cin;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // oracle layout index
+  if (i >= cout * K) return;
+  const int co = i / K, r = i % K, ci = r / 9, tap = r % 9;
+  const long long src = (long long)co * K + tap * cin + ci;
+  float s = 0.f;
+  for (int c = 0; c < nchunks; ++c) s += partial[(long long)c * cout * K + src];
+  grad[i] = s;
+}
+
+// grad b[co] = sum_p dZ[p][co]; one block per output channel
+__global__ void bgrad_kernel(const unsigned short* __restrict__ dZ, long long P, int cout,
+                             float* __restrict__ grad) {
+  __shared__ float red[256];
+  const int co = blockIdx.x;
+  float s = 0.f;
+  for (long long p = threadIdx.x; p < P; p += blockDim.x) s += from_bf16(dZ[p * cout + co]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[co] = red[0];
+}
+
+// FP32 planes [sample][c][y][x] (c < cin) -> X0[p][16] in BF16, scaled
+__global__ void pack_kernel(const float* __restrict__ planes, int cin, const float* __restrict__ scale,
+                            long long hw, long long P, unsigned short* __restrict__ X0) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= P * 16) return;
+  const long long p = i / 16;
+  const int c = (int)(i % 16);
+  const long long s = p / hw, q = p % hw;
+  X0[i] = c < cin ? to_bf16(scale[c] * planes[(s * cin + c) * hw + q]) : (unsigned short)0;
+}
+
+// out[p] = Z4[p][0]
+__global__ void output_kernel(const float* __restrict__ Z4, long long P, float* __restrict__ out) {
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (p < P) out[p] = Z4[p * 16];
+}
+
+// loss partials (FP64) and dZ4 = d(mean (z - t)^2) / dz4 in BF16 (channel 0)
+__global__ void loss_kernel(const float* __restrict__ Z4, const float* __restrict__ target,
+                            long long P, unsigned short* __restrict__ dZ4,
+                            double* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += stride) {
+    const float r = Z4[p * 16] - target[p];
+    s += (double)r * (double)r;
+    dZ4[p * 16] = to_bf16(2.0f * r / (float)P);
+#pragma unroll
+    for (int c = 1; c < 16; ++c) dZ4[p * 16 + c] = 0;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials(const double* __restrict__ partial, int n, long long P,
+                             double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] / (double)P;
+}
+
+// Adam on the FP32 master parameters (bias-corrected step size c1 / (sqrt(v^) + eps))
+__global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ m,
+                            float* __restrict__ v, const float* __restrict__ grad, int n, float lr,
+                            float b1, float b2, float eps, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = grad[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 GEMM copies of one layer: Wg[co][tap * cin + ci] and the flipped
+// transpose Wf[ci][tap' * cout + co] = W[co][ci][8 - tap']
+__global__ void weights_kernel(const float* __restrict__ W, int cin, int cout,
+                               unsigned short* __restrict__ Wg, unsigned short* __restrict__ Wf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // oracle layout
+  if (i >= cout * cin * 9) return;
+  const int co = i / (cin * 9), r = i % (cin * 9), ci = r / 9, tap = r % 9;
+  const unsigned short h = to_bf16(W[i]);
+  Wg[(long long)co * 9 * cin + tap * cin + ci] = h;
+  Wf[(long long)ci * 9 * cout + (8 - tap) * cout + co] = h;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launch
+
+hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
+                    const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
+                    int W, int rows, hipStream_t s) {
+  const dim3 grid((W + 63) / 64, rows), blk(256);
+  // forward: layer l maps C_in(l) -> C_out(l); backward (the adjoint of
+  // layer l) maps C_out(l) -> C_in(l)
+  if (mode != kBwd) {
+    switch (layer) {
+      case 0: hipLaunchKernelGGL((conv_kernel<16, 32, kFwdAct>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
+      case 1: case 2: hipLaunchKernelGGL((conv_kernel<32, 32, kFwdAct>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
+      default: hipLaunchKernelGGL((conv_kernel<32, 16, kFwdLinear>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows);
+    }
+  } else {
+    switch (layer) {
+      case 1: case 2: hipLaunchKernelGGL((conv_kernel<32, 32, kBwd>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
+      case 3: hipLaunchKernelGGL((conv_kernel<16, 32, kBwd>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
+      default: return hipErrorInvalidValue;  // the input layer needs no input gradient
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
+                     int nchunks, int chunk, int H, int W, long long P, float* gradW, float* gradb,
+                     hipStream_t s) {
+  const int cin = layer == 0 ? 16 : 32, cout = layer == 3 ? 16 : 32;
+  const int tiles = (cout / 16) * (9 * cin / 16);
+  const dim3 grid((tiles + 3) / 4, nchunks), blk(256);
+  switch (layer) {
+    case 0: hipLaunchKernelGGL((wgrad_kernel<16, 32>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk); break;
+    case 1: case 2: hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk); break;
+    default: hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nw = cout * cin * 9;
+  hipLaunchKernelGGL(wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, s, partial, nchunks, cin,
+                     cout, gradW);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bgrad_kernel, dim3(cout), dim3(256), 0, s, dZ, P, cout, gradb);
+  return hipGetLastError();
+}
+
+hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
+                    unsigned short* X0, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((P * 16 + 255) / 256)), dim3(256), 0, s, planes,
+                     cin, scale, hw, P, X0);
+  return hipGetLastError();
+}
+
+hipError_t cnn_output(const float* Z4, long long P, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(output_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, Z4, P, out);
+  return hipGetLastError();
+}
+
+hipError_t cnn_loss(const float* Z4, const float* target, long long P, unsigned short* dZ4,
+                    double* partial, int nparts, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(loss_kernel, dim3(nparts), dim3(256), 0, s, Z4, target, P, dZ4, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, partial, nparts, P, loss);
+  return hipGetLastError();
+}
+
+hipError_t cnn_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float b1,
+                    float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta, m, v, grad, n, lr,
+                     b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t cnn_weights(const float* W, int cin, int cout, unsigned short* Wg, unsigned short* Wf,
+                       hipStream_t s) {
+  const int n = cout * cin * 9;
+  hipLaunchKernelGGL(weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, cin, cout, Wg, Wf);
+  return hipGetLastError();
+}
+
+}  // namespace pflb

@@ -325,13 +325,16 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
 //   H_1 = w [c.d_t(c1 u)/cs^2 + c.n 4 (1-phi) c1/W + A D_m (Keq c2 phi - c1 (1-phi))],
 //   H_2 = w [c.d_t(c2 u)/cs^2 - c.n 4 phi c2/W + A D_m (c1 (1-phi) - Keq c2 phi)],
 //   ~H_1 = -w D_m grad phi . grad psi = -~H_2
+// `xs` is an extra exchange per step carried the same way as ~H (h1 loses
+// w_i xs, h2 gains it, so c1 + c2 is untouched): the learned closure's
+// correction on a coarse grid, 0 otherwise.
 template <class LF, class T, class Emit>
 __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], const T (&dh2)[LF::Q],
                                  const Node<T>& s, const T (&n)[3], const T (&gphi)[3],
                                  const T (&gpsi)[3], const Flow<T>& fl, const T (&dJ1)[3],
-                                 const T (&dJ2)[3], Emit&& emit) {
+                                 const T (&dJ2)[3], Emit&& emit, T xs = T(0)) {
   const T M1 = P.A * s.Dm * (P.Keq * s.c2 * s.phi - s.c1 * s.omphi);
-  const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]);
+  const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]) + xs;
   const T fl1 = P.four_over_W * s.omphi * s.c1;
   const T fl2 = P.four_over_W * s.phi * s.c2;
   auto cu_of = [&](int i) {
@@ -367,12 +370,12 @@ __device__ inline void collide(const KParams<T>& P, const T (&df)[LF::Q], const 
                                const T (&dh1)[LF::Q], const T (&dh2)[LF::Q], const Node<T>& s,
                                const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
                                const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3],
-                               EF&& emit_f, EG&& emit_g, EH&& emit_h) {
+                               EF&& emit_f, EG&& emit_g, EH&& emit_h, T xs = T(0)) {
   T n[3];
   normal(P, gphi, n);
   collide_g<LG>(P, g, gphi, fl, emit_g);
   collide_f<LF>(P, df, s, n, fl, dJphi, emit_f);
-  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h);
+  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h, xs);
 }
 
 // In-place form (post-collision values written back into the arrays).

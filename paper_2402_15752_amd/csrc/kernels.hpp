@@ -25,9 +25,11 @@ constexpr int kVariants3D = 8;
 const char* step2d_variant_name(int v);
 const char* step3d_variant_name(int v);
 
+// closure: per-node extra exchange added to the auxiliary scalar source
+// (N FP32 values in node order), or null
 template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, hipStream_t stream);
+                         int variant, const float* closure, hipStream_t stream);
 
 // P: host copy of the lattice constants (grid, launch shape); Pdev: the same
 // constants in device memory, read by the kernel
@@ -59,6 +61,27 @@ hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* pre
 
 // tiles of an nx x ny lattice for a 2-D step variant
 int step2d_tiles(int nx, int ny, int variant);
+
+// ------------------------------------------------------- closure network
+// (cnn.hip) layer l = 0..3 maps C_in = 16, 32, 32, 32 to C_out = 32, 32, 32,
+// 16; activations NHWC BF16, P pixels of `rows` rows of width W, samples of
+// H rows stacked.  mode 0: leaky-ReLU forward, 1: linear forward, 2: the
+// adjoint of layer l (dZ of layer l in, dZ of layer l - 1 out).
+hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
+                    const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
+                    int W, int rows, hipStream_t s);
+hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
+                     int nchunks, int chunk, int H, int W, long long P, float* gradW, float* gradb,
+                     hipStream_t s);
+hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
+                    unsigned short* X0, hipStream_t s);
+hipError_t cnn_output(const float* Z4, long long P, float* out, hipStream_t s);
+hipError_t cnn_loss(const float* Z4, const float* target, long long P, unsigned short* dZ4,
+                    double* partial, int nparts, double* loss, hipStream_t s);
+hipError_t cnn_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float b1,
+                    float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t cnn_weights(const float* W, int cin, int cout, unsigned short* Wg, unsigned short* Wf,
+                       hipStream_t s);
 
 // equilibrium initialisation from FP64 staging arrays in device memory:
 // phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
 
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
-                          hipStream_t stream) {
+                          const float* closure, hipStream_t stream) {
   Geo2<Off> G;
   G.nx = P.nx;
   G.ny = P.ny;
@@ -53,6 +53,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.ntiles = G.tiles_x * ((P.ny + TY - 1) / TY);
   G.sS = Off(P.stride * (long long)sizeof(S));
   G.sT = Off(P.stride * (long long)sizeof(T));
+  G.closure = closure;
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
   hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off>), dim3(nblocks), dim3(TX * TY),
                      0, stream, src, dst, hist, fields, P, G);
@@ -70,38 +71,41 @@ const char* step2d_variant_name(int v) {
 
 template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, hipStream_t stream) {
+                         int variant, const float* closure, hipStream_t stream) {
   constexpr int M = kModeStep;
   using U = uint32_t;
   if (!fits_u32(L::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
       return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t>(src, dst, hist, fields, P,
-                                                                      stream);
-    return launch_variant<S, T, 128, 4, false, M, uint64_t>(src, dst, hist, fields, P, stream);
+                                                                      closure, stream);
+    return launch_variant<S, T, 128, 4, false, M, uint64_t>(src, dst, hist, fields, P, closure, stream);
   }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, kModeMacros, U>(src, dst, hist, fields, P, stream);
+    return launch_variant<S, T, 64, 4, false, kModeMacros, U>(src, dst, hist, fields, P, closure, stream);
   switch (variant) {
-    case 1: return launch_variant<S, T, 32, 8, false, M, U>(src, dst, hist, fields, P, stream);
-    case 2: return launch_variant<S, T, 32, 4, false, M, U>(src, dst, hist, fields, P, stream);
-    case 3: return launch_variant<S, T, 128, 4, false, M, U>(src, dst, hist, fields, P, stream);
-    case 4: return launch_variant<S, T, 64, 4, true, M, U>(src, dst, hist, fields, P, stream);
-    case 5: return launch_variant<S, T, 32, 8, true, M, U>(src, dst, hist, fields, P, stream);
-    case 6: return launch_variant<S, T, 32, 4, true, M, U>(src, dst, hist, fields, P, stream);
-    case 7: return launch_variant<S, T, 128, 4, true, M, U>(src, dst, hist, fields, P, stream);
-    default: return launch_variant<S, T, 64, 4, false, M, U>(src, dst, hist, fields, P, stream);
+    case 1: return launch_variant<S, T, 32, 8, false, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 2: return launch_variant<S, T, 32, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 3: return launch_variant<S, T, 128, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 4: return launch_variant<S, T, 64, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 5: return launch_variant<S, T, 32, 8, true, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 6: return launch_variant<S, T, 32, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 7: return launch_variant<S, T, 128, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
+    default: return launch_variant<S, T, 64, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
   }
 }
 
 template hipError_t launch_step2d<double, double>(const double*, double*, double*, double*,
-                                                  const KParams<double>&, int, int, hipStream_t);
+                                                  const KParams<double>&, int, int, const float*,
+                                                  hipStream_t);
 template hipError_t launch_step2d<float, float>(const float*, float*, float*, float*,
-                                                const KParams<float>&, int, int, hipStream_t);
+                                                const KParams<float>&, int, int, const float*,
+                                                hipStream_t);
 template hipError_t launch_step2d<__half, float>(const __half*, __half*, float*, float*,
-                                                 const KParams<float>&, int, int, hipStream_t);
+                                                 const KParams<float>&, int, int, const float*,
+                                                hipStream_t);
 template hipError_t launch_step2d<__hip_bfloat16, float>(const __hip_bfloat16*, __hip_bfloat16*,
                                                          float*, float*, const KParams<float>&, int,
-                                                         int, hipStream_t);
+                                                         int, const float*, hipStream_t);
 
 }  // namespace pflb

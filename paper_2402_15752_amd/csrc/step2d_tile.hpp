@@ -25,6 +25,7 @@ struct Geo2 {
   int tiles_x, ntiles;
   Off sS;  // bytes between two population planes
   Off sT;  // bytes between two history / field planes
+  const float* closure;  // per-node extra exchange (learned closure) or null
 };
 
 // One TX x TY tile of the fused 2-D step (moments, stencils, macros,
@@ -176,7 +177,8 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
         const Off t = target(i);
         st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
         st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
-      });
+      },
+      G.closure ? T(G.closure[y * nx + x]) : T(0));
 }
 
 }  // namespace pflb

@@ -56,17 +56,17 @@ def test_gradient_matches_finite_differences():
 
 def test_periodic_shift_equivariance_in_x():
     x, t, theta = small_case(4, W=8)
-    out, _ = C.forward(theta, x)
-    out_s, _ = C.forward(theta, np.roll(x, 3, axis=-1))
+    out = C.forward(theta, x)[0]
+    out_s = C.forward(theta, np.roll(x, 3, axis=-1))[0]
     np.testing.assert_allclose(np.roll(out, 3, axis=-1), out_s, rtol=1e-12, atol=1e-14)
 
 
 def test_zero_padding_in_y_is_per_sample():
     """Stacking samples along the batch axis must not couple them."""
     x, t, theta = small_case(5, B=3)
-    out, _ = C.forward(theta, x)
+    out = C.forward(theta, x)[0]
     for b in range(3):
-        ob, _ = C.forward(theta, x[b:b + 1])
+        ob = C.forward(theta, x[b:b + 1])[0]
         np.testing.assert_allclose(ob[0], out[b], rtol=1e-13, atol=1e-15)
 
 
@@ -106,3 +106,33 @@ def test_oracle_closure_term_closed_form():
     o2.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
     o2.step(1)
     np.testing.assert_allclose(o2.field("c1"), c1, rtol=0, atol=1e-15)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: even mantissa wins (1)
+    vals = np.array([1.0, 1 + 2.0**-8, 1 + 3 * 2.0**-8, 1 + 2.0**-9, -(1 + 2.0**-8), 3.14159, 1e-30])
+    want = np.array([1.0, 1.0, 1 + 2.0**-6, 1.0, -1.0, 3.140625, None], dtype=object)
+    got = C.bf16(vals)
+    for g, w in zip(got[:-1], want[:-1]):
+        assert g == w, (g, w)
+    assert abs(got[-1] - 1e-30) <= 1e-30 * 2.0**-8
+
+
+def test_bf16_storage_model_is_close_to_fp64():
+    """The BF16 storage model differs from the FP64 network by BF16-sized
+    amounts only (and equals it when every stored value is exact)."""
+    x, t, theta = small_case(6)
+    l64, g64 = C.loss_and_grad(theta, x, t)
+    l16, g16 = C.loss_and_grad(theta, x, t, storage="bf16")
+    assert abs(l16 - l64) <= 3e-2 * l64
+    assert np.linalg.norm(g16 - g64) <= 0.1 * np.linalg.norm(g64)
+    # exact case: inputs and weights representable, zero target and biases
+    th = C.bf16(theta) * 0
+    k = 0
+    for ci, co in C.LAYERS:
+        th[k:k + co * ci * 9] = C.bf16(theta[k:k + co * ci * 9] * 0 + 0.125)
+        k += co * ci * 9 + co
+    xx = np.ones_like(x)
+    o64 = C.forward(th, xx)[0]
+    o16 = C.forward(th, xx, storage="bf16")[0]
+    assert np.max(np.abs(o16 - o64)) <= 1e-2 * np.max(np.abs(o64))

@@ -1,0 +1,164 @@
+"""GPU tests of the closure network (BF16 MFMA forward / backward / Adam)
+against the FP64 oracle network, and of the closure hook in the 2-D step
+against the FP64 LB oracle.
+
+Tolerances.  Weights, activations and back-propagated gradients are stored
+in BF16 (8 significant bits).  Against the FP64 network the output carries
+~1e-2 relative error; the weight gradients grow by ~3x per layer towards
+the input (leaky-ReLU kinks flip where z is within BF16 noise of 0), up to
+~6e-2 on the first layer.  So each result is checked twice: against the
+oracle's BF16 storage model (same rounding points, FP64 arithmetic), which
+only FP32 accumulation order separates from the GPU -- 1e-2 -- and against
+the FP64 network -- 3e-2 (output), 1.2e-1 (gradients, per layer, relative
+L2).  The closure hook is plain FP64 / FP32 arithmetic: 1e-12 / 1e-5 as
+for the step itself.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cnn_ref as C
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cplb():
+    import torch
+
+    from paper_2402_15752_amd import cplb as L
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    L.library()
+    return L
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def setup_net(cplb, B, H, Wd, seed, cin=5):
+    import torch
+    rng = np.random.default_rng(seed)
+    theta = C.init_params(seed) * np.concatenate(
+        [np.full(C.num_params() - (16 * 32 * 9 + 16), 1.0), np.full(16 * 32 * 9 + 16, 5.0)])
+    theta += rng.normal(size=theta.size) * 0.02 * (np.arange(theta.size) % 7 == 0)
+    theta = theta.astype(np.float32).astype(np.float64)  # the GPU holds FP32 masters
+    planes = rng.normal(size=(B, cin, H, Wd))
+    scale = rng.uniform(0.5, 1.5, size=cin)
+    net = cplb.ClosureNet(B, H, Wd)
+    net.set_params(theta)
+    net.set_input_scale(scale)
+    x = np.zeros((B, 16, H, Wd))
+    x[:, :cin] = planes * scale[None, :, None, None]
+    # the GPU rounds the scaled inputs to BF16 before the first layer
+    x = x.astype(np.float32)
+    tp = torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous()
+    return net, theta, x, tp
+
+
+@pytest.mark.parametrize("B,H,Wd", [(2, 16, 48), (1, 12, 40), (3, 8, 64)])
+def test_forward_matches_oracle(cplb, B, H, Wd):
+    say(f"cnn forward B={B} H={H} W={Wd}")
+    net, theta, x, tp = setup_net(cplb, B, H, Wd, seed=B * 100 + H)
+    out = net.forward(tp).cpu().numpy()
+    ref_out = C.forward(theta, x)[0]
+    ref16 = C.forward(theta, x, storage="bf16")[0]
+    e, e16 = rel(out, ref_out), rel(out, ref16)
+    say(f"  rel L2 vs fp64 {e:.2e}, vs bf16 storage model {e16:.2e}")
+    assert np.all(np.isfinite(out)) and e <= 3e-2 and e16 <= 1e-2, (e, e16)
+    net.close()
+
+
+@pytest.mark.parametrize("B,H,Wd", [(2, 16, 48), (1, 12, 40)])
+def test_gradients_match_oracle(cplb, B, H, Wd):
+    import torch
+    say(f"cnn gradients B={B} H={H} W={Wd}")
+    net, theta, x, tp = setup_net(cplb, B, H, Wd, seed=7 + H)
+    rng = np.random.default_rng(11)
+    target = rng.normal(size=(B, H, Wd)) * 0.5
+    net.forward(tp)
+    loss = net.backward(torch.tensor(target, dtype=torch.float32, device="cuda").contiguous())
+    g = net.grads()
+    lref, gref = C.loss_and_grad(theta, x, target)
+    l16, g16 = C.loss_and_grad(theta, x, target, storage="bf16")
+    say(f"  loss {loss:.6e} oracle {lref:.6e} bf16 model {l16:.6e}")
+    assert abs(loss - lref) <= 3e-2 * lref and abs(loss - l16) <= 1e-3 * l16
+    k = 0
+    for n, (ci, co) in enumerate(C.LAYERS):
+        nw = co * ci * 9
+        ew, ew16 = rel(g[k:k + nw], gref[k:k + nw]), rel(g[k:k + nw], g16[k:k + nw])
+        eb, eb16 = (rel(g[k + nw:k + nw + co], gref[k + nw:k + nw + co]),
+                    rel(g[k + nw:k + nw + co], g16[k + nw:k + nw + co]))
+        say(f"  layer {n}: dW {ew:.2e} ({ew16:.2e} vs bf16 model) db {eb:.2e} ({eb16:.2e})")
+        assert ew <= 1.2e-1 and eb <= 1.2e-1, (n, ew, eb)
+        assert ew16 <= 1e-2 and eb16 <= 1e-2, (n, ew16, eb16)
+        k += nw + co
+    net.close()
+
+
+def test_training_fits_a_teacher(cplb):
+    """Adam on the GPU fits the output of a different (teacher) parameter set
+    on a fixed batch: the FP64 loss falls by more than 10x."""
+    import torch
+    B, H, Wd = 2, 16, 32
+    rng = np.random.default_rng(3)
+    planes = rng.normal(size=(B, 5, H, Wd))
+    x = np.zeros((B, 16, H, Wd))
+    x[:, :5] = planes
+    teacher = C.init_params(99)
+    teacher[-(16 * 32 * 9 + 16):] *= 5.0
+    target = C.forward(teacher, x)[0]
+    net = cplb.ClosureNet(B, H, Wd, seed=5)
+    tp = torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous()
+    tt = torch.tensor(target, dtype=torch.float32, device="cuda").contiguous()
+    losses = []
+    for it in range(300):
+        net.forward(tp)
+        losses.append(net.backward(tt))
+        net.adam(lr=2e-3)
+    say(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.1 * losses[0]
+    net.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_closure_hook_matches_oracle(cplb, precision, tol):
+    """Random fields, walls, and a random per-node closure exchange: the
+    GPU step with the closure equals the oracle step with the same closure."""
+    import torch
+    p = W.params(nx=67, ny=37, periodic=(1, 0, 1), precision=precision, sigma=2e-3, rho1=3.0,
+                 rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07, D2=0.02, Keq=0.6,
+                 A=0.4, g=(0.0, -2e-5, 0.0), rho_ref=1.5,
+                 ref_f=W.phase_reference(precision))
+    f = W.random_fields(p, seed=21)
+    s = (np.random.default_rng(4).normal(size=W.shape_of(p)) * 1e-3).astype(np.float32)
+    g = cplb.Lattice(p)
+    g.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    ts = torch.tensor(s, device="cuda").contiguous()
+    g.set_closure(ts)
+    o = ref.Oracle(p)
+    o.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    o.set_closure(s.astype(np.float64))
+    g.step(3)
+    o.step(3)
+    for k in ("phi", "c1", "c2", "ux", "uy", "p"):
+        a, b = g.field(k).cpu().numpy(), o.field(k)
+        scale = max(np.linalg.norm(b), np.linalg.norm(b - b.mean()))
+        e = np.linalg.norm(a - b) / scale
+        assert e <= tol, (k, e)
+    # the closure really acts: switching it off changes c1 by ~3 s per node
+    g2 = cplb.Lattice(p)
+    g2.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    g2.step(3)
+    d = g.field("c1").cpu().numpy() - g2.field("c1").cpu().numpy()
+    assert np.abs(d).max() > 1e-4
+    r, r2 = g.reduce(), g2.reduce()
+    assert abs(r["sum_c"] - r2["sum_c"]) <= 1e-5 * abs(r2["sum_c"])
