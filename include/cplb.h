@@ -214,6 +214,13 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
 int cplb_batch_init_sdf(cplb_batch_t* b, int icase, const double* l, double c1_a, double c1_b,
                         double c2_a, double c2_b);
 
+/* Initial state of every case from device FP32 planes in the layout of
+ * cplb_batch_gather_fields (nplanes planes per case; planes iphi, ic1, ic2
+ * hold phi, c1, c2; u = p = 0): equilibria and history as cplb_init_fields.
+ * Asynchronous. */
+int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes, int iphi,
+                           int ic1, int ic2);
+
 /* Advance every case nsteps >= 0 steps.  Asynchronous; a caller may capture
  * the launches in a HIP graph. */
 int cplb_batch_step(cplb_batch_t* b, int64_t nsteps);
@@ -226,6 +233,23 @@ int cplb_batch_read_field(cplb_batch_t* b, int icase, int field, void* dev_dst, 
 
 /* Reductions of one case, as cplb_reduce (out[7] = batch step counter). */
 int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]);
+
+/* Nodes of all cases together (the length of a per-node batch buffer). */
+int64_t cplb_batch_num_nodes(const cplb_batch_t* b);
+
+/* Learned closure for every case (as cplb_set_closure): dev_s (device, FP32)
+ * holds the cases' per-node values one after the other in case order,
+ * cplb_batch_num_nodes values; NULL switches it off.  The buffer stays the
+ * caller's; its contents may change between steps.  Synchronises. */
+int cplb_batch_set_closure(cplb_batch_t* b, const float* dev_s);
+
+/* Fields fields[0..nf) (CPLB_FIELD_*) of every case at the current level
+ * into dev_dst (device, FP32).  Case c owns nplanes >= nf planes of its N
+ * values, starting at nplanes times the number of nodes of the cases
+ * before it; its first nf planes are written, the others left as they are
+ * (room for planes the caller fills once).  Asynchronous. */
+int cplb_batch_gather_fields(cplb_batch_t* b, const int* fields, int nf, int nplanes,
+                             float* dev_dst);
 
 /* Size classes: number, class of a case, cases in a class, and the 2-D
  * step variant (cplb_variant_name of a D2Q9 lattice names it) each class
@@ -293,6 +317,16 @@ int cplb_cnn_get_grads(cplb_cnn_t* c, float* host_grad);
 /* One Adam step on the last gradients (bias-corrected), then the BF16
  * weight copies are refreshed.  Asynchronous. */
 int cplb_cnn_adam(cplb_cnn_t* c, float lr, float beta1, float beta2, float eps);
+
+/* The forward output is multiplied by `scale` (default 1): the network is
+ * trained on targets divided by it. */
+int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale);
+
+/* Block average of nsamples fine planes (H f x W f each, device FP32) onto
+ * coarse planes (H x W, device FP32): the restriction of fine-grid fields
+ * to the coarse grid.  Asynchronous on hip_stream. */
+int cplb_cnn_restrict(void* hip_stream, const float* dev_fine, int nsamples, int H, int W, int f,
+                      float* dev_coarse);
 
 const char* cplb_cnn_last_error(const cplb_cnn_t* c);
 void cplb_cnn_destroy(cplb_cnn_t* c);

@@ -38,7 +38,9 @@ EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init
            "cplb_cnn_num_params", "cplb_cnn_workspace_bytes", "cplb_cnn_create",
            "cplb_cnn_set_params", "cplb_cnn_init_params", "cplb_cnn_get_params",
            "cplb_cnn_set_input_scale", "cplb_cnn_forward", "cplb_cnn_backward",
-           "cplb_cnn_get_grads", "cplb_cnn_adam", "cplb_cnn_last_error", "cplb_cnn_destroy")
+           "cplb_cnn_get_grads", "cplb_cnn_adam", "cplb_cnn_last_error", "cplb_cnn_destroy",
+           "cplb_batch_num_nodes", "cplb_batch_set_closure", "cplb_batch_gather_fields",
+           "cplb_cnn_set_output_scale", "cplb_cnn_restrict", "cplb_batch_init_planes")
 
 
 class cplb_params(ctypes.Structure):
@@ -138,6 +140,13 @@ def library():
         L.cplb_cnn_last_error.restype = ctypes.c_char_p
         L.cplb_cnn_destroy.argtypes = [vp]
         L.cplb_cnn_destroy.restype = None
+        L.cplb_batch_num_nodes.argtypes = [vp]
+        L.cplb_batch_num_nodes.restype = ctypes.c_int64
+        L.cplb_batch_set_closure.argtypes = [vp, vp]
+        L.cplb_batch_gather_fields.argtypes = [vp, ctypes.POINTER(i32), i32, i32, vp]
+        L.cplb_cnn_set_output_scale.argtypes = [vp, ctypes.c_float]
+        L.cplb_batch_init_planes.argtypes = [vp, vp, i32, i32, i32, i32]
+        L.cplb_cnn_restrict.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         _lib = L
     return _lib
 
@@ -456,6 +465,21 @@ def cplb_batch_reduce(b, icase: int):
     return out, rc
 
 
+def cplb_batch_num_nodes(b) -> int:
+    return library().cplb_batch_num_nodes(b)
+
+
+def cplb_batch_set_closure(b, dev_ptr):
+    _bcheck(b, library().cplb_batch_set_closure(b, None if dev_ptr is None
+                                                else ctypes.c_void_p(dev_ptr)))
+
+
+def cplb_batch_gather_fields(b, field_ids, nplanes, dev_ptr):
+    arr = (ctypes.c_int * len(field_ids))(*field_ids)
+    _bcheck(b, library().cplb_batch_gather_fields(b, arr, len(field_ids), nplanes,
+                                                  ctypes.c_void_p(dev_ptr)))
+
+
 def cplb_batch_num_classes(b) -> int:
     return library().cplb_batch_num_classes(b)
 
@@ -534,6 +558,15 @@ class Batch:
         cplb_batch_init_sdf(self._b, icase, l, float(c1[0]), float(c1[1]), float(c2[0]),
                             float(c2[1]))
 
+    def init_planes(self, planes, nplanes, iphi=0, ic1=1, ic2=2):
+        """Equilibrium initial state of every case from a float32 device
+        buffer in the gather layout (u = p = 0)."""
+        assert planes.dtype == self.torch.float32 and planes.is_contiguous()
+        assert planes.numel() == self.num_nodes * nplanes
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        _bcheck(self._b, library().cplb_batch_init_planes(self._b, ctypes.c_void_p(planes.data_ptr()),
+                                                          nplanes, iphi, ic1, ic2))
+
     def step(self, n=1):
         cplb_batch_step(self._b, n)
 
@@ -563,6 +596,43 @@ class Batch:
         r = dict(zip(keys, out.tolist()))
         r["rc"] = rc
         return r
+
+    @property
+    def num_nodes(self):
+        return cplb_batch_num_nodes(self._b)
+
+    def set_closure(self, s):
+        """Per-node extra exchange of every case (float32 device tensor of
+        num_nodes values, cases one after the other), or None; kept alive
+        while set."""
+        if s is None:
+            cplb_batch_set_closure(self._b, None)
+            self._closure = None
+            return
+        assert s.dtype == self.torch.float32 and s.is_contiguous() and s.numel() == self.num_nodes
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        cplb_batch_set_closure(self._b, s.data_ptr())
+        self._closure = s
+
+    def gather(self, names, out=None, nplanes=None):
+        """Fields `names` of every case into one float32 device tensor: case c
+        owns `nplanes` (default len(names)) planes of its nodes, the first
+        len(names) written.  With cases of equal size the result is shaped
+        [ncases, nplanes, ny, nx]."""
+        torch = self.torch
+        nplanes = nplanes or len(names)
+        n = self.num_nodes * nplanes
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=self.device)
+        assert out.numel() == n and out.dtype == torch.float32 and out.is_contiguous()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        cplb_batch_gather_fields(self._b, [FIELDS[k] for k in names], nplanes, out.data_ptr())
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        shapes = {(p["ny"], p["nx"]) for p in self.params}
+        if len(shapes) == 1:
+            ny, nx = shapes.pop()
+            return out.view(self.n, nplanes, ny, nx)
+        return out
 
     def classes(self):
         """[(cases in class, variant index)] per size class."""
@@ -727,3 +797,24 @@ class ClosureNet:
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         cplb_cnn_adam(self._c, lr, beta1, beta2, eps)
+
+    def set_output_scale(self, scale):
+        _ccheck(self._c, library().cplb_cnn_set_output_scale(self._c, float(scale)))
+
+
+def restrict(fine, factor, out=None, stream=None):
+    """Block average of fine planes [n, H f, W f] (float32 device tensor)
+    onto [n, H, W] on the GPU (cplb_cnn_restrict)."""
+    import torch
+    n, Hf, Wf = (int(v) for v in fine.shape)
+    H, W = Hf // factor, Wf // factor
+    assert H * factor == Hf and W * factor == Wf and fine.dtype == torch.float32
+    fine = fine.contiguous()
+    if out is None:
+        out = torch.empty((n, H, W), dtype=torch.float32, device=fine.device)
+    s = stream if stream is not None else torch.cuda.current_stream(fine.device)
+    rc = library().cplb_cnn_restrict(ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(fine.data_ptr()),
+                                     n, H, W, factor, ctypes.c_void_p(out.data_ptr()))
+    if rc:
+        raise CplbError(rc, "cplb_cnn_restrict failed")
+    return out

@@ -104,6 +104,8 @@ int validate_batch(const cplb_params* prm, int n, char* err, size_t errn) {
 struct cplb_batch {
   int n;
   int precision;
+  long long nodes;  // all nodes of all cases
+  long long max_n;  // nodes of the largest case
   std::vector<cplb_params> prm;
   std::vector<Geometry> G;
   std::vector<KParams<double>> k64;
@@ -245,6 +247,8 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
   cplb_batch_t* b = new (std::nothrow) cplb_batch_t();
   if (!b) return CPLB_ENOMEM;
   b->n = ncases;
+  b->nodes = 0;
+  b->max_n = 0;
   b->precision = prm[0].precision;
   b->stream = (hipStream_t)hip_stream;
   b->ws = (char*)dev_workspace;
@@ -271,6 +275,10 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
     D.wall_y = prm[c].periodic[1] ? 0 : 1;
     D.sS = (unsigned)(G.stride * G.s_pop);
     D.sT = (unsigned)(G.stride * G.s_cmp);
+    D.closure = nullptr;
+    D.out_off = b->nodes;
+    b->nodes += G.n;
+    if (G.n > b->max_n) b->max_n = G.n;
     b->case_cls[c] = class_of(prm[c].nx);
   }
   // cases grouped by class, and every class's tile prefix for every variant
@@ -388,6 +396,55 @@ int cplb_batch_init_sdf(cplb_batch_t* b, int icase, const double* l, double c1_a
   return CPLB_OK;
 }
 
+int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes, int iphi,
+                           int ic1, int ic2) {
+  if (!b) return CPLB_EINVAL;
+  if (!dev_planes || nplanes < 1 || iphi < 0 || ic1 < 0 || ic2 < 0 || iphi >= nplanes ||
+      ic1 >= nplanes || ic2 >= nplanes)
+    return set_err(b, CPLB_EINVAL, "invalid plane layout (%d planes)", nplanes);
+  const double cab[4] = {0, 0, 0, 0};
+  for (int c = 0; c < b->n; ++c) {
+    const Geometry& G = b->G[c];
+    BatchCase& D = b->cases[c];
+    double* stage = (double*)D.lat[b->cur ^ 1];  // idle lattice: 3 N doubles fit
+    const float* base = dev_planes + D.out_off * nplanes;
+    const int which[3] = {iphi, ic1, ic2};
+    for (int k = 0; k < 3; ++k) {
+      const int rc = hip_check(b, launch_convert<float>(base + (size_t)which[k] * G.n, stage + k * G.n,
+                                                        CPLB_DTYPE_F64, G.n, b->stream),
+                               "init staging");
+      if (rc) return rc;
+    }
+    void* lat = (void*)D.lat[b->cur];
+    const double W = b->prm[c].W;
+    hipError_t e;
+    switch (b->precision) {
+      case CPLB_F64:
+        e = launch_init<double, double>(2, (double*)lat, (double*)D.hist, stage, stage + G.n,
+                                        stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k64[c],
+                                        b->stream);
+        break;
+      case CPLB_F32:
+        e = launch_init<float, float>(2, (float*)lat, (float*)D.hist, stage, stage + G.n,
+                                      stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k32[c],
+                                      b->stream);
+        break;
+      case CPLB_F32_S16F:
+        e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist, stage, stage + G.n,
+                                       stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k32[c],
+                                       b->stream);
+        break;
+      default:
+        e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist, stage,
+                                               stage + G.n, stage + 2 * G.n, nullptr, nullptr, 0, W,
+                                               cab, b->k32[c], b->stream);
+    }
+    const int rc = hip_check(b, e, "init kernel");
+    if (rc) return rc;
+  }
+  return CPLB_OK;
+}
+
 int cplb_batch_step(cplb_batch_t* b, int64_t nsteps) {
   if (!b) return CPLB_EINVAL;
   if (nsteps < 0) return set_err(b, CPLB_EINVAL, "nsteps must be >= 0");
@@ -445,6 +502,42 @@ int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]) {
   out[7] = (double)b->step;
   if (out[6] > 0) return set_err(b, CPLB_EUNSTABLE, "non-finite values in case %d", icase);
   return CPLB_OK;
+}
+
+int cplb_batch_set_closure(cplb_batch_t* b, const float* dev_s) {
+  if (!b) return CPLB_EINVAL;
+  for (int c = 0; c < b->n; ++c) b->cases[c].closure = dev_s ? dev_s + b->cases[c].out_off : nullptr;
+  int rc = hip_check(b, hipMemcpyAsync(b->d_cases, b->cases.data(), b->n * sizeof(BatchCase),
+                                       hipMemcpyHostToDevice, b->stream), "closure table upload");
+  if (!rc) rc = hip_check(b, hipStreamSynchronize(b->stream), "closure table synchronise");
+  return rc;
+}
+
+int64_t cplb_batch_num_nodes(const cplb_batch_t* b) { return b ? b->nodes : -1; }
+
+int cplb_batch_gather_fields(cplb_batch_t* b, const int* fields, int nf, int nplanes,
+                             float* dev_dst) {
+  if (!b) return CPLB_EINVAL;
+  if (!fields || nf < 1 || nf > CPLB_NFIELDS || !dev_dst)
+    return set_err(b, CPLB_EINVAL, "gather needs 1..%d field ids and a destination", CPLB_NFIELDS);
+  if (nplanes < nf) return set_err(b, CPLB_EINVAL, "nplanes %d below the %d fields", nplanes, nf);
+  int ids[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < nf; ++k) {
+    if (fields[k] < 0 || fields[k] >= CPLB_NFIELDS)
+      return set_err(b, CPLB_EINVAL, "unknown field id %d", fields[k]);
+    ids[k] = fields[k];
+  }
+  for (int cls = 0; cls < kBatchClasses; ++cls) {
+    const int rc = hip_check(b, run_class(b, cls, kModeMacros, 0), "batch macros kernel");
+    if (rc) return rc;
+  }
+  const hipError_t e =
+      b->precision == CPLB_F64
+          ? launch_batch_gather<double>(b->d_cases, b->n, b->max_n, ids, nf, nplanes, dev_dst,
+                                        b->stream)
+          : launch_batch_gather<float>(b->d_cases, b->n, b->max_n, ids, nf, nplanes, dev_dst,
+                                       b->stream);
+  return hip_check(b, e, "field gather");
 }
 
 int cplb_batch_num_classes(const cplb_batch_t* b) { return b ? kBatchClasses : 0; }

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, 
   G.ntiles = G.tiles_x * ((G.ny + TY - 1) / TY);
   G.sS = D->sS;
   G.sT = D->sT;
-  G.closure = nullptr;
+  G.closure = D->closure;
   const S* src = (const S*)D->lat[parity];
   S* dst = (S*)D->lat[parity ^ 1];
   const KParams<T>& P = *(const KParams<T>*)(kps + c);
@@ -90,6 +90,42 @@ hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* pre
     default: return launch_b<S, T, 64, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
   }
 }
+
+namespace {
+
+struct GatherIds {
+  int id[9];
+};
+
+template <class T>
+__global__ void gather_kernel(CPtr<BatchCase> cases, GatherIds ids, int nplanes,
+                              float* __restrict__ dst) {
+  const int c = blockIdx.y, f = blockIdx.z;
+  CPtr<BatchCase> D = cases + c;
+  const long long n = (long long)D->nx * D->ny;
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* src = (const T*)((const char*)D->fields + (size_t)ids.id[f] * D->sT);
+  dst[D->out_off * nplanes + f * n + i] = (float)src[i];
+}
+
+}  // namespace
+
+template <class T>
+hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max_n,
+                               const int (&ids)[9], int nf, int nplanes, float* dst,
+                               hipStream_t stream) {
+  GatherIds g;
+  for (int k = 0; k < 9; ++k) g.id[k] = ids[k];
+  const dim3 grid((unsigned)((max_n + 255) / 256), ncases, nf);
+  hipLaunchKernelGGL(gather_kernel<T>, grid, dim3(256), 0, stream, (CPtr<BatchCase>)cases, g, nplanes, dst);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_gather<double>(const BatchCase*, int, long long, const int (&)[9],
+                                                int, int, float*, hipStream_t);
+template hipError_t launch_batch_gather<float>(const BatchCase*, int, long long, const int (&)[9],
+                                               int, int, float*, hipStream_t);
 
 #define PFLB_BATCH_INST(S, T)                                                                    \
   template hipError_t launch_batch2d<S, T>(const BatchCase*, const int*, const int*, int, int,   \

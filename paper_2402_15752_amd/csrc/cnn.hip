@@ -205,10 +205,27 @@ __global__ void pack_kernel(const float* __restrict__ planes, int cin, const flo
   X0[i] = c < cin ? to_bf16(scale[c] * planes[(s * cin + c) * hw + q]) : (unsigned short)0;
 }
 
-// out[p] = Z4[p][0]
-__global__ void output_kernel(const float* __restrict__ Z4, long long P, float* __restrict__ out) {
+// out[p] = scale * Z4[p][0]
+__global__ void output_kernel(const float* __restrict__ Z4, long long P, float scale,
+                              float* __restrict__ out) {
   const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (p < P) out[p] = Z4[p * 16];
+  if (p < P) out[p] = scale * Z4[p * 16];
+}
+
+__global__ void restrict_kernel(const float* __restrict__ fine, int nsamples, int H, int W, int f,
+                                float* __restrict__ coarse) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long n = (long long)nsamples * H * W;
+  if (i >= n) return;
+  const long long s = i / ((long long)H * W);
+  const int r = (int)(i % ((long long)H * W));
+  const int y = r / W, x = r % W;
+  const long long Wf = (long long)W * f;
+  const float* base = fine + s * (long long)H * f * Wf;
+  float acc = 0.f;
+  for (int j = 0; j < f; ++j)
+    for (int k = 0; k < f; ++k) acc += base[(long long)(f * y + j) * Wf + f * x + k];
+  coarse[i] = acc / (float)(f * f);
 }
 
 // loss partials (FP64) and dZ4 = d(mean (z - t)^2) / dz4 in BF16 (channel 0)
@@ -329,8 +346,17 @@ hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long 
   return hipGetLastError();
 }
 
-hipError_t cnn_output(const float* Z4, long long P, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(output_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, Z4, P, out);
+hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(output_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, Z4, P,
+                     scale, out);
+  return hipGetLastError();
+}
+
+hipError_t cnn_restrict(const float* fine, int nsamples, int H, int W, int f, float* coarse,
+                        hipStream_t s) {
+  const long long n = (long long)nsamples * H * W;
+  hipLaunchKernelGGL(restrict_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fine,
+                     nsamples, H, W, f, coarse);
   return hipGetLastError();
 }
 

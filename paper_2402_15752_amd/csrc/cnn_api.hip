@@ -97,6 +97,7 @@ struct cplb_cnn {
   CnnLayout L;
   long long used_P;  // pixels of the last forward
   int adam_t;
+  float out_scale;
   char err[512];
   template <class X>
   X* at(size_t off) const {
@@ -165,6 +166,7 @@ int cplb_cnn_create(int nsamples, int H, int W, void* dev_workspace, size_t byte
   c->L = cnn_layout(c->P);
   c->used_P = 0;
   c->adam_t = 0;
+  c->out_scale = 1.f;
   c->err[0] = 0;
   const float one[16] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
   rc = hip_check(c, hipMemcpyAsync(c->at<float>(c->L.scale), one, sizeof(one),
@@ -257,8 +259,8 @@ int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int c
   }
   c->used_P = P;
   if (dev_out)
-    rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, dev_out, c->stream),
-                   "output copy");
+    rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, c->out_scale, dev_out,
+                                 c->stream), "output copy");
   return rc;
 }
 
@@ -310,6 +312,21 @@ int cplb_cnn_adam(cplb_cnn_t* c, float lr, float beta1, float beta2, float eps) 
                                  bc2, c->stream), "adam");
   if (!rc) rc = refresh_weights(c);
   return rc;
+}
+
+int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale) {
+  if (!c || !std::isfinite(scale)) return CPLB_EINVAL;
+  c->out_scale = scale;
+  return CPLB_OK;
+}
+
+int cplb_cnn_restrict(void* hip_stream, const float* dev_fine, int nsamples, int H, int W, int f,
+                      float* dev_coarse) {
+  if (!dev_fine || !dev_coarse || nsamples < 1 || H < 1 || W < 1 || f < 1) return CPLB_EINVAL;
+  return cnn_restrict(dev_fine, nsamples, H, W, f, dev_coarse, (hipStream_t)hip_stream) ==
+                 hipSuccess
+             ? CPLB_OK
+             : CPLB_EHIP;
 }
 
 const char* cplb_cnn_last_error(const cplb_cnn_t* c) { return c ? c->err : "null network"; }

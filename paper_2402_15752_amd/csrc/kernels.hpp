@@ -47,6 +47,8 @@ struct BatchCase {
   int wall_x, wall_y;  // 1: half-way bounce-back walls on both faces
   unsigned int sS;     // bytes between two population planes
   unsigned int sT;     // bytes between two history / field planes
+  const float* closure;  // per-node extra exchange of this case, or null
+  long long out_off;     // first value of this case in a gathered field buffer
 };
 
 // One step (or the field read-out in kModeMacros) of every case of one size
@@ -62,6 +64,15 @@ hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* pre
 // tiles of an nx x ny lattice for a 2-D step variant
 int step2d_tiles(int nx, int ny, int variant);
 
+// Copy fields `ids[0..nf)` of every case (its field planes must be current)
+// into dst as FP32: case c starts at dst[out_off(c) * nplanes] and holds
+// nplanes >= nf planes of its N values, the first nf of them written.
+// max_n: the largest N of a case.
+template <class T>
+hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max_n,
+                               const int (&ids)[9], int nf, int nplanes, float* dst,
+                               hipStream_t stream);
+
 // ------------------------------------------------------- closure network
 // (cnn.hip) layer l = 0..3 maps C_in = 16, 32, 32, 32 to C_out = 32, 32, 32,
 // 16; activations NHWC BF16, P pixels of `rows` rows of width W, samples of
@@ -75,7 +86,10 @@ hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* d
                      hipStream_t s);
 hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
                     unsigned short* X0, hipStream_t s);
-hipError_t cnn_output(const float* Z4, long long P, float* out, hipStream_t s);
+hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s);
+// block average: coarse[s][y][x] = mean of fine[s][f y + j][f x + i], 0 <= i, j < f
+hipError_t cnn_restrict(const float* fine, int nsamples, int H, int W, int f, float* coarse,
+                        hipStream_t s);
 hipError_t cnn_loss(const float* Z4, const float* target, long long P, unsigned short* dZ4,
                     double* partial, int nparts, double* loss, hipStream_t s);
 hipError_t cnn_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float b1,
