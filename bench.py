@@ -33,22 +33,25 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44915524, "write": 43041543, "src": "79b503c127b86ec7"},
-    "rising_droplet_256c_f32": {"read": 3683998782, "write": 3200334112, "src": "79b503c127b86ec7"},
-    "rising_droplet_256c_f32_s16f": {"read": 2475879219, "write": 1756400432,
-                                     "src": "79b503c127b86ec7"},
+    "rising_bubble_256x1024_f32": {"read": 44993460, "write": 43069479, "src": "c33950995b5579c8"},
+    "rising_droplet_256c_f32": {"read": 3682441023, "write": 3201391232, "src": "c33950995b5579c8"},
+    "rising_droplet_256c_f32_s16f": {"read": 2476021953, "write": 1756257781,
+                                     "src": "c33950995b5579c8"},
 }
+
+
+# the sources that define the single-lattice step kernels and their launch
+STEP_SOURCES = ("addr.hpp", "common.hpp", "step2d.hip", "step2d_tile.hpp", "step3d.hip")
 
 
 def kernel_source_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_2402_15752_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in STEP_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -172,6 +175,19 @@ def time_batch(steps, warmup, tune_steps=5):
             "clamped_diffusivities": len(sw["clamps"]), "nonfinite_sampled": nonfinite}
 
 
+def closure_speedup():
+    """The learned closure's side of the metric: trained on the GPU from
+    fine-grid runs (64 static-drop cases, 64x64 coarse vs 256x256 fine,
+    200 coarse steps), evaluated on 16 held-out cases.  Reports the median
+    (c1, c2) relative L2 error against the restricted fine run with and
+    without the closure, and the wall time of the closure-corrected coarse
+    run against the fine run (same cases, same physical time)."""
+    from paper_2402_15752_amd import closure as CL
+    r = CL.experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), seed=1)
+    r.pop("net")
+    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+
+
 def cpu_baseline(w, seconds=25.0):
     """The FP64 CPU oracle, untuned, on a bounded sample of the same workload:
     a fixed number of steps sized to ~10-30 s of CPU work."""
@@ -201,7 +217,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="rising_bubble_256x1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D side measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3-D, batch and closure side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (5 launches): the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -277,6 +294,7 @@ def main():
             del w3
         out["also_3d_256c"] = extra
         out["also_batch_512"] = time_batch(40, 5)
+        out["closure"] = closure_speedup()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -125,7 +125,9 @@ def generate(cases, steps, stream=None, log=None, net=None, skip=5):
     target is the exchange part of its growth over one coarse step,
     s_k = (dE_c1 - dE_c2) / 2 with dE = E_k+1 - E_k: the per-node exchange
     that, applied at step k, removes as much of the new error as an
-    exchange (h1 -> h2, c1 + c2 kept) can.  Inputs are the coarse state at
+    exchange (h1 -> h2, c1 + c2 kept) can.  With the closure running, the
+    exchange it applied at step k is added: the target stays the whole
+    exchange, not the residual.  Inputs are the coarse state at
     t_k, as the closure sees it when it runs.  The first `skip` steps are
     dropped."""
     import torch
@@ -161,6 +163,9 @@ def generate(cases, steps, stream=None, log=None, net=None, skip=5):
             e_new = x[:, 1:3] - fine[:, 1:3]
             d = e_new - err
             Y[k] = 0.5 * (d[:, 0] - d[:, 1])
+            if s is not None:
+                # the exchange already applied is part of the one wanted
+                Y[k] += s.view(n, nc, nc)
             err = e_new
         if log and (k + 1) % max(1, steps // 4) == 0:
             torch.cuda.synchronize()
@@ -175,14 +180,18 @@ def generate(cases, steps, stream=None, log=None, net=None, skip=5):
             Y.reshape((steps - skip) * n, nc, nc))
 
 
-def train(X, Y, iters=1500, batch=32, lr=2e-3, seed=0, log=None, net=None, capacity=64):
+def train(X, Y, iters=1500, batch=32, lr=2e-3, seed=0, log=None, net=None, capacity=64,
+          scale=None):
     """Fit the closure network to (X, Y) on the GPU (minibatch Adam, FP64 loss).
-    Returns (net, scale, losses); the network's output is scaled back by
-    `scale`.  The network is built for up to max(batch, capacity) samples per
-    call (the coarse cases it will drive at once)."""
+    Returns (net, scale, losses); the network learns Y / scale (scale: the
+    standard deviation of Y unless given, as when training continues) and
+    its output is scaled back by `scale`.  The network is built for up to
+    max(batch, capacity) samples per call (the coarse cases it will drive at
+    once)."""
     import torch
     ns, nc = X.shape[0], X.shape[-1]
-    scale = float(Y.std().item()) or 1.0
+    if scale is None:
+        scale = float(Y.std().item()) or 1.0
     Yn = (Y / scale).contiguous()
     if net is None:
         net = cplb.ClosureNet(max(batch, capacity), nc, nc, seed=seed + 1)
@@ -292,11 +301,11 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
     train_cases = draw_cases(n_train, seed=seed, nc=nc)
     test_cases = draw_cases(n_test, seed=seed + 1000, nc=nc)
     X, Y = generate(train_cases, steps=steps, log=log)
-    net, _, l1 = train(X, Y, iters=iters[0], batch=batch, seed=seed, log=log,
-                       capacity=max(n_train, n_test))
+    net, scale, l1 = train(X, Y, iters=iters[0], batch=batch, seed=seed, log=log,
+                           capacity=max(n_train, n_test))
     X2, Y2 = generate(train_cases, steps=steps, net=net)
     net, _, l2 = train(torch.cat([X, X2]), torch.cat([Y, Y2]), iters=iters[1], batch=batch,
-                       seed=seed + 1, log=log, net=net)
+                       seed=seed + 1, log=log, net=net, scale=scale)
     del X, Y, X2, Y2
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -311,5 +320,6 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
         t_fine_ms=ev["t_fine"] * 1e3, t_coarse_ms=ev["t_coarse"] * 1e3,
         t_closure_ms=ev["t_closure"] * 1e3,
         speedup_closure_vs_fine=ev["t_fine"] / max(ev["t_closure"], 1e-12),
-        train_s=t_train, loss_first=float(l1[0]), loss_last=float(np.mean(l2[-50:])),
+        train_s=t_train, loss_first=float(np.mean(l1[:50])), loss_round1=float(np.mean(l1[-50:])),
+        loss_last=float(np.mean(l2[-50:])),
         net=net)

@@ -173,3 +173,96 @@ def test_full_sweep_sampled_cases(cplb):
         for f in ("phi", "c1", "c2", "ux", "uy", "p"):
             assert np.array_equal(b.field(k, f).cpu().numpy(), g.field(f).cpu().numpy()), (k, f)
         g.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_closure_equals_single_lattice_closure(cplb, precision):
+    """A per-node closure exchange over the whole batch (cases one after the
+    other) acts on each case exactly as the same slice does on the case run
+    alone: bitwise equal fields, and c1 + c2 still conserved."""
+    import torch
+    cases = mixed_cases(precision, seed=9)
+    say(f"batch closure vs single-lattice closure, {precision}, 8 steps")
+    b = make_batch(cplb, cases)
+    n = b.num_nodes
+    assert n == sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    s = torch.tensor(np.random.default_rng(2).normal(size=n) * 2e-3, dtype=torch.float32,
+                     device="cuda").contiguous()
+    b.set_closure(s)
+    c0 = [b.reduce(k)["sum_c"] for k in range(len(cases))]
+    b.step(8)
+    off = 0
+    for k, c in enumerate(cases):
+        nx, ny = c["params"]["nx"], c["params"]["ny"]
+        g = cplb.Lattice(c["params"])
+        g.init_sdf(c["sdf"], c1=c["init"]["c1"], c2=c["init"]["c2"])
+        g.set_closure(s[off:off + nx * ny].view(ny, nx).contiguous())
+        g.step(8)
+        for f in ("phi", "c1", "c2", "ux", "uy", "p"):
+            a, r = b.field(k, f).cpu().numpy(), g.field(f).cpu().numpy()
+            assert np.array_equal(a, r), (k, f, float(np.abs(a - r).max()))
+        tol = 1e-12 if precision == "f64" else 1e-6
+        assert abs(b.reduce(k)["sum_c"] - c0[k]) <= tol * abs(c0[k]), k
+        off += nx * ny
+        g.close()
+    # switching the closure off restores the plain step
+    b.set_closure(None)
+    p = make_batch(cplb, cases)
+    b2 = make_batch(cplb, cases)
+    b2.set_closure(s)
+    b2.set_closure(None)
+    p.step(3)
+    b2.step(3)
+    assert np.array_equal(p.field(4, "c1").cpu().numpy(), b2.field(4, "c1").cpu().numpy())
+
+
+def test_batch_gather_layout_and_init_planes(cplb):
+    """gather writes field f of case c at [c's offset * nplanes + f * nodes_c]
+    (float32 of the same values field() returns) and leaves the extra planes
+    alone; init_planes from that buffer equals init_fields from the same
+    values (u = p = 0), bitwise, after further steps."""
+    import torch
+    cases = mixed_cases("f32", seed=13)
+    b = make_batch(cplb, cases)
+    b.step(7)
+    names = ("phi", "c1", "c2", "ux")
+    nplanes = 6
+    out = torch.full((b.num_nodes * nplanes,), -7.0, dtype=torch.float32, device="cuda")
+    g = b.gather(names, out=out, nplanes=nplanes).cpu().numpy()
+    off = 0
+    for k, c in enumerate(cases):
+        nx, ny = c["params"]["nx"], c["params"]["ny"]
+        blk = g[off * nplanes:(off + nx * ny) * nplanes].reshape(nplanes, ny, nx)
+        for f, name in enumerate(names):
+            want = b.field(k, name, dtype=torch.float32).cpu().numpy()
+            assert np.array_equal(blk[f], want), (k, name)
+        assert np.all(blk[len(names):] == -7.0), k
+        off += nx * ny
+    # a fresh batch from the gathered phi, c1, c2 (plane order permuted)
+    perm = torch.tensor(g).view(-1).clone()
+    planes = torch.empty_like(perm)
+    off = 0
+    for c in cases:
+        m = c["params"]["nx"] * c["params"]["ny"]
+        src = perm[off * nplanes:(off + m) * nplanes].view(nplanes, m)
+        dst = planes[off * nplanes:(off + m) * nplanes].view(nplanes, m)
+        dst[:] = src
+        dst[0], dst[2], dst[4] = src[2], src[0], src[1]  # c2, phi, c1 at 0, 2, 4
+        off += m
+    b2 = cplb.Batch([c["params"] for c in cases])
+    b2.init_planes(planes.cuda(), nplanes, iphi=2, ic1=4, ic2=0)
+    b2.step(5)
+    for k, c in enumerate(cases):
+        gk = cplb.Lattice(c["params"])
+        m = c["params"]["nx"] * c["params"]["ny"]
+        shp = (c["params"]["ny"], c["params"]["nx"])
+        phi, c1, c2 = (b.field(k, f, dtype=torch.float32).cpu().numpy().astype(np.float64)
+                       for f in ("phi", "c1", "c2"))
+        gk.init_fields(phi.reshape(shp), c1.reshape(shp), c2.reshape(shp))
+        gk.step(5)
+        for f in ("phi", "c1", "c2", "ux", "uy", "p"):
+            assert np.array_equal(b2.field(k, f).cpu().numpy(), gk.field(f).cpu().numpy()), (k, f)
+        assert m > 0
+        gk.close()
+    with pytest.raises(AssertionError):
+        b2.init_planes(planes.cuda()[:-1], nplanes)

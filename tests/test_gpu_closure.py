@@ -162,3 +162,13 @@ def test_closure_hook_matches_oracle(cplb, precision, tol):
     assert np.abs(d).max() > 1e-4
     r, r2 = g.reduce(), g2.reduce()
     assert abs(r["sum_c"] - r2["sum_c"]) <= 1e-5 * abs(r2["sum_c"])
+
+
+@pytest.mark.parametrize("n,H,Wd,F", [(3, 8, 12, 4), (2, 5, 7, 2), (1, 16, 64, 4)])
+def test_restrict_is_the_block_mean(cplb, n, H, Wd, F):
+    import torch
+    x = np.random.default_rng(n + H).normal(size=(n, H * F, Wd * F)).astype(np.float32)
+    out = cplb.restrict(torch.tensor(x, device="cuda"), F).cpu().numpy()
+    want = x.astype(np.float64).reshape(n, H, F, Wd, F).mean(axis=(2, 4))
+    assert out.shape == (n, H, Wd)
+    np.testing.assert_allclose(out, want, rtol=0, atol=2e-6 * np.abs(x).max())
