@@ -133,6 +133,7 @@ struct cplb_ref {
   double *fs, *gs, *h1s, *h2s;
   /* pass-1 fields */
   double *phi, *c1, *c2, *psi, *Dm;
+  double* ctot; /* c1 + c2; in the one-scalar model the moment c = sum h3_i itself */
   /* pass-2 fields */
   double *gphi, *gpsi, *lap, *nrm, *mu_phi, *rho, *F, *u, *pr, *mu, *tau_g;
   /* history: fields of the previous time level */
@@ -185,6 +186,10 @@ static int check_params(const cplb_ref_params* p, char* err) {
     strcpy(err, "2-D lattice: g[2] must be 0");
     return -1;
   }
+  if (p->scalar_model != CPLB_REF_TWO_SCALAR && p->scalar_model != CPLB_REF_ONE_SCALAR) {
+    strcpy(err, "unknown scalar model");
+    return -1;
+  }
   if (!(p->W > 0 && p->sigma >= 0 && p->M > 0 && p->D1 > 0 && p->D2 > 0 && p->Keq > 0 && p->A >= 0 &&
         p->n_eps > 0)) {
     strcpy(err, "need W, M, D1, D2, Keq, n_eps > 0 and sigma, A >= 0");
@@ -229,6 +234,7 @@ int cplb_ref_create(const cplb_ref_params* prm, cplb_ref_t** out) {
   h->c2 = alloc0(N);
   h->psi = alloc0(N);
   h->Dm = alloc0(N);
+  h->ctot = alloc0(N);
   h->gphi = alloc0(3 * N);
   h->gpsi = alloc0(3 * N);
   h->lap = alloc0(N);
@@ -245,7 +251,7 @@ int cplb_ref_create(const cplb_ref_params* prm, cplb_ref_t** out) {
   h->c1_old = alloc0(N);
   h->c2_old = alloc0(N);
   if (!h->f || !h->h1 || !h->h2 || !h->g || !h->fs || !h->h1s || !h->h2s || !h->gs || !h->phi ||
-      !h->c1 || !h->c2 || !h->psi || !h->Dm || !h->gphi || !h->gpsi || !h->lap || !h->nrm ||
+      !h->c1 || !h->c2 || !h->psi || !h->Dm || !h->ctot || !h->gphi || !h->gpsi || !h->lap || !h->nrm ||
       !h->mu_phi || !h->rho || !h->F || !h->u || !h->pr || !h->mu || !h->tau_g || !h->u_old ||
       !h->phi_old || !h->c1_old || !h->c2_old) {
     cplb_ref_destroy(h);
@@ -260,7 +266,8 @@ void cplb_ref_destroy(cplb_ref_t* h) {
   double* all[] = {h->f,   h->g,     h->h1,  h->h2,     h->fs,      h->gs,      h->h1s,
                    h->h2s, h->phi,   h->c1,  h->c2,     h->psi,     h->Dm,      h->gphi,
                    h->gpsi, h->lap,  h->nrm, h->mu_phi, h->rho,     h->F,       h->u,
-                   h->pr,  h->mu,    h->tau_g, h->u_old, h->phi_old, h->c1_old, h->c2_old};
+                   h->pr,  h->mu,    h->tau_g, h->u_old, h->phi_old, h->c1_old, h->c2_old,
+                   h->ctot};
   for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); k++) free(all[k]);
   free(h);
 }
@@ -317,6 +324,17 @@ static double h_eq(const lattice_t* L, int i, double c, const double* u) {
   return L->w[i] * c * (1.0 + cdot(L->c[i], u) / L->cs2);
 }
 
+/* one-scalar model (Sec. III D): h3_0^eq = c + (w_0 - 1) c / K_eff,
+ * h3_i^eq = w_i c / K_eff + w_i c_i.(c u) / cs^2 for i != 0 */
+static double h3_eq(const lattice_t* L, int i, double c, double Keff, const double* u) {
+  if (i == 0) return c + (L->w[0] - 1.0) * c / Keff;
+  return L->w[i] * c / Keff + L->w[i] * c * cdot(L->c[i], u) / L->cs2;
+}
+
+/* equilibrium concentration ratio across the interface, K_eff = Keq phi + 1 - phi
+ * (Sec. II D) */
+static double k_eff(const cplb_ref_params* P, double phi) { return P->Keq * phi + (1.0 - phi); }
+
 /* ---------------------------------------------------------------- init */
 
 int cplb_ref_init_fields(cplb_ref_t* h, const double* phi, const double* c1, const double* c2,
@@ -330,16 +348,23 @@ int cplb_ref_init_fields(cplb_ref_t* h, const double* phi, const double* c1, con
       for (int a = 0; a < d; a++) un[a] = u[a * N + n];
     double pn = p ? p[n] : 0.0;
     double rho = phi[n] * (h->p.rho1 - h->p.rho2) + h->p.rho2;
+    const int one = h->p.scalar_model == CPLB_REF_ONE_SCALAR;
     for (int i = 0; i < h->LF.q; i++) {
       h->f[i * N + n] = f_eq(&h->LF, i, phi[n], un);
-      h->h1[i * N + n] = h_eq(&h->LF, i, c1[n], un);
-      h->h2[i * N + n] = h_eq(&h->LF, i, c2[n], un);
+      if (one) {
+        /* h3 carries the total c = c1 + c2 */
+        h->h1[i * N + n] = h3_eq(&h->LF, i, c1[n] + c2[n], k_eff(&h->p, phi[n]), un);
+        h->h2[i * N + n] = 0.0;
+      } else {
+        h->h1[i * N + n] = h_eq(&h->LF, i, c1[n], un);
+        h->h2[i * N + n] = h_eq(&h->LF, i, c2[n], un);
+      }
     }
     for (int i = 0; i < h->LG.q; i++) h->g[i * N + n] = g_eq(&h->LG, i, pn, rho, un);
     for (int a = 0; a < 3; a++) h->u_old[a * N + n] = un[a];
     h->phi_old[n] = phi[n];
-    h->c1_old[n] = c1[n];
-    h->c2_old[n] = c2[n];
+    h->c1_old[n] = one ? c1[n] + c2[n] : c1[n];
+    h->c2_old[n] = one ? 0.0 : c2[n];
   }
   h->step = 0;
   h->macros_valid = 0;
@@ -383,6 +408,21 @@ static void pass1(cplb_ref_t* h) {
     double phi = 0, S1 = 0, S2 = 0;
     for (int i = 0; i < h->LF.q; i++) phi += h->f[i * N + n];
     for (int i = 0; i < h->LF.q; i++) S1 += h->h1[i * N + n];
+    if (P->scalar_model == CPLB_REF_ONE_SCALAR) {
+      /* c = sum h3_i; the phase parts of c at interfacial equilibrium,
+         c~1 = Keq c~2 and c = c~1 phi + c~2 (1 - phi) (Sec. II D); the
+         effective diffusivity D_eff = D1 Keq phi + D2 (1 - phi) is kept
+         in the D_m slot */
+      const double c = S1, Keff = k_eff(P, phi);
+      const double ct2 = c / Keff;
+      h->phi[n] = phi;
+      h->Dm[n] = P->D1 * P->Keq * phi + P->D2 * (1.0 - phi);
+      h->c1[n] = P->Keq * ct2 * phi;
+      h->c2[n] = ct2 * (1.0 - phi);
+      h->psi[n] = h->c1[n] + P->Keq * h->c2[n];
+      h->ctot[n] = c;
+      continue;
+    }
     for (int i = 0; i < h->LF.q; i++) S2 += h->h2[i * N + n];
     /* mixed diffusivity, Sec. II C */
     double Dm = P->D1 * P->D2 / (P->Keq * P->D1 * (1.0 - phi) + P->D2 * phi);
@@ -399,6 +439,7 @@ static void pass1(cplb_ref_t* h) {
     h->c1[n] = c1;
     h->c2[n] = c2;
     h->psi[n] = c1 + P->Keq * c2;
+    h->ctot[n] = c1 + c2;
   }
 }
 
@@ -526,6 +567,23 @@ static void collide(cplb_ref_t* h) {
       double gi = h->g[i * N + n];
       h->gs[i * N + n] = gi - (gi - geq) / tau_g + (1.0 - 1.0 / (2.0 * tau_g)) * Gi;
     }
+    if (P->scalar_model == CPLB_REF_ONE_SCALAR) {
+      /* one-scalar set h3 (Sec. III D): tau_h3 from D_eff = (tau_h3 - 1/2) cs^2,
+         source H3_i = w_i c_i.d_t(c u)/cs^2; the history keeps c in the c1 slot */
+      const double c = h->ctot[n], Keff = k_eff(P, phi);
+      const double tau3 = 0.5 + Dm / LF->cs2;
+      double dcu[3];
+      for (int a = 0; a < 3; a++) dcu[a] = c * u[a] - h->c1_old[n] * u_old[a];
+      for (int i = 0; i < LF->q; i++) {
+        const int* cc = LF->c[i];
+        double heq = h3_eq(LF, i, c, Keff, u);
+        double H3 = LF->w[i] * cdot(cc, dcu) / LF->cs2;
+        double a1 = h->h1[i * N + n];
+        h->h1s[i * N + n] = a1 - (a1 - heq) / tau3 + (1.0 - 1.0 / (2.0 * tau3)) * H3;
+        h->h2s[i * N + n] = 0.0;
+      }
+      continue;
+    }
     /* two-scalar sets h1, h2 with sources H_k and auxiliary sources ~H_k */
     const double M1 = P->A * Dm * (P->Keq * c2 * phi - c1 * (1.0 - phi));
     const double M2 = P->A * Dm * (c1 * (1.0 - phi) - P->Keq * c2 * phi);
@@ -598,8 +656,15 @@ int cplb_ref_step(cplb_ref_t* h, int64_t nsteps) {
     /* history for the next backward difference */
     memcpy(h->u_old, h->u, 3 * N * sizeof(double));
     memcpy(h->phi_old, h->phi, N * sizeof(double));
-    memcpy(h->c1_old, h->c1, N * sizeof(double));
-    memcpy(h->c2_old, h->c2, N * sizeof(double));
+    if (h->p.scalar_model == CPLB_REF_ONE_SCALAR) {
+      for (long n = 0; n < N; n++) {
+        h->c1_old[n] = h->ctot[n];
+        h->c2_old[n] = 0.0;
+      }
+    } else {
+      memcpy(h->c1_old, h->c1, N * sizeof(double));
+      memcpy(h->c2_old, h->c2, N * sizeof(double));
+    }
     h->macros_valid = 0;
     h->step++;
   }
@@ -645,7 +710,7 @@ int cplb_ref_reduce(cplb_ref_t* h, double out[8]) {
     s_phi += h->phi[n];
     s_c1 += h->c1[n];
     s_c2 += h->c2[n];
-    s_c += h->c1[n] + h->c2[n];
+    s_c += h->ctot[n];
     if (sqrt(u2) > umax) umax = sqrt(u2);
     ke += 0.5 * h->rho[n] * u2;
   }

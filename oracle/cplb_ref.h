@@ -24,6 +24,12 @@ extern "C" {
 
 enum { CPLB_REF_D2Q9 = 0, CPLB_REF_D3Q19_D3Q7 = 1 };
 enum { CPLB_REF_VISC_LINEAR = 0, CPLB_REF_VISC_EXP = 1 };
+/* One-scalar model (Sec. II D, III D): the populations h3 of the total
+ * concentration c = c1 + c2 take the place of h1 (h2 stays zero).  Fields
+ * c1, c2 read back as the phase parts of c at interfacial equilibrium,
+ * c1 = Keq phi c / K_eff, c2 = (1 - phi) c / K_eff, K_eff = Keq phi + 1 - phi;
+ * the history keeps c in the c1 slot. */
+enum { CPLB_REF_TWO_SCALAR = 0, CPLB_REF_ONE_SCALAR = 1 };
 enum {
   CPLB_REF_OK = 0,
   CPLB_REF_EINVAL = -1,
@@ -50,6 +56,8 @@ typedef struct cplb_ref_params {
   double g[3];              /* gravity vector; body force G = (rho-rho_ref) g  */
   double rho_ref;
   double n_eps;             /* n = grad phi / sqrt(|grad phi|^2 + n_eps^2), > 0 */
+  int32_t scalar_model;     /* CPLB_REF_TWO_SCALAR (h1, h2; Sec. III C) or
+                               CPLB_REF_ONE_SCALAR (h3 for c = c1 + c2; Sec. III D) */
 } cplb_ref_params;
 
 typedef struct cplb_ref cplb_ref_t;

@@ -17,6 +17,7 @@ FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7
 SETS = {"f": 0, "g": 1, "h1": 2, "h2": 3}
 LATTICES = {"d2q9": 0, "d3q19_d3q7": 1}
 VISC = {"linear": 0, "exp": 1}
+SCALAR_MODELS = {"two": 0, "one": 1}
 
 
 class RefParams(ctypes.Structure):
@@ -29,7 +30,7 @@ class RefParams(ctypes.Structure):
         ("sigma", ctypes.c_double), ("W", ctypes.c_double), ("M", ctypes.c_double),
         ("D1", ctypes.c_double), ("D2", ctypes.c_double), ("Keq", ctypes.c_double),
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
-        ("n_eps", ctypes.c_double),
+        ("n_eps", ctypes.c_double), ("scalar_model", ctypes.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ def make_params(p: dict) -> RefParams:
     for k in ("rho1", "rho2", "mu1", "mu2", "sigma", "W", "M", "D1", "D2", "Keq", "A",
               "rho_ref", "n_eps"):
         setattr(r, k, float(p[k]))
+    r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
     return r
 
 
