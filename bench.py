@@ -67,15 +67,26 @@ def alg_bytes_per_node(p):
     and written once, plus the (u, phi, c1, c2) history read and written."""
     d = 2 if p["lattice"] == "d2q9" else 3
     qtot = 36 if d == 2 else 40
+    nhist = d + 3
+    if p.get("scalar_model", "two") == "one":
+        # one-scalar model: f, g, h3 (27 values), history (u, phi, c)
+        qtot, nhist = 27, d + 2
     s_pop = {"f64": 8, "f32": 4, "f32_s16f": 2, "f32_s16b": 2}[p["precision"]]
     s_hist = 8 if p["precision"] == "f64" else 4
-    return 2 * qtot * s_pop + 2 * (d + 3) * s_hist
+    return 2 * qtot * s_pop + 2 * nhist * s_hist
 
 
 def make_workload(name):
     import workloads as W
     if name == "rising_bubble_256x1024":
         return W.rising_bubble_2d(256, 1024, "f32")
+    if name == "rising_bubble_one_256x1024":
+        # the one-scalar model (h3) on the same bubble, Keq = 2
+        return W.rising_bubble_2d(256, 1024, "f32", scalar_model="one")
+    if name == "rising_bubble_2048x4096":
+        # the same bubble 8x wider: 8.4M nodes, 2.75 GB per step, far beyond the
+        # Infinity Cache -- the 2-D step against HBM
+        return W.rising_bubble_2d(2048, 4096, "f32")
     if name.startswith("rising_droplet_256c"):
         prec = name[len("rising_droplet_256c_"):] or "f32"
         return W.rising_droplet_3d(256, prec)
@@ -222,6 +233,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (5 launches): the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
+    ap.add_argument("--part", choices=("step", "batch", "closure"), default="step",
+                    help="batch / closure: run only that side measurement and print its JSON "
+                         "(for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the step is "
@@ -231,6 +245,13 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+
+    if args.part == "batch":
+        print(json.dumps(time_batch(args.steps, args.warmup)), flush=True)
+        return
+    if args.part == "closure":
+        print(json.dumps(closure_speedup()), flush=True)
+        return
 
     if args.copy_calibration:
         # a plain copy of known size: reads and writes exactly 1 GiB per launch
@@ -293,6 +314,16 @@ def main():
                 extra[w3["name"]]["traffic_GBs"] = round(t3 / (r3["avg_kernel_ms"] * 1e-3) / 1e9, 1)
             del w3
         out["also_3d_256c"] = extra
+        w1 = make_workload("rising_bubble_one_256x1024")
+        r1 = time_gpu(w1, 2000, 200)
+        b1 = alg_bytes_per_node(w1["params"])
+        a1 = b1 * r1["n"] / (r1["avg_kernel_ms"] * 1e-3) / 1e9
+        out["also_one_scalar"] = {
+            "workload": w1["name"], "mlups": round(r1["n"] * 2000 / (r1["total_ms"] * 1e-3) / 1e6, 1),
+            "avg_kernel_ms": round(r1["avg_kernel_ms"], 5), "alg_bytes_per_node": b1,
+            "achieved_GBs": round(a1, 1), "frac": round(a1 / HBM_PEAK_GBS, 4),
+            "nonfinite": r1["reduce"]["nonfinite"]}
+        del w1
         out["also_batch_512"] = time_batch(40, 5)
         out["closure"] = closure_speedup()
     if not args.no_cpu_baseline:

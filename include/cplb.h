@@ -61,6 +61,22 @@ extern "C" {
 #define CPLB_VISC_LINEAR 0 /* mu = phi (mu1 - mu2) + mu2, Eq. (1.8)            */
 #define CPLB_VISC_EXP 1    /* log mu = c1 log mu1 + c2 log mu2, Eq. (4.3)      */
 
+/* scalar transport models (cplb_params.scalar_model)
+ * CPLB_TWO_SCALAR: c1, c2 carried by h1, h2 with the exchange and auxiliary
+ *   sources (Sec. II C, III C).
+ * CPLB_ONE_SCALAR: the total c = c1 + c2 carried by one set h3 (Sec. II D,
+ *   III D): h3_0^eq = c + (w0 - 1) c / K_eff, h3_i^eq = w_i c / K_eff +
+ *   w_i c_i.(c u) / cs^2, source w_i c_i.d_t(c u) / cs^2, per-node
+ *   tau_h3 = 1/2 + D_eff / cs^2 with D_eff = D1 Keq phi + D2 (1 - phi) and
+ *   K_eff = Keq phi + 1 - phi.  CPLB_D2Q9 single lattices only (the batch and
+ *   the 3-D lattice take the two-scalar model).  h3 occupies the h1 planes;
+ *   the h2 planes are neither read nor written.  Fields c1, c2 read back as
+ *   the phase parts of c at interfacial equilibrium, c1 = Keq phi c / K_eff,
+ *   c2 = (1 - phi) c / K_eff; init takes c = c1 + c2.  Stable for
+ *   K_eff >= 1 - w0 = 5/9 (the rest equilibrium stays non-negative). */
+#define CPLB_TWO_SCALAR 0
+#define CPLB_ONE_SCALAR 1
+
 /* field ids for cplb_read_field */
 #define CPLB_FIELD_PHI 0
 #define CPLB_FIELD_P 1
@@ -83,7 +99,7 @@ typedef struct cplb_params {
   int32_t precision;     /* CPLB_F64 | CPLB_F32 | CPLB_F32_S16F | CPLB_F32_S16B  */
   int32_t visc_law;      /* CPLB_VISC_LINEAR | CPLB_VISC_EXP                     */
   int32_t periodic[3];   /* per axis: 1 periodic, 0 half-way bounce-back walls   */
-  int32_t reserved;      /* must be 0                                            */
+  int32_t scalar_model;  /* CPLB_TWO_SCALAR (0) | CPLB_ONE_SCALAR (1)             */
   double rho1, rho2;     /* densities of fluid 1 (phi = 1) and fluid 2 (Sec. II B) */
   double mu1, mu2;       /* viscosities of the two fluids (or the exp-law bases) */
   double sigma;          /* surface tension: beta = 12 sigma/W, k = 3 sigma W/2  */
@@ -166,7 +182,7 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes);
  * order, owned by the caller and kept alive while set) is an extra exchange
  * per step carried like the auxiliary source ~H_k (Sec. III C): h1 loses
  * w_i s, h2 gains it, so c1 + c2 is conserved exactly.  NULL switches it
- * off.  CPLB_EINVAL on a 3-D lattice. */
+ * off.  CPLB_EINVAL on a 3-D lattice or with the one-scalar model. */
 int cplb_set_closure(cplb_t* h, const float* dev_s);
 
 /* Step-kernel variants (tile shape, non-temporal population traffic).
@@ -201,7 +217,7 @@ typedef struct cplb_batch cplb_batch_t;
 
 /* Device workspace for ncases >= 1 cases with parameters prm[0..ncases).
  * CPLB_EINVAL for an invalid case (the checks of cplb_create, plus:
- * CPLB_D2Q9 only, same precision as case 0). */
+ * CPLB_D2Q9 and the two-scalar model only, same precision as case 0). */
 int cplb_batch_workspace_bytes(const cplb_params* prm, int ncases, size_t* bytes);
 
 /* Validate every case, carve the workspace (256-byte aligned, at least

@@ -22,6 +22,8 @@ CPLB_OK, CPLB_EINVAL, CPLB_ENOMEM, CPLB_EHIP, CPLB_EUNSTABLE, CPLB_ESTATE = 0, -
 LATTICES = {"d2q9": 0, "d3q19_d3q7": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f32_s16f": 2, "f32_s16b": 3}
 VISC = {"linear": 0, "exp": 1}
+SCALAR_MODELS = {"two": 0, "one": 1}
+CPLB_TWO_SCALAR, CPLB_ONE_SCALAR = 0, 1
 FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
 DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
@@ -47,7 +49,7 @@ class cplb_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32), ("visc_law", ctypes.c_int32),
-        ("periodic", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3), ("scalar_model", ctypes.c_int32),
         ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
         ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
         ("sigma", ctypes.c_double), ("W", ctypes.c_double), ("M", ctypes.c_double),
@@ -168,7 +170,7 @@ def make_params(p: dict) -> cplb_params:
     for a in range(3):
         r.periodic[a] = int(p["periodic"][a])
         r.g[a] = float(p["g"][a])
-    r.reserved = 0
+    r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
     for k in ("rho1", "rho2", "mu1", "mu2", "sigma", "W", "M", "D1", "D2", "Keq", "A", "rho_ref",
               "n_eps"):
         setattr(r, k, float(p[k]))

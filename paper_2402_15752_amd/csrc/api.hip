@@ -350,6 +350,8 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
 int cplb_set_closure(cplb_t* h, const float* dev_s) {
   if (!h) return CPLB_EINVAL;
   if (h->G.dim != 2 && dev_s) return set_err(h, CPLB_EINVAL, "a closure applies to D2Q9 lattices%s", "");
+  if (h->prm.scalar_model != CPLB_TWO_SCALAR && dev_s)
+    return set_err(h, CPLB_EINVAL, "a closure applies to the two-scalar model%s", "");
   h->closure = dev_s;
   return CPLB_OK;
 }

@@ -34,6 +34,11 @@ __global__ __launch_bounds__(256) void init_kernel(S* __restrict__ lat, T* __res
     c1 = in_c1[node];
     c2 = in_c2[node];
   }
+  if (P.one_scalar) {
+    // one-scalar model: h3 carries c = c1 + c2, the history keeps c in the c1 slot
+    c1 += c2;
+    c2 = 0.0;
+  }
   T u[3] = {0, 0, 0};
   if (in_u)
     for (int a = 0; a < LG::D; ++a) u[a] = T(in_u[a * n_nodes + node]);

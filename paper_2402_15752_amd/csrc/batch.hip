@@ -86,6 +86,10 @@ int validate_batch(const cplb_params* prm, int n, char* err, size_t errn) {
       snprintf(err, errn, "case %d: batches hold D2Q9 lattices only", c);
       return CPLB_EINVAL;
     }
+    if (prm[c].scalar_model != CPLB_TWO_SCALAR) {
+      snprintf(err, errn, "case %d: batches run the two-scalar model only", c);
+      return CPLB_EINVAL;
+    }
     if (prm[c].precision != prm[0].precision) {
       snprintf(err, errn, "case %d: every case needs the precision of case 0", c);
       return CPLB_EINVAL;

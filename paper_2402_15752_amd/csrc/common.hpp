@@ -44,6 +44,8 @@ struct KParams {
   T four_over_W;
   T neps2;            // n_eps^2 of the regularised normal
   T ref_phi, one_minus_ref_phi, ref_c1, ref_c2;  // reference state of the deviations
+  int one_scalar;     // 1: one-scalar model, h3 in the h1 planes (Sec. III D)
+  T D1K;              // D1 Keq of D_eff = D1 Keq phi + D2 (1 - phi)
 };
 
 // ------------------------------------------------------------ storage codec
@@ -115,7 +117,8 @@ template <class T>
 struct Node {
   T dphi, phi, omphi;  // phi - phi_ref, phi, 1 - phi
   T dc1, dc2, c1, c2;  // c_k - c_k,ref and c_k
-  T Dm;                // mixed diffusivity
+  T Dm;                // mixed diffusivity (one-scalar model: D_eff)
+  T c, dc, ct;         // one-scalar model: c, c - c_ref, c / K_eff
 };
 
 // --------------------------------------------------- moments and recovery
@@ -146,6 +149,32 @@ __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const 
   s.dc2 = s2 - a * e;
   s.c1 = P.ref_c1 + s.dc1;
   s.c2 = P.ref_c2 + s.dc2;
+}
+
+// One-scalar model (Sec. II D, III D): c = sum h3_i; the phase parts of c at
+// interfacial equilibrium (c~1 = Keq c~2, c = c~1 phi + c~2 (1 - phi)) give
+// c~2 = c / K_eff, c1 = Keq phi c~2, c2 = (1 - phi) c~2 with
+// K_eff = Keq phi + 1 - phi; D_eff = D1 Keq phi + D2 (1 - phi) goes to Dm.
+template <class LF, class T>
+__device__ inline void moments_one(const KParams<T>& P, const T (&df)[LF::Q],
+                                   const T (&dh3)[LF::Q], Node<T>& s) {
+  T s0 = df[0], s1 = dh3[0];
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) {
+    s0 += df[i];
+    s1 += dh3[i];
+  }
+  s.dphi = s0;
+  s.phi = P.ref_phi + s0;
+  s.omphi = P.one_minus_ref_phi - s0;
+  s.dc = s1;
+  s.c = P.ref_c1 + s1;
+  s.ct = s.c / (P.Keq * s.phi + s.omphi);
+  s.c1 = P.Keq * s.phi * s.ct;
+  s.c2 = s.omphi * s.ct;
+  s.dc1 = s.c1 - P.ref_c1;
+  s.dc2 = s.c2 - P.ref_c2;
+  s.Dm = P.D1K * s.phi + P.D2 * s.omphi;
 }
 
 // ---------------------------------------------------------- flow macros
@@ -364,6 +393,30 @@ __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], con
   }
 }
 
+// one-scalar set (Sec. III D): h3_0^eq = c + (w0 - 1) c / K_eff,
+//   h3_i^eq = w_i c / K_eff + w_i c_i.(c u) / cs^2, H3_i = w_i c_i.d_t(c u) / cs^2,
+//   tau_h3 = 1/2 + D_eff / cs^2 per node.  On the deviations dh3_i = h3_i - w_i c_ref
+//   the rest direction closes the zeroth moment as for the other sets.
+template <class LF, class T, class Emit>
+__device__ inline void collide_h3(const KParams<T>& P, const T (&dh3)[LF::Q], const Node<T>& s,
+                                  const Flow<T>& fl, const T (&dJ)[3], Emit&& emit) {
+  const T nu = s.Dm * T(1.0 / LF::cs2);  // tau_h3 - 1/2
+  const T del = T(2) * nu / (T(0.5) + nu);
+  const T hdel = T(0.5) * del;
+  const T dct = s.ct - P.ref_c1;
+  auto eq = [&](int i) {
+    return T(LF::w[i]) * dct + kw<LF, T>(i) * s.c * cdot<LF>(i, fl.u);
+  };
+  T rest = s.dc;
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) rest -= eq(i);
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) {
+    const T H = i == 0 ? T(0) : kw<LF, T>(i) * cdot<LF>(i, dJ);
+    emit(i, relax(dh3[i], i == 0 ? rest : eq(i), del, hdel, H));
+  }
+}
+
 // All four sets at one node, post-collision values handed to the emitters.
 template <class LF, class LG, class T, class EF, class EG, class EH>
 __device__ inline void collide(const KParams<T>& P, const T (&df)[LF::Q], const T (&g)[LG::Q],
@@ -413,13 +466,24 @@ __device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const 
   const T rho = phi * P.drho + P.rho2;
   const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const T dphi = phi - P.ref_phi, dc1 = c1 - P.ref_c1, dc2 = c2 - P.ref_c2;
+  // one-scalar model: h3 (in the h1 slot) of c = c1 + c2, h2 = 0
+  const T c = c1 + c2;
+  const T dct = c / (P.Keq * phi + (T(1) - phi)) - P.ref_c1;
+  T rest3 = c - P.ref_c1;
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
     const T cu = cdot<LF>(i, u);
     df[i] = T(LF::w[i]) * (dphi + phi * cu * inv_csf);
-    dh1[i] = T(LF::w[i]) * (dc1 + c1 * cu * inv_csf);
-    dh2[i] = T(LF::w[i]) * (dc2 + c2 * cu * inv_csf);
+    if (P.one_scalar) {
+      dh1[i] = T(LF::w[i]) * (dct + c * cu * inv_csf);
+      dh2[i] = T(0);
+      if (i > 0) rest3 -= dh1[i];
+    } else {
+      dh1[i] = T(LF::w[i]) * (dc1 + c1 * cu * inv_csf);
+      dh2[i] = T(LF::w[i]) * (dc2 + c2 * cu * inv_csf);
+    }
   }
+  if (P.one_scalar) dh1[0] = rest3;
 #pragma unroll
   for (int i = 0; i < LG::Q; ++i) {
     const T cu = cdot<LG>(i, u);

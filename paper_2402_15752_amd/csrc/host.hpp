@@ -31,7 +31,10 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
   if (p->precision < CPLB_F64 || p->precision > CPLB_F32_S16B) return fail("unknown precision");
   if (p->visc_law != CPLB_VISC_LINEAR && p->visc_law != CPLB_VISC_EXP)
     return fail("unknown viscosity law");
-  if (p->reserved != 0) return fail("reserved field must be 0");
+  if (p->scalar_model != CPLB_TWO_SCALAR && p->scalar_model != CPLB_ONE_SCALAR)
+    return fail("unknown scalar model");
+  if (p->scalar_model == CPLB_ONE_SCALAR && p->lattice != CPLB_D2Q9)
+    return fail("the one-scalar model runs on CPLB_D2Q9 only");
   const int d = p->lattice == CPLB_D2Q9 ? 2 : 3;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
   if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
@@ -125,6 +128,9 @@ KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
   K.A = T(p->A);
   K.half_A = T(0.5 * p->A);
   K.four_over_W = T(4.0 / p->W);
+  // one-scalar model (Sec. III D): D_eff = D1 Keq phi + D2 (1 - phi)
+  K.one_scalar = p->scalar_model == CPLB_ONE_SCALAR;
+  K.D1K = T(p->D1 * p->Keq);
   K.neps2 = T(p->n_eps * p->n_eps);
   // reference state of the stored deviations (f, h1, h2; g is stored as is)
   K.ref_phi = T(p->ref[0]);

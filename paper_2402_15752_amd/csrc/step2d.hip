@@ -26,7 +26,7 @@ namespace {
 using L = D2Q9;
 using Lay = Layout<D2Q9, D2Q9>;
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, bool ONE>
 __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
                                                         T* __restrict__ fields, KParams<T> P,
@@ -38,10 +38,10 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= G.ntiles) return;
-  step2d_tile<S, T, TX, TY, NTS, MODE, Off>(src, dst, hist, fields, P, G, tile);
+  step2d_tile<S, T, TX, TY, NTS, MODE, Off, ONE>(src, dst, hist, fields, P, G, tile);
 }
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, bool ONE>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                           const float* closure, hipStream_t stream) {
   Geo2<Off> G;
@@ -55,7 +55,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.sT = Off(P.stride * (long long)sizeof(T));
   G.closure = closure;
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off>), dim3(nblocks), dim3(TX * TY),
+  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off, ONE>), dim3(nblocks), dim3(TX * TY),
                      0, stream, src, dst, hist, fields, P, G);
   return hipGetLastError();
 }
@@ -69,30 +69,45 @@ const char* step2d_variant_name(int v) {
   return v >= 0 && v < kVariants2D ? names[v] : "?";
 }
 
-template <class S, class T>
-hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, const float* closure, hipStream_t stream) {
+namespace {
+
+// the variant switch of one scalar model (ONE: the one-scalar model, Sec. III D)
+template <class S, class T, bool ONE>
+hipError_t launch_model(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
+                        int variant, const float* closure, hipStream_t stream) {
   constexpr int M = kModeStep;
   using U = uint32_t;
   if (!fits_u32(L::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t>(src, dst, hist, fields, P,
-                                                                      closure, stream);
-    return launch_variant<S, T, 128, 4, false, M, uint64_t>(src, dst, hist, fields, P, closure, stream);
+      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t, ONE>(src, dst, hist, fields,
+                                                                           P, closure, stream);
+    return launch_variant<S, T, 128, 4, false, M, uint64_t, ONE>(src, dst, hist, fields, P,
+                                                                closure, stream);
   }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, kModeMacros, U>(src, dst, hist, fields, P, closure, stream);
+    return launch_variant<S, T, 64, 4, false, kModeMacros, U, ONE>(src, dst, hist, fields, P,
+                                                                  closure, stream);
   switch (variant) {
-    case 1: return launch_variant<S, T, 32, 8, false, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 2: return launch_variant<S, T, 32, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 3: return launch_variant<S, T, 128, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 4: return launch_variant<S, T, 64, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 5: return launch_variant<S, T, 32, 8, true, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 6: return launch_variant<S, T, 32, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
-    case 7: return launch_variant<S, T, 128, 4, true, M, U>(src, dst, hist, fields, P, closure, stream);
-    default: return launch_variant<S, T, 64, 4, false, M, U>(src, dst, hist, fields, P, closure, stream);
+    case 1: return launch_variant<S, T, 32, 8, false, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 2: return launch_variant<S, T, 32, 4, false, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 3: return launch_variant<S, T, 128, 4, false, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 4: return launch_variant<S, T, 64, 4, true, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 5: return launch_variant<S, T, 32, 8, true, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 6: return launch_variant<S, T, 32, 4, true, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    case 7: return launch_variant<S, T, 128, 4, true, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
+    default: return launch_variant<S, T, 64, 4, false, M, U, ONE>(src, dst, hist, fields, P, closure, stream);
   }
+}
+
+}  // namespace
+
+template <class S, class T>
+hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
+                         int variant, const float* closure, hipStream_t stream) {
+  if (P.one_scalar)
+    return launch_model<S, T, true>(src, dst, hist, fields, P, mode, variant, nullptr, stream);
+  return launch_model<S, T, false>(src, dst, hist, fields, P, mode, variant, closure, stream);
 }
 
 template hipError_t launch_step2d<double, double>(const double*, double*, double*, double*,

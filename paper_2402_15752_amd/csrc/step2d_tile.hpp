@@ -31,7 +31,9 @@ struct Geo2 {
 // One TX x TY tile of the fused 2-D step (moments, stencils, macros,
 // history, collision, push), shared by the single-lattice and the batched
 // kernels.  `tile` is the tile index in row-major order over the grid.
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off>
+// ONE selects the one-scalar model (Sec. III D): h3 in the h1 planes, no h2
+// traffic, no psi stencil, history (u, phi, c).
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, bool ONE = false>
 __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ dst,
                                    T* __restrict__ hist, T* __restrict__ fields,
                                    const KParams<T>& P, const Geo2<Off>& G, int tile) {
@@ -75,35 +77,49 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   // ---- 1. all global loads first
   T f[9], h1[9], h2[9], g[9], hf[9], hh1[9], hh2[9];
   T hs[kHist2D];
+  constexpr int NH = ONE ? kHist2D - 1 : kHist2D;  // one-scalar: (ux, uy, phi, c)
   if (own_slot) {
     load_q<L, NTS, false>(sF, G.sS, node, f);
     load_q<L, NTS, false>(sH1, G.sS, node, h1);
-    load_q<L, NTS, false>(sH2, G.sS, node, h2);
+    if (!ONE) load_q<L, NTS, false>(sH2, G.sS, node, h2);
   }
   if (active) {
     load_q<L, NTS, false>(sG, G.sS, node, g);
 #pragma unroll
-    for (int k = 0; k < kHist2D; ++k) hs[k] = *at(hist, plane<false>(k, G.sT) + nodeT);
+    for (int k = 0; k < NH; ++k) hs[k] = *at(hist, plane<false>(k, G.sT) + nodeT);
   }
   if (halo) {
     load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
-    load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
-    load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
+    if (!ONE) {
+      load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
+      load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
+    }
   }
 
   // ---- 2. moments to LDS (deviations: the stencils only take differences
   //         and zero-sum weighted sums)
   Node<T> s{};
   if (own_slot) {
-    moments<L>(P, f, h1, h2, s);
+    if constexpr (ONE) {
+      moments_one<L>(P, f, h1, s);
+    } else {
+      moments<L>(P, f, h1, h2, s);
+      spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+    }
     sphi[ty + 1][tx + 1] = s.dphi;
-    spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
   }
   if (halo) {
-    Node<T> q;
-    moments<L>(P, hf, hh1, hh2, q);
-    sphi[hy + 1][hx + 1] = q.dphi;
-    spsi[hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+    if constexpr (ONE) {
+      T d = hf[0];
+#pragma unroll
+      for (int i = 1; i < 9; ++i) d += hf[i];
+      sphi[hy + 1][hx + 1] = d;
+    } else {
+      Node<T> q;
+      moments<L>(P, hf, hh1, hh2, q);
+      sphi[hy + 1][hx + 1] = q.dphi;
+      spsi[hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+    }
   }
   __syncthreads();
   if (!active) return;
@@ -113,7 +129,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const T a = sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
-    const T b = spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
+    const T b = ONE ? T(0) : spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
     const T wc = T(L::w[i] / L::cs2);
     if (L::cx[i]) {
       gphi[0] += wc * T(L::cx[i]) * a;
@@ -143,13 +159,19 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
     return;
   }
 
-  // backward-difference time derivatives against the history (R1)
+  // backward-difference time derivatives against the history (R1); the
+  // one-scalar model keeps c in the c1 slot
+  const T cA = ONE ? s.c : s.c1;
   const T dJphi[3] = {s.phi * fl.u[0] - hs[2] * hs[0], s.phi * fl.u[1] - hs[2] * hs[1], T(0)};
-  const T dJ1[3] = {s.c1 * fl.u[0] - hs[3] * hs[0], s.c1 * fl.u[1] - hs[3] * hs[1], T(0)};
-  const T dJ2[3] = {s.c2 * fl.u[0] - hs[4] * hs[0], s.c2 * fl.u[1] - hs[4] * hs[1], T(0)};
+  const T dJ1[3] = {cA * fl.u[0] - hs[3] * hs[0], cA * fl.u[1] - hs[3] * hs[1], T(0)};
+  T dJ2[3] = {T(0), T(0), T(0)};
+  if constexpr (!ONE) {
+    dJ2[0] = s.c2 * fl.u[0] - hs[4] * hs[0];
+    dJ2[1] = s.c2 * fl.u[1] - hs[4] * hs[1];
+  }
 #pragma unroll
-  for (int k = 0; k < kHist2D; ++k) {
-    const T v = k < 2 ? fl.u[k] : (k == 2 ? s.phi : (k == 3 ? s.c1 : s.c2));
+  for (int k = 0; k < NH; ++k) {
+    const T v = k < 2 ? fl.u[k] : (k == 2 ? s.phi : (k == 3 ? cA : s.c2));
     *at(hist, plane<false>(k, G.sT) + nodeT) = v;
   }
 
@@ -169,6 +191,20 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
   S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
   S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
+  if constexpr (ONE) {
+    T n[3];
+    normal(P, gphi, n);
+    collide_g<L>(P, g, gphi, fl, [&](int i, T v) {
+      st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
+    });
+    collide_f<L>(P, f, s, n, fl, dJphi, [&](int i, T v) {
+      st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
+    });
+    collide_h3<L>(P, h1, s, fl, dJ1, [&](int i, T v) {
+      st_pop<NTS>(at(dH1, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
+    });
+    return;
+  }
   collide<L, L>(
       P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
       [&](int i, T v) { st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },

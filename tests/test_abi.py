@@ -68,11 +68,24 @@ def test_workspace_bytes_cover_two_lattices(cplb):
 @pytest.mark.parametrize("bad", [dict(D2=0.0), dict(Keq=0.0), dict(M=-1.0), dict(nx=0),
                                  dict(rho1=0.0), dict(g=(0, 0, 1e-5)), dict(n_eps=0.0),
                                  dict(periodic=(1, 0, 1), ny=1), dict(nz=2),
-                                 dict(precision="f32", sigma=float("nan"))])
+                                 dict(precision="f32", sigma=float("nan")),
+                                 dict(scalar_model="one", lattice="d3q19_d3q7", nz=8, nx=8, ny=8)])
 def test_validation_rejects(cplb, bad):
     p = W.params(**bad)
     with pytest.raises(cplb.CplbError) as e:
         cplb.cplb_workspace_bytes(cplb.make_params(p))
+    assert e.value.code == cplb.CPLB_EINVAL
+
+
+def test_scalar_model_field(cplb):
+    """The one-scalar model is selected through cplb_params.scalar_model; an
+    unknown model id is refused."""
+    prm = cplb.make_params(W.params(scalar_model="one"))
+    assert prm.scalar_model == cplb.CPLB_ONE_SCALAR
+    assert cplb.cplb_workspace_bytes(prm) > 0
+    prm.scalar_model = 2
+    with pytest.raises(cplb.CplbError) as e:
+        cplb.cplb_workspace_bytes(prm)
     assert e.value.code == cplb.CPLB_EINVAL
 
 
@@ -104,6 +117,7 @@ def test_batch_validation_and_workspace(cplb):
         [W.params(precision="f32"), W.params(nx=8, ny=8, nz=8, lattice="d3q19_d3q7",
                                              precision="f32")],                 # not D2Q9
         [W.params(precision="f32"), W.params(precision="f32", D1=0.0)],         # invalid case
+        [W.params(precision="f32"), W.params(precision="f32", scalar_model="one")],  # one-scalar
     ]
     for ps in bad_sets:
         with pytest.raises(cplb.CplbError) as e:

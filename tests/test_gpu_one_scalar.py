@@ -1,0 +1,110 @@
+"""GPU parity of the one-scalar model (Sec. III D) against the oracle,
+through the C-ABI: h3 in place of h1, h2, per-node tau_h3 from D_eff,
+equilibrium on c / K_eff.  Same tolerances as the two-scalar step: FP64
+to round-off (1e-12), FP32 1e-5, FP16 storage 2e-3."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "c1", "c2", "ux", "uy", "p", "mu", "psi")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cplb():
+    import torch
+
+    from paper_2402_15752_amd import cplb as C
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    C.library()
+    return C
+
+
+def rel_err(a, b):
+    scale = max(np.linalg.norm(b), np.linalg.norm(b - b.mean()), 1e-300)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / scale)
+
+
+def compare(g, o, names, tol, label):
+    errs = {}
+    for k in names:
+        a = g.field(k).cpu().numpy()
+        assert np.all(np.isfinite(a)), (label, k)
+        errs[k] = rel_err(a, o.field(k))
+    say(f"  {label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, bad)
+
+
+@pytest.mark.parametrize("periodic", [(1, 1, 1), (0, 1, 1), (1, 0, 1), (0, 0, 1)])
+@pytest.mark.parametrize("shape", [(67, 37), (5, 3), (130, 9)])
+def test_one_scalar_fp64_random_fields(cplb, periodic, shape):
+    nx, ny = shape
+    say(f"one-scalar fp64 random {shape} periodic={periodic}")
+    p = W.params(nx=nx, ny=ny, periodic=periodic, precision="f64", sigma=2e-3, rho1=3.0,
+                 rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07, D2=0.02, Keq=0.6,
+                 g=(2e-5, -3e-5, 0.0), rho_ref=1.5, scalar_model="one")
+    f = W.random_fields(p, seed=nx * 5 + ny)
+    g = cplb.Lattice(p)
+    o = ref.Oracle(p)
+    for x in (g, o):
+        x.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    compare(g, o, FIELDS, 1e-13, "t=0")
+    g.step(3)
+    o.step(3)
+    compare(g, o, FIELDS, 1e-12, "t=3")
+    r, ro = g.reduce(), o.reduce()
+    assert abs(r["sum_c"] - ro["sum_c"]) <= 1e-12 * abs(ro["sum_c"])
+
+
+def test_one_scalar_large_diffusivity_ratio_fp64(cplb):
+    """The 1-D leakage case (D1/D2 = 10^4, Keq = 1) on a y-uniform D2Q9
+    lattice, 2000 steps: the GPU follows the oracle, leak included."""
+    N = 200
+    x = (np.arange(N) + 0.5) / N * 2.0 - 1.0
+    l = ((0.5 - np.abs(x)) * N / 2.0).reshape(1, N)
+    p = W.params(nx=N, ny=1, periodic=(1, 1, 1), sigma=0.0, D1=0.1, D2=1e-5, Keq=1.0,
+                 precision="f64", scalar_model="one")
+    g = cplb.Lattice(p)
+    o = ref.Oracle(p)
+    for s in (g, o):
+        s.init_sdf(l, c1=(0.0, 1.0))
+    g.step(2000)
+    o.step(2000)
+    compare(g, o, ("phi", "c1", "c2"), 1e-10, "t=2000")
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-5), ("f32_s16f", 2e-3)])
+def test_one_scalar_rising_bubble(cplb, precision, tol):
+    w = W.rising_bubble_2d(nx=64, ny=256, precision=precision, scalar_model="one")
+    say(f"one-scalar rising bubble 64x256 {precision}, 1000 steps")
+    p = w["params"]
+    g = cplb.Lattice(p)
+    o = ref.Oracle(dict(p, precision="f64"))
+    for s in (g, o):
+        s.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    r0 = g.reduce()
+    g.step(1000)
+    o.step(1000)
+    compare(g, o, ("phi", "c1", "c2", "ux", "uy", "p"), tol, f"{precision} t=1000")
+    r = g.reduce()
+    assert abs(r["sum_c"] - r0["sum_c"]) <= (1e-6 if precision == "f32" else 1e-4) * r0["sum_c"]
+
+
+def test_one_scalar_refuses_a_closure(cplb):
+    import torch
+    p = W.params(nx=16, ny=8, precision="f32", scalar_model="one")
+    g = cplb.Lattice(p)
+    with pytest.raises(cplb.CplbError) as e:
+        g.set_closure(torch.zeros((8, 16), dtype=torch.float32, device="cuda"))
+    assert e.value.code == cplb.CPLB_EINVAL

@@ -270,6 +270,7 @@ VARIANT_CASES = [
     ("d2q9 f64", dict(nx=67, ny=37, periodic=(1, 0, 1), precision="f64")),
     ("d2q9 f32", dict(nx=130, ny=9, periodic=(0, 1, 1), precision="f32")),
     ("d2q9 s16f", dict(nx=67, ny=37, periodic=(1, 1, 1), precision="f32_s16f")),
+    ("d2q9 one f32", dict(nx=67, ny=37, periodic=(0, 1, 1), precision="f32", scalar_model="one")),
     ("d3 f64", dict(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=(1, 0, 0),
                     precision="f64")),
     ("d3 f32", dict(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=(0, 1, 0),
