@@ -323,6 +323,19 @@ int cplb_cnn_set_input_scale(cplb_cnn_t* c, const float scale[16]);
  * (device, may be NULL) receives [nsamples][H][W] FP32.  Asynchronous. */
 int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin, float* dev_out);
 
+/* Inference: the forward pass without the FP32 pre-activations the
+ * backward pass needs (activations in BF16 only, the output scaled and
+ * written by the last convolution).  dev_out (device) receives
+ * [nsamples][H][W] FP32, bitwise equal to cplb_cnn_forward's output.  A
+ * following cplb_cnn_backward needs a cplb_cnn_forward first.  No host
+ * synchronisation and no allocation: capturable in a HIP graph.
+ * Asynchronous. */
+int cplb_cnn_infer(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin, float* dev_out);
+
+/* Stream of every following call (hip_stream is a hipStream_t); the caller
+ * orders it after work already queued on the previous stream. */
+int cplb_cnn_set_stream(cplb_cnn_t* c, void* hip_stream);
+
 /* Loss mean((out - target)^2) of the last forward against dev_target
  * ([nsamples][H][W] FP32, device), accumulated in FP64, and the gradient of
  * every parameter (FP32).  *loss (may be NULL) receives the loss; with it

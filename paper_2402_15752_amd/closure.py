@@ -145,6 +145,7 @@ def generate(cases, steps, stream=None, log=None, net=None, skip=5):
     if net is not None:
         s = torch.zeros(n * nc * nc, dtype=torch.float32, device=dev)
         R.coarse.set_closure(s)
+        net.set_stream(R.stream)
     x = R.coarse.gather(FIELDS, out=R.coarse_buf, nplanes=N_PLANES)
     with torch.cuda.stream(R.stream):
         x[:, len(FIELDS):] = R.planes[:, len(FIELDS):]
@@ -154,7 +155,7 @@ def generate(cases, steps, stream=None, log=None, net=None, skip=5):
         with torch.cuda.stream(R.stream):
             X[k] = x
         if net is not None:
-            net.forward(x, out=s.view(n, nc, nc))
+            net.infer(x, out=s.view(n, nc, nc))
         R.coarse.step(1)
         R.fine.step(F * F)
         R.restricted_fine(fine)
@@ -222,7 +223,8 @@ def rel_l2(a, b):
 def evaluate(cases, steps, net=None, stream=None, log=None):
     """Free coarse runs of `cases` for `steps` coarse steps, plain and with
     the closure network, against the restricted fine run of F^2 steps each.
-    Returns per-case scalar errors and wall times (graph-free launches, one
+    Returns per-case scalar errors and wall times (the fine run from the
+    library's own step loop, the coarse runs replayed from HIP graphs; one
     synchronisation at the end of each run)."""
     import torch
     R = Runner(cases, stream)
@@ -244,28 +246,53 @@ def evaluate(cases, steps, net=None, stream=None, log=None):
     torch.cuda.synchronize()
     ref = ref.cpu().numpy()
 
-    def run(with_net):
+    # a captured graph replays its steps from the lattice parity it was
+    # captured at: whole graphs of an even number of steps keep it
+    assert steps % 2 == 0, "evaluate needs an even number of coarse steps"
+
+    def run(with_net, chunk=10):
+        # `chunk` coarse steps (gather, network, step) captured once in a HIP
+        # graph on the runner's stream and replayed: the wall time is that
+        # of the GPU work, not of the Python launches
         R.coarse_from(planes0)
         s = None
         if with_net:
             s = torch.zeros(n * nc * nc, dtype=torch.float32, device=R.fine.device)
             R.coarse.set_closure(s)
+            net.set_stream(R.stream)
         else:
             R.coarse.set_closure(None)
+        x = R.coarse.gather(FIELDS, out=R.coarse_buf, nplanes=N_PLANES)
+        with torch.cuda.stream(R.stream):
+            x[:, len(FIELDS):] = planes0[:, len(FIELDS):]
+
+        def steps_of(k):
+            for _ in range(k):
+                if with_net:
+                    R.coarse.gather(FIELDS, out=R.coarse_buf, nplanes=N_PLANES)
+                    net.infer(x, out=s.view(n, nc, nc))
+                R.coarse.step(1)
+
+        graphs = {}
+        for k in {chunk, steps % chunk} - {0}:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=R.stream):
+                steps_of(k)
+            graphs[k] = g
+        # capturing ran nothing: restart from the initial state
+        R.coarse_from(planes0)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
-            if with_net:
-                x = R.coarse.gather(FIELDS, out=R.coarse_buf, nplanes=N_PLANES)
-                if _ == 0:
-                    with torch.cuda.stream(R.stream):
-                        x[:, len(FIELDS):] = planes0[:, len(FIELDS):]
-                net.forward(x, out=s.view(n, nc, nc))
-            R.coarse.step(1)
+        with torch.cuda.stream(R.stream):
+            for _ in range(steps // chunk):
+                graphs[chunk].replay()
+            if steps % chunk:
+                graphs[steps % chunk].replay()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         out = R.coarse.gather(FIELDS).cpu().numpy()
         R.coarse.set_closure(None)
+        del graphs
         return out, dt
 
     plain, t_plain = run(False)

@@ -42,7 +42,8 @@ EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init
            "cplb_cnn_set_input_scale", "cplb_cnn_forward", "cplb_cnn_backward",
            "cplb_cnn_get_grads", "cplb_cnn_adam", "cplb_cnn_last_error", "cplb_cnn_destroy",
            "cplb_batch_num_nodes", "cplb_batch_set_closure", "cplb_batch_gather_fields",
-           "cplb_cnn_set_output_scale", "cplb_cnn_restrict", "cplb_batch_init_planes")
+           "cplb_cnn_set_output_scale", "cplb_cnn_restrict", "cplb_batch_init_planes",
+           "cplb_cnn_infer", "cplb_cnn_set_stream")
 
 
 class cplb_params(ctypes.Structure):
@@ -134,6 +135,8 @@ def library():
         L.cplb_cnn_get_params.argtypes = [vp, fp]
         L.cplb_cnn_set_input_scale.argtypes = [vp, fp]
         L.cplb_cnn_forward.argtypes = [vp, i32, vp, i32, vp]
+        L.cplb_cnn_infer.argtypes = [vp, i32, vp, i32, vp]
+        L.cplb_cnn_set_stream.argtypes = [vp, vp]
         L.cplb_cnn_backward.argtypes = [vp, vp, dp]
         L.cplb_cnn_get_grads.argtypes = [vp, fp]
         L.cplb_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -789,6 +792,28 @@ class ClosureNet:
         cplb_cnn_forward(self._c, B, planes.data_ptr(), cin, out.data_ptr())
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return out
+
+    def infer(self, planes, out=None):
+        """Inference (no training buffers): planes [B, cin, H, W] float32
+        device tensor -> [B, H, W], equal to forward()."""
+        torch = self.torch
+        assert planes.dtype == torch.float32 and planes.is_contiguous()
+        B, cin = int(planes.shape[0]), int(planes.shape[1])
+        if out is None:
+            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == B * self.H * self.W
+        self._order()
+        _ccheck(self._c, library().cplb_cnn_infer(self._c, B, ctypes.c_void_p(planes.data_ptr()),
+                                                  cin, ctypes.c_void_p(out.data_ptr())))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def set_stream(self, stream):
+        """Run every following call on `stream` (a torch stream), after the
+        work already queued on the current one."""
+        stream.wait_stream(self.stream)
+        _ccheck(self._c, library().cplb_cnn_set_stream(self._c, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def backward(self, target) -> float:
         """Loss of the last forward against target [B, H, W] (FP64), and

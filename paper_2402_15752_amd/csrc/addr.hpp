@@ -43,6 +43,27 @@ __device__ inline Off plane(int k, Off stride) {
     return Off(k) * stride;
 }
 
+// Plane skew of the population sets.  Plane i of a set is stored shifted by
+// -c_ix nodes: the push store of direction i (to x + c_i) then starts a
+// wave's run on the aligned address the own node x would have, and the
+// one-node misalignment moves to the loads, which do not pay for it (a run
+// of stores shifted by one node costs 14% (FP32) to 24% (16-bit) of the
+// bandwidth on MI355X, a run of shifted loads nothing).  The padding of
+// every plane (>= 64 values past the last node) absorbs the shift; plane 0
+// of every set is the rest direction and is not shifted.  Every access to a
+// population plane adds skew<L, S>(i): loads, push and bounce-back stores
+// and the initialisation.
+template <class L, class S, class Off>
+__device__ constexpr Off skew(int i) {
+  return L::cx[i] > 0 ? Off(0) - Off(sizeof(S)) : (L::cx[i] < 0 ? Off(sizeof(S)) : Off(0));
+}
+
+// the same in elements, for element-indexed accesses
+template <class L>
+__device__ constexpr long long skew_el(int i) {
+  return -(long long)L::cx[i];
+}
+
 template <class P, class Off>
 __device__ inline P* at(P* base, Off off) {
   using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
@@ -81,7 +102,8 @@ template <class L, bool NTS, bool PIN, class S, class T, class Off>
 __device__ inline void load_q(const S* __restrict__ base, Off sS, Off node, T (&x)[L::Q]) {
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    x[i] = Codec<S, T>::ld(ld_pop<NTS>(at(base, plane<PIN>(i, sS) + node)), T(L::w[i]));
+    x[i] = Codec<S, T>::ld(ld_pop<NTS>(at(base, plane<PIN>(i, sS) + node + skew<L, S, Off>(i))),
+                           T(L::w[i]));
 }
 
 // Push deltas of one lane (bytes, modular arithmetic in Off) and its

@@ -139,7 +139,8 @@ int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, cons
   return CPLB_OK;
 }
 
-constexpr uint32_t kStateMagic = 0x42504C43u;  // "CLPB"
+// "CLP2": lattices with the skewed plane layout of the push streaming
+constexpr uint32_t kStateMagic = 0x32504C43u;
 
 struct StateHeader {
   uint32_t magic, abi;
@@ -308,7 +309,8 @@ int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes) {
   o += sizeof(hd);
   const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
   for (int q = 0; q < h->G.qtot; ++q, o += pb) {
-    rc = hip_check(h, hipMemcpy(o, (char*)h->lat[h->cur] + q * h->G.stride * h->G.s_pop, pb,
+    const long long first = q * h->G.stride + plane_skew_el(h->G.dim, q);  // node 0 of plane q
+    rc = hip_check(h, hipMemcpy(o, (char*)h->lat[h->cur] + first * h->G.s_pop, pb,
                                 hipMemcpyDeviceToHost), "checkpoint copy");
     if (rc) return rc;
   }
@@ -334,7 +336,8 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
   const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
   h->cur = 0;
   for (int q = 0; q < h->G.qtot; ++q, o += pb) {
-    rc = hip_check(h, hipMemcpy((char*)h->lat[0] + q * h->G.stride * h->G.s_pop, o, pb,
+    const long long first = q * h->G.stride + plane_skew_el(h->G.dim, q);  // node 0 of plane q
+    rc = hip_check(h, hipMemcpy((char*)h->lat[0] + first * h->G.s_pop, o, pb,
                                 hipMemcpyHostToDevice), "restore copy");
     if (rc) return rc;
   }

@@ -1,4 +1,5 @@
 // Initialisation, field conversion and reductions.
+#include "addr.hpp"
 #include "kernels.hpp"
 
 namespace pflb {
@@ -48,12 +49,15 @@ __global__ __launch_bounds__(256) void init_kernel(S* __restrict__ lat, T* __res
   const long long st = P.stride;
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
-    store_one<LF>(lat, (Lay::F0 + i) * st + node, i, f[i]);
-    store_one<LF>(lat, (Lay::H10 + i) * st + node, i, h1[i]);
-    store_one<LF>(lat, (Lay::H20 + i) * st + node, i, h2[i]);
+    // plane skew of the push streaming (addr.hpp)
+    const long long n = node + skew_el<LF>(i);
+    store_one<LF>(lat, (Lay::F0 + i) * st + n, i, f[i]);
+    store_one<LF>(lat, (Lay::H10 + i) * st + n, i, h1[i]);
+    store_one<LF>(lat, (Lay::H20 + i) * st + n, i, h2[i]);
   }
 #pragma unroll
-  for (int i = 0; i < LG::Q; ++i) store_one<LG>(lat, (Lay::G0 + i) * st + node, i, g[i]);
+  for (int i = 0; i < LG::Q; ++i)
+    store_one<LG>(lat, (Lay::G0 + i) * st + node + skew_el<LG>(i), i, g[i]);
   int k = 0;
   for (int a = 0; a < LG::D; ++a) hist[(k++) * st + node] = u[a];
   hist[(k++) * st + node] = T(phi);

@@ -48,150 +48,204 @@ __device__ inline float4v mfma(short4v a, short4v b, float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2 };
+enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2, kInfAct = 3, kInfOut = 4 };
 
-// One wave: 16 consecutive pixels of a row x all COUT channels.
+constexpr int kConvGroups = 2;  // 16-pixel groups per wave
+
+// One wave: G groups of 16 consecutive pixels of a row x all COUT channels;
+// the weight operand of each (tap, channel group) is loaded once for the G
+// groups.  Waves are laid over (row, segment of 16 G pixels), so short rows
+// still fill every wave of a block.
 // kFwdAct / kFwdLinear: Z = conv(X) + b (FP32), A = act(Z) (BF16).
+// kInfAct: A = lrelu(conv(X) + b) only (inference: no FP32 copy).
+// kInfOut: out[p] = scale * (conv(X) + b)[channel 0], written to Z.
 // kBwd: X is dZ of the layer above, W its flipped transpose; the result is
 // dA of the layer below, written as dZ = dA * lrelu'(Zprev) in BF16.
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, int G>
 __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restrict__ X,
                                                    const unsigned short* __restrict__ Wg,
                                                    const float* __restrict__ bias,
                                                    float* __restrict__ Z,
                                                    unsigned short* __restrict__ A,
                                                    const float* __restrict__ Zprev, int H, int W,
-                                                   int rows) {
+                                                   int rows, float scale) {
   constexpr int NT = COUT / 16, K = 9 * CIN;
   static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R = blockIdx.y;  // global row (sample * H + y)
+  const int lane = threadIdx.x & 63;
+  const int segs = (W + 16 * G - 1) / (16 * G);
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int R = wid / segs;  // global row (sample * H + y)
   if (R >= rows) return;
-  const int x0 = blockIdx.x * 64 + wave * 16;
-  if (x0 >= W) return;
+  const int xw = (wid - R * segs) * 16 * G;  // first pixel of the wave
   const int m = lane & 15, g = lane >> 4;
   const int y = R % H;
-  const int x = x0 + m;  // pixel of this lane's A row
-  float4v acc[NT];
+  float4v acc[G][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const bool ok = x < W && y + dy >= 0 && y + dy < H;
-    int xs = x + dx;
-    xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-    const long long ps = (long long)(R + dy) * W + xs;
+    const bool rowok = y + dy >= 0 && y + dy < H;
+    const long long rowbase = (long long)(R + dy) * W;
 #pragma unroll
     for (int cg = 0; cg < CIN / 16; ++cg) {
-      const short4v a = ok ? load4(X + ps * CIN + cg * 16 + 4 * g) : short4v{0, 0, 0, 0};
       const int k = tap * CIN + cg * 16 + 4 * g;
+      short4v b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const short4v b = load4(Wg + (long long)(t * 16 + m) * K + k);
-        acc[t] = mfma(a, b, acc[t]);
+      for (int t = 0; t < NT; ++t) b[t] = load4(Wg + (long long)(t * 16 + m) * K + k);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int x = xw + q * 16 + m;  // pixel of this lane's A row
+        int xs = x + dx;
+        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+        const short4v a = rowok && x < W ? load4(X + (rowbase + xs) * CIN + cg * 16 + 4 * g)
+                                         : short4v{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = mfma(a, b[t], acc[q][t]);
       }
     }
   }
   // D[pixel 4 g + j][channel l % 16]
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + m;
+  for (int q = 0; q < G; ++q) {
+    const int x0 = xw + q * 16;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int xp = x0 + 4 * g + j;
-      if (xp >= W) continue;
-      const long long p = (long long)R * W + xp;
-      float v = acc[t][j];
-      if (MODE == kBwd) {
-        const float zp = Zprev[p * COUT + co];
-        v *= zp > 0.f ? 1.f : kSlope;
-        A[p * COUT + co] = to_bf16(v);
-      } else {
-        v += bias[co];
-        Z[p * COUT + co] = v;
-        A[p * COUT + co] = to_bf16(MODE == kFwdAct ? (v > 0.f ? v : kSlope * v) : v);
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + m;
+      if (MODE == kInfOut && co != 0) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int xp = x0 + 4 * g + j;
+        if (xp >= W) continue;
+        const long long p = (long long)R * W + xp;
+        float v = acc[q][t][j];
+        if (MODE == kBwd) {
+          const float zp = Zprev[p * COUT + co];
+          v *= zp > 0.f ? 1.f : kSlope;
+          A[p * COUT + co] = to_bf16(v);
+        } else if (MODE == kInfOut) {
+          Z[p] = scale * (v + bias[0]);
+        } else {
+          v += bias[co];
+          if (MODE != kInfAct) Z[p * COUT + co] = v;
+          A[p * COUT + co] = to_bf16(MODE == kFwdLinear ? v : (v > 0.f ? v : kSlope * v));
+        }
       }
     }
   }
 }
 
-// Weight gradient: partial[chunk][co][k] = sum over the chunk's pixels p of
-// dZ[p][co] * X(p shifted by tap(k))[ci(k)].  One wave per 16 x 16 tile of
-// (co, k) and chunk; the pixel sum is the MFMA's K dimension.
+// Weight and bias gradients, per chunk of pixels:
+//   partial[chunk][co][k] = sum_p dZ[p][co] * X(p shifted by tap(k))[ci(k)],
+//   bpart[chunk][co]      = sum_p dZ[p][co].
+// One wave per 16-wide tile of k = tap * CIN + ci and chunk, all output
+// channels at once (the shifted-X operand is loaded once for every co tile);
+// the pixel sum is the MFMA's K dimension.  Each lane walks its four pixels
+// p = pb + 4 g + j with 32-bit row / column counters instead of dividing.
+// The k tile 0 also sums its dZ operand for the bias.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void wgrad_kernel(const unsigned short* __restrict__ X,
                                                     const unsigned short* __restrict__ dZ,
-                                                    float* __restrict__ partial, int H, int W,
-                                                    long long P, int chunk) {
+                                                    float* __restrict__ partial,
+                                                    float* __restrict__ bpart, int H, int W,
+                                                    int P, int chunk) {
   constexpr int K = 9 * CIN, MT = COUT / 16, NTL = K / 16;
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= MT * NTL) return;
-  const int mt = tile / NTL, nt = tile % NTL;
+  const int nt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (nt >= NTL) return;
   const int c = blockIdx.y;
   const int m = lane & 15, g = lane >> 4;
-  const int co = mt * 16 + m;      // A row of this lane
-  const int kk = nt * 16 + m;      // B column of this lane
+  const int kk = nt * 16 + m;  // B column of this lane
   const int tap = kk / CIN, ci = kk % CIN;
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const long long p0 = (long long)c * chunk;
-  const long long p1 = p0 + chunk < P ? p0 + chunk : P;
-  float4v acc = {0.f, 0.f, 0.f, 0.f};
-  for (long long pb = p0; pb < p1; pb += 16) {
-    short4v a, b;
+  const int p0 = c * chunk;
+  const int p1 = p0 + chunk < P ? p0 + chunk : P;
+  // row R (sample * H + y), column x and y of the lane's pixel p0 + 4 g + j
+  int R[4], xc[4], yc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = p0 + 4 * g + j;
+    R[j] = p / W;
+    xc[j] = p - R[j] * W;
+    yc[j] = R[j] % H;
+  }
+  float4v acc[MT];
+  float bsum[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
+    bsum[t] = 0.f;
+  }
+  for (int pb = p0; pb < p1; pb += 16) {
+    short4v a[MT], b;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long p = pb + 4 * g + j;
-      unsigned short av = 0, bv = 0;
-      if (p < p1) {
-        av = dZ[p * COUT + co];
-        const long long R = p / W;
-        const int x = (int)(p - R * W), y = (int)(R % H);
-        if (y + dy >= 0 && y + dy < H) {
-          int xs = x + dx;
-          xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-          bv = X[((R + dy) * W + xs) * CIN + ci];
-        }
+      const int p = pb + 4 * g + j;
+      const bool valid = p < p1;
+      unsigned short bv = 0;
+      if (valid && yc[j] + dy >= 0 && yc[j] + dy < H) {
+        int xs = xc[j] + dx;
+        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+        bv = X[((long long)(R[j] + dy) * W + xs) * CIN + ci];
       }
-      a[j] = (short)av;
       b[j] = (short)bv;
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        a[t][j] = (short)(valid ? dZ[(long long)p * COUT + t * 16 + m] : (unsigned short)0);
+      // advance to pixel p + 16
+      xc[j] += 16;
+      while (xc[j] >= W) {
+        xc[j] -= W;
+        ++R[j];
+        if (++yc[j] == H) yc[j] = 0;
+      }
     }
-    acc = mfma(a, b, acc);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      acc[t] = mfma(a[t], b, acc[t]);
+      if (nt == 0)
+        bsum[t] += (from_bf16((unsigned short)a[t][0]) + from_bf16((unsigned short)a[t][1])) +
+                   (from_bf16((unsigned short)a[t][2]) + from_bf16((unsigned short)a[t][3]));
+    }
   }
   // D[co row 4 g + j][k column l % 16]
   float* out = partial + (long long)c * COUT * K;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) out[(long long)(mt * 16 + 4 * g + j) * K + nt * 16 + m] = acc[j];
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(t * 16 + 4 * g + j) * K + nt * 16 + m] = acc[t][j];
+  if (nt == 0) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      float v = bsum[t];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (g == 0) bpart[c * COUT + t * 16 + m] = v;
+    }
+  }
 }
 
-// grad W[co][ci][ky][kx] = sum over chunks of partial[chunk][co][tap * CIN + ci]
-__global__ void wgrad_reduce(const float* __restrict__ partial, int nchunks, int cin, int cout,
-                             float* __restrict__ grad) {
+// grad W[co][ci][ky][kx] = sum over chunks of partial[chunk][co][tap * CIN + ci];
+// grad b[co] = sum over chunks of bpart[chunk][co]
+__global__ void wgrad_reduce(const float* __restrict__ partial, const float* __restrict__ bpart,
+                             int nchunks, int cin, int cout, float* __restrict__ gradW,
+                             float* __restrict__ gradb) {
   const int K = 9 * cin;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // oracle layout index
-  if (i >= cout * K) return;
-  const int co = i / K, r = i % K, ci = r / 9, tap = r % 9;
-  const long long src = (long long)co * K + tap * cin + ci;
-  float s = 0.f;
-  for (int c = 0; c < nchunks; ++c) s += partial[(long long)c * cout * K + src];
-  grad[i] = s;
-}
-
-// grad b[co] = sum_p dZ[p][co]; one block per output channel
-__global__ void bgrad_kernel(const unsigned short* __restrict__ dZ, long long P, int cout,
-                             float* __restrict__ grad) {
-  __shared__ float red[256];
-  const int co = blockIdx.x;
-  float s = 0.f;
-  for (long long p = threadIdx.x; p < P; p += blockDim.x) s += from_bf16(dZ[p * cout + co]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  if (i < cout * K) {
+    const int co = i / K, r = i % K, ci = r / 9, tap = r % 9;
+    const long long src = (long long)co * K + tap * cin + ci;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += partial[(long long)c * cout * K + src];
+    gradW[i] = s;
+  } else if (i < cout * K + cout) {
+    const int co = i - cout * K;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += bpart[c * cout + co];
+    gradb[co] = s;
   }
-  if (threadIdx.x == 0) grad[co] = red[0];
 }
 
 // FP32 planes [sample][c][y][x] (c < cin) -> X0[p][16] in BF16, scaled
@@ -297,45 +351,59 @@ __global__ void weights_kernel(const float* __restrict__ W, int cin, int cout,
 
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
-                    int W, int rows, hipStream_t s) {
-  const dim3 grid((W + 63) / 64, rows), blk(256);
+                    int W, int rows, float scale, hipStream_t s) {
+  constexpr int G = kConvGroups;
+  const long long waves = (long long)rows * ((W + 16 * G - 1) / (16 * G));
+  const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+#define PFLB_CONV(CI, CO, MO) \
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MO, G>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, scale)
   // forward: layer l maps C_in(l) -> C_out(l); backward (the adjoint of
   // layer l) maps C_out(l) -> C_in(l)
-  if (mode != kBwd) {
-    switch (layer) {
-      case 0: hipLaunchKernelGGL((conv_kernel<16, 32, kFwdAct>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
-      case 1: case 2: hipLaunchKernelGGL((conv_kernel<32, 32, kFwdAct>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
-      default: hipLaunchKernelGGL((conv_kernel<32, 16, kFwdLinear>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows);
-    }
-  } else {
-    switch (layer) {
-      case 1: case 2: hipLaunchKernelGGL((conv_kernel<32, 32, kBwd>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
-      case 3: hipLaunchKernelGGL((conv_kernel<16, 32, kBwd>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows); break;
-      default: return hipErrorInvalidValue;  // the input layer needs no input gradient
-    }
+  switch (mode) {
+    case kFwdAct:
+    case kFwdLinear:
+      switch (layer) {
+        case 0: PFLB_CONV(16, 32, kFwdAct); break;
+        case 1: case 2: PFLB_CONV(32, 32, kFwdAct); break;
+        default: PFLB_CONV(32, 16, kFwdLinear);
+      }
+      break;
+    case kInfAct:
+    case kInfOut:
+      switch (layer) {
+        case 0: PFLB_CONV(16, 32, kInfAct); break;
+        case 1: case 2: PFLB_CONV(32, 32, kInfAct); break;
+        default: PFLB_CONV(32, 16, kInfOut);
+      }
+      break;
+    default:
+      switch (layer) {
+        case 1: case 2: PFLB_CONV(32, 32, kBwd); break;
+        case 3: PFLB_CONV(16, 32, kBwd); break;
+        default: return hipErrorInvalidValue;  // the input layer needs no input gradient
+      }
   }
+#undef PFLB_CONV
   return hipGetLastError();
 }
 
 hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
-                     int nchunks, int chunk, int H, int W, long long P, float* gradW, float* gradb,
-                     hipStream_t s) {
+                     float* bpart, int nchunks, int chunk, int H, int W, long long P, float* gradW,
+                     float* gradb, hipStream_t s) {
   const int cin = layer == 0 ? 16 : 32, cout = layer == 3 ? 16 : 32;
-  const int tiles = (cout / 16) * (9 * cin / 16);
-  const dim3 grid((tiles + 3) / 4, nchunks), blk(256);
+  const int ntiles = 9 * cin / 16;
+  const dim3 grid((ntiles + 3) / 4, nchunks), blk(256);
+  const int Pi = (int)P;
   switch (layer) {
-    case 0: hipLaunchKernelGGL((wgrad_kernel<16, 32>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk); break;
-    case 1: case 2: hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk); break;
-    default: hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, blk, 0, s, X, dZ, partial, H, W, P, chunk);
+    case 0: hipLaunchKernelGGL((wgrad_kernel<16, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk); break;
+    case 1: case 2: hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk); break;
+    default: hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nw = cout * cin * 9;
-  hipLaunchKernelGGL(wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, s, partial, nchunks, cin,
-                     cout, gradW);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bgrad_kernel, dim3(cout), dim3(256), 0, s, dZ, P, cout, gradb);
+  const int n = cout * cin * 9 + cout;
+  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, bpart, nchunks,
+                     cin, cout, gradW, gradb);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ int w_offset(int l) {  // start of W of layer l in the parameter vector
 
 struct CnnLayout {
   size_t theta, m, v, grad, wg[kLayers], wf[kLayers], scale, x0, z[kLayers], a[kLayers],
-      dz[kLayers], wpart, lpart, loss, total;
+      dz[kLayers], wpart, bpart, lpart, loss, total;
 };
 
 CnnLayout cnn_layout(long long P) {
@@ -65,6 +65,7 @@ CnnLayout cnn_layout(long long P) {
   }
   const long long nchunks = (P + kChunk - 1) / kChunk;
   L.wpart = take((size_t)nchunks * 32 * 9 * 32 * 4);
+  L.bpart = take((size_t)nchunks * 32 * 4);
   L.lpart = take(kLossParts * 8);
   L.loss = take(8);
   L.total = off;
@@ -251,9 +252,9 @@ int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int c
   const unsigned short* x = c->at<unsigned short>(c->L.x0);
   for (int l = 0; l < kLayers; ++l) {
     const float* bias = c->at<float>(c->L.theta) + w_offset(l) + kCout[l] * kCin[l] * 9;
-    rc = hip_check(c, cnn_conv(l, l == kLayers - 1 ? 1 : 0, x, c->at<unsigned short>(c->L.wg[l]), bias,
+    rc = hip_check(c, cnn_conv(l, kConvForward, x, c->at<unsigned short>(c->L.wg[l]), bias,
                                c->at<float>(c->L.z[l]), c->at<unsigned short>(c->L.a[l]), nullptr,
-                               c->H, c->W, rows, c->stream), "forward convolution");
+                               c->H, c->W, rows, 1.f, c->stream), "forward convolution");
     if (rc) return rc;
     x = c->at<unsigned short>(c->L.a[l]);
   }
@@ -262,6 +263,39 @@ int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int c
     rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, c->out_scale, dev_out,
                                  c->stream), "output copy");
   return rc;
+}
+
+int cplb_cnn_infer(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin, float* dev_out) {
+  if (!c) return CPLB_EINVAL;
+  if (nsamples < 1 || nsamples > c->nsamples)
+    return set_err(c, CPLB_EINVAL, "nsamples %d outside 1..%d", nsamples, c->nsamples);
+  if (cin < 1 || cin > 16) return set_err(c, CPLB_EINVAL, "input planes %d outside 1..16", cin);
+  if (!dev_planes || !dev_out) return set_err(c, CPLB_EINVAL, "null input planes or output");
+  const long long hw = (long long)c->H * c->W, P = nsamples * hw;
+  const int rows = nsamples * c->H;
+  int rc = hip_check(c, cnn_pack(dev_planes, cin, c->at<float>(c->L.scale), hw, P,
+                                 c->at<unsigned short>(c->L.x0), c->stream), "input packing");
+  if (rc) return rc;
+  // activations ping-pong between a[0] and a[1]; no FP32 pre-activations
+  const unsigned short* x = c->at<unsigned short>(c->L.x0);
+  for (int l = 0; l < kLayers && rc == CPLB_OK; ++l) {
+    const float* bias = c->at<float>(c->L.theta) + w_offset(l) + kCout[l] * kCin[l] * 9;
+    unsigned short* a = c->at<unsigned short>(c->L.a[l % 2]);
+    const bool last = l == kLayers - 1;
+    rc = hip_check(c, cnn_conv(l, last ? kConvInferOut : kConvInfer, x,
+                               c->at<unsigned short>(c->L.wg[l]), bias, last ? dev_out : nullptr,
+                               a, nullptr, c->H, c->W, rows, c->out_scale, c->stream),
+                   "inference convolution");
+    x = a;
+  }
+  c->used_P = 0;  // the training buffers of the last forward are gone
+  return rc;
+}
+
+int cplb_cnn_set_stream(cplb_cnn_t* c, void* hip_stream) {
+  if (!c) return CPLB_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return CPLB_OK;
 }
 
 int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
@@ -282,14 +316,14 @@ int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
     const unsigned short* xin = l == 0 ? c->at<unsigned short>(c->L.x0) : c->at<unsigned short>(c->L.a[l - 1]);
     const int wo = w_offset(l);
     rc = hip_check(c, cnn_wgrad(l, xin, c->at<unsigned short>(c->L.dz[l]), c->at<float>(c->L.wpart),
-                                nchunks, kChunk, c->H, c->W, P, grad + wo,
+                                c->at<float>(c->L.bpart), nchunks, kChunk, c->H, c->W, P, grad + wo,
                                 grad + wo + kCout[l] * kCin[l] * 9, c->stream),
                    "weight gradient");
     if (rc || l == 0) break;
-    rc = hip_check(c, cnn_conv(l, 2, c->at<unsigned short>(c->L.dz[l]),
+    rc = hip_check(c, cnn_conv(l, kConvAdjoint, c->at<unsigned short>(c->L.dz[l]),
                                c->at<unsigned short>(c->L.wf[l]), nullptr, nullptr,
                                c->at<unsigned short>(c->L.dz[l - 1]), c->at<float>(c->L.z[l - 1]),
-                               c->H, c->W, rows, c->stream), "input gradient");
+                               c->H, c->W, rows, 1.f, c->stream), "input gradient");
   }
   if (rc) return rc;
   if (loss) {

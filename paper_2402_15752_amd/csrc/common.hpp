@@ -521,14 +521,6 @@ __device__ inline void st_pop(S* p, S v) {
 }
 
 template <class L, bool NTS = false, class S, class T>
-__device__ inline void load_set(const S* __restrict__ src, long long stride, long long node,
-                                int plane0, T (&x)[L::Q]) {
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    x[i] = Codec<S, T>::ld(ld_pop<NTS>(src + (plane0 + i) * stride + node), T(L::w[i]));
-}
-
-template <class L, bool NTS = false, class S, class T>
 __device__ inline void store_one(S* __restrict__ dst, long long idx, int i, T x) {
   st_pop<NTS>(dst + idx, Codec<S, T>::st(x, T(1.0 / L::w[i])));
 }

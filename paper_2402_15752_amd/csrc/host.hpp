@@ -80,6 +80,17 @@ inline Geometry geometry(const cplb_params* p) {
   return G;
 }
 
+// Plane skew (elements) of population plane q of the lattice layout: plane i
+// of a set is stored shifted by -c_ix nodes (see addr.hpp); host copies of
+// whole planes (checkpoints) start there.
+inline long long plane_skew_el(int dim, int q) {
+  if (dim == 2) return -(long long)D2Q9::cx[q % 9];
+  using Lay = Layout<D3Q7, D3Q19>;
+  if (q < Lay::G0) return -(long long)D3Q7::cx[q];
+  if (q < Lay::H10) return -(long long)D3Q19::cx[q - Lay::G0];
+  return -(long long)D3Q7::cx[(q - Lay::H10) % 7];
+}
+
 // every 2-D set (9 planes), the history and the field buffer below 4 GiB:
 // 32-bit byte offsets reach every value
 inline bool fits_u32_planes(const Geometry& G) {

@@ -76,14 +76,17 @@ hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max
 // ------------------------------------------------------- closure network
 // (cnn.hip) layer l = 0..3 maps C_in = 16, 32, 32, 32 to C_out = 32, 32, 32,
 // 16; activations NHWC BF16, P pixels of `rows` rows of width W, samples of
-// H rows stacked.  mode 0: leaky-ReLU forward, 1: linear forward, 2: the
-// adjoint of layer l (dZ of layer l in, dZ of layer l - 1 out).
+// H rows stacked.  Modes: training forward (Z in FP32 and A = act(Z) in
+// BF16; the last layer linear), the adjoint of layer l (dZ of layer l in, dZ
+// of layer l - 1 out), inference (A only; the last layer writes
+// scale * channel 0 to Z, which is then the [P] output).
+enum { kConvForward = 0, kConvAdjoint = 2, kConvInfer = 3, kConvInferOut = 4 };
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
-                    int W, int rows, hipStream_t s);
+                    int W, int rows, float scale, hipStream_t s);
 hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
-                     int nchunks, int chunk, int H, int W, long long P, float* gradW, float* gradb,
-                     hipStream_t s);
+                     float* bpart, int nchunks, int chunk, int H, int W, long long P, float* gradW,
+                     float* gradb, hipStream_t s);
 hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
                     unsigned short* X0, hipStream_t s);
 hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s);

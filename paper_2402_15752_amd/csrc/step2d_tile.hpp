@@ -184,8 +184,9 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
     Off t = node;
     if (cx) t += cx < 0 ? push.dxm : push.dxp;
     if (cy) t += cy < 0 ? push.dym : push.dyp;
-    return (push.bits & link_mask(cx, cy, 0)) ? plane<false>(L::opp[i], G.sS) + node
-                                              : plane<false>(i, G.sS) + t;
+    return (push.bits & link_mask(cx, cy, 0))
+               ? plane<false>(L::opp[i], G.sS) + node + skew<L, S, Off>(L::opp[i])
+               : plane<false>(i, G.sS) + t + skew<L, S, Off>(i);
   };
   S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
   S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     auto load_g = [&] {
 #pragma unroll
       for (int i = 0; i < 19; ++i)
-        g[i] = Codec<S, T>::ld(ld_pop<NTG>(at(sG, plane<true>(i, G.sS) + node)), T(LG::w[i]));
+        g[i] = Codec<S, T>::ld(
+            ld_pop<NTG>(at(sG, plane<true>(i, G.sS) + node + skew<LG, S, Off>(i))), T(LG::w[i]));
 #pragma unroll
       for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane<true>(k, G.sT) + nodeT);
     };
@@ -245,13 +246,16 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
           dzp = Off(0) - Off(nz - 1) * G.nxy;
         }
         // byte offset of the push target of direction i (plane i of its set),
-        // or of the bounce-back target (plane opp(i), this node)
+        // or of the bounce-back target (plane opp(i), this node); the plane
+        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix
         auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
+          const Off sk = cx > 0 ? Off(0) - BS : (cx < 0 ? BS : Off(0));
           Off t = node;
           if (cx) t += cx < 0 ? push.dxm : push.dxp;
           if (cy) t += cy < 0 ? push.dym : push.dyp;
           if (cz) t += cz < 0 ? dzm : dzp;
-          return (bits & link_mask(cx, cy, cz)) ? plane<true>(o, G.sS) + node : plane<true>(i, G.sS) + t;
+          return (bits & link_mask(cx, cy, cz)) ? plane<true>(o, G.sS) + node - sk
+                                                : plane<true>(i, G.sS) + t + sk;
         };
         S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
         S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);

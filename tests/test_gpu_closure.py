@@ -172,3 +172,20 @@ def test_restrict_is_the_block_mean(cplb, n, H, Wd, F):
     want = x.astype(np.float64).reshape(n, H, F, Wd, F).mean(axis=(2, 4))
     assert out.shape == (n, H, Wd)
     np.testing.assert_allclose(out, want, rtol=0, atol=2e-6 * np.abs(x).max())
+
+
+def test_infer_equals_forward_bitwise(cplb):
+    """The inference path (no FP32 pre-activations, output written by the
+    last convolution) gives the training forward's output bit for bit, on
+    another stream too."""
+    import torch
+    net, theta, x, tp = setup_net(cplb, 3, 16, 48, seed=5)
+    net.set_output_scale(2.5)
+    a = net.forward(tp).cpu().numpy()
+    b = net.infer(tp).cpu().numpy()
+    assert np.array_equal(a, b)
+    s = torch.cuda.Stream()
+    net.set_stream(s)
+    c = net.infer(tp[:2].contiguous()).cpu().numpy()
+    assert np.array_equal(a[:2], c)
+    net.close()
