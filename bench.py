@@ -33,10 +33,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44993460, "write": 43069479, "src": "c33950995b5579c8"},
-    "rising_droplet_256c_f32": {"read": 3682441023, "write": 3201391232, "src": "c33950995b5579c8"},
-    "rising_droplet_256c_f32_s16f": {"read": 2476021953, "write": 1756257781,
-                                     "src": "c33950995b5579c8"},
+    "rising_bubble_256x1024_f32": {"read": 45045046, "write": 43037223,
+                                  "src": "91042dd3c39c7e5c"},
+    "rising_droplet_256c_f32": {"read": 3756780808, "write": 3096946272,
+                               "src": "91042dd3c39c7e5c"},
+    "rising_droplet_256c_f32_s16f": {"read": 2477269448, "write": 1749233947,
+                                    "src": "91042dd3c39c7e5c"},
+    "rising_bubble_2048x4096_f32": {"read": 1475349202, "write": 1376897608,
+                                   "src": "91042dd3c39c7e5c"},
+    "rising_bubble_one_256x1024_f32": {"read": 32830240, "write": 32516664,
+                                      "src": "91042dd3c39c7e5c"},
 }
 
 
@@ -323,6 +329,9 @@ def main():
             "avg_kernel_ms": round(r1["avg_kernel_ms"], 5), "alg_bytes_per_node": b1,
             "achieved_GBs": round(a1, 1), "frac": round(a1 / HBM_PEAK_GBS, 4),
             "nonfinite": r1["reduce"]["nonfinite"]}
+        t1 = measured_traffic(w1["name"])
+        if t1 is not None:
+            out["also_one_scalar"]["traffic_GBs"] = round(t1 / (r1["avg_kernel_ms"] * 1e-3) / 1e9, 1)
         del w1
         out["also_batch_512"] = time_batch(40, 5)
         out["closure"] = closure_speedup()

@@ -186,6 +186,22 @@ static int check_params(const cplb_ref_params* p, char* err) {
     strcpy(err, "2-D lattice: g[2] must be 0");
     return -1;
   }
+  for (int f = 0; f < 6; f++) {
+    if (p->scalar_bc[f] != CPLB_REF_NOFLUX && p->scalar_bc[f] != CPLB_REF_DIRICHLET) {
+      strcpy(err, "unknown scalar boundary");
+      return -1;
+    }
+    if (p->scalar_bc[f] == CPLB_REF_DIRICHLET) {
+      if (f / 2 >= d || p->periodic[f / 2]) {
+        strcpy(err, "a Dirichlet face needs a walled axis of the lattice");
+        return -1;
+      }
+      if (p->scalar_model != CPLB_REF_TWO_SCALAR) {
+        strcpy(err, "Dirichlet faces take the two-scalar model");
+        return -1;
+      }
+    }
+  }
   if (p->scalar_model != CPLB_REF_TWO_SCALAR && p->scalar_model != CPLB_REF_ONE_SCALAR) {
     strcpy(err, "unknown scalar model");
     return -1;
@@ -609,8 +625,11 @@ static void collide(cplb_ref_t* h) {
 /* -------------------------------------------------------------- pass 4 */
 
 /* X_i(x + c_i, t+1) = X_i*(x, t); a link that leaves through a wall comes
- * back to x in the opposite direction (half-way bounce-back, resting wall). */
-static void stream_set(const cplb_ref_t* h, const lattice_t* L, const double* src, double* dst) {
+ * back to x in the opposite direction (half-way bounce-back, resting wall).
+ * For the scalar sets (k = 0: h1, 1: h2; k = -1: any other set) a Dirichlet
+ * face returns -X_i*(x) + 2 w_i c_wall instead (half-way anti-bounce-back). */
+static void stream_set(const cplb_ref_t* h, const lattice_t* L, const double* src, double* dst,
+                       int k) {
   const long N = h->N;
   const long n3[3] = {h->nx, h->ny, h->nz};
 #pragma omp parallel for schedule(static)
@@ -619,20 +638,24 @@ static void stream_set(const cplb_ref_t* h, const lattice_t* L, const double* sr
     coords(h, n, &x[0], &x[1], &x[2]);
     for (int i = 0; i < L->q; i++) {
       long v[3];
-      int wall = 0;
+      int face = -1;
       for (int a = 0; a < 3; a++) {
         v[a] = x[a] + L->c[i][a];
         if (v[a] < 0 || v[a] >= n3[a]) {
           if (h->p.periodic[a])
             v[a] = (v[a] + n3[a]) % n3[a];
-          else
-            wall = 1;
+          else if (face < 0)
+            face = 2 * a + (v[a] < 0 ? 0 : 1);
         }
       }
-      if (wall)
-        dst[L->opp[i] * N + n] = src[i * N + n];
-      else
+      if (face >= 0) {
+        double out = src[i * N + n];
+        if (k >= 0 && h->p.scalar_bc[face] == CPLB_REF_DIRICHLET)
+          out = -out + 2.0 * L->w[i] * h->p.c_wall[face][k];
+        dst[L->opp[i] * N + n] = out;
+      } else {
         dst[i * N + v[0] + n3[0] * (v[1] + n3[1] * v[2])] = src[i * N + n];
+      }
     }
   }
 }
@@ -649,10 +672,10 @@ int cplb_ref_step(cplb_ref_t* h, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; s++) {
     macros(h);
     collide(h);
-    stream_set(h, &h->LF, h->fs, h->f);
-    stream_set(h, &h->LG, h->gs, h->g);
-    stream_set(h, &h->LF, h->h1s, h->h1);
-    stream_set(h, &h->LF, h->h2s, h->h2);
+    stream_set(h, &h->LF, h->fs, h->f, -1);
+    stream_set(h, &h->LG, h->gs, h->g, -1);
+    stream_set(h, &h->LF, h->h1s, h->h1, 0);
+    stream_set(h, &h->LF, h->h2s, h->h2, 1);
     /* history for the next backward difference */
     memcpy(h->u_old, h->u, 3 * N * sizeof(double));
     memcpy(h->phi_old, h->phi, N * sizeof(double));

@@ -30,6 +30,12 @@ enum { CPLB_REF_VISC_LINEAR = 0, CPLB_REF_VISC_EXP = 1 };
  * c1 = Keq phi c / K_eff, c2 = (1 - phi) c / K_eff, K_eff = Keq phi + 1 - phi;
  * the history keeps c in the c1 slot. */
 enum { CPLB_REF_TWO_SCALAR = 0, CPLB_REF_ONE_SCALAR = 1 };
+/* Scalar boundary of a wall face (Sec. IV): no flux (half-way bounce-back,
+ * the default) or a Dirichlet value (half-way anti-bounce-back of h1, h2:
+ * h_opp(i)(x) = -h_i*(x) + 2 w_i c_wall).  f and g bounce back at every
+ * wall.  A link leaving through two walls (a corner) takes the boundary of
+ * the x face, then of the y face. */
+enum { CPLB_REF_NOFLUX = 0, CPLB_REF_DIRICHLET = 1 };
 enum {
   CPLB_REF_OK = 0,
   CPLB_REF_EINVAL = -1,
@@ -58,6 +64,9 @@ typedef struct cplb_ref_params {
   double n_eps;             /* n = grad phi / sqrt(|grad phi|^2 + n_eps^2), > 0 */
   int32_t scalar_model;     /* CPLB_REF_TWO_SCALAR (h1, h2; Sec. III C) or
                                CPLB_REF_ONE_SCALAR (h3 for c = c1 + c2; Sec. III D) */
+  int32_t scalar_bc[6];     /* faces x-, x+, y-, y+, z-, z+ of a walled axis:
+                               CPLB_REF_NOFLUX or CPLB_REF_DIRICHLET (h1, h2)   */
+  double c_wall[6][2];      /* (c1, c2) imposed at each Dirichlet face          */
 } cplb_ref_params;
 
 typedef struct cplb_ref cplb_ref_t;

@@ -18,6 +18,7 @@ SETS = {"f": 0, "g": 1, "h1": 2, "h2": 3}
 LATTICES = {"d2q9": 0, "d3q19_d3q7": 1}
 VISC = {"linear": 0, "exp": 1}
 SCALAR_MODELS = {"two": 0, "one": 1}
+SCALAR_BC = {"noflux": 0, "dirichlet": 1}
 
 
 class RefParams(ctypes.Structure):
@@ -31,6 +32,7 @@ class RefParams(ctypes.Structure):
         ("D1", ctypes.c_double), ("D2", ctypes.c_double), ("Keq", ctypes.c_double),
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
         ("n_eps", ctypes.c_double), ("scalar_model", ctypes.c_int32),
+        ("scalar_bc", ctypes.c_int32 * 6), ("c_wall", ctypes.c_double * 12),
     ]
 
 
@@ -82,6 +84,10 @@ def make_params(p: dict) -> RefParams:
               "rho_ref", "n_eps"):
         setattr(r, k, float(p[k]))
     r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
+    for f in range(6):
+        r.scalar_bc[f] = SCALAR_BC[p.get("scalar_bc", ("noflux",) * 6)[f]]
+        cw = p.get("c_wall", ((0.0, 0.0),) * 6)[f]
+        r.c_wall[2 * f], r.c_wall[2 * f + 1] = float(cw[0]), float(cw[1])
     return r
 
 

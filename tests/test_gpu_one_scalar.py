@@ -101,7 +101,11 @@ def test_one_scalar_rising_bubble(cplb, precision, tol):
     names = ("phi", "c1", "c2", "ux", "uy", "p") if precision == "f32" else ("phi", "c1", "c2")
     compare(g, o, names, tol, f"{precision} t=1000")
     r = g.reduce()
-    assert abs(r["sum_c"] - r0["sum_c"]) <= (1e-6 if precision == "f32" else 1e-4) * r0["sum_c"]
+    # FP32 storage conserves the solute to round-off; 16-bit storage rounds
+    # every population each step (drift reported, held to the field bound)
+    drift = abs(r["sum_c"] - r0["sum_c"]) / r0["sum_c"]
+    say(f"  solute drift {drift:.2e}")
+    assert drift <= (1e-6 if precision == "f32" else 2e-3)
 
 
 def test_one_scalar_refuses_a_closure(cplb):
