@@ -77,6 +77,16 @@ extern "C" {
 #define CPLB_TWO_SCALAR 0
 #define CPLB_ONE_SCALAR 1
 
+/* Scalar boundary of a wall face (cplb_params.scalar_bc, Sec. IV): no flux
+ * (half-way bounce-back, the default) or a Dirichlet value (half-way
+ * anti-bounce-back of h1, h2: h_opp(i)(x) = -h_i*(x) + 2 w_i c_wall, the
+ * value imposed half a node outside the boundary node).  f and g bounce back
+ * at every wall.  A link leaving through two walls (a corner) takes the
+ * boundary of the x face.  Dirichlet faces need a walled axis, the
+ * CPLB_D2Q9 lattice and the two-scalar model. */
+#define CPLB_BC_NOFLUX 0
+#define CPLB_BC_DIRICHLET 1
+
 /* field ids for cplb_read_field */
 #define CPLB_FIELD_PHI 0
 #define CPLB_FIELD_P 1
@@ -115,6 +125,9 @@ typedef struct cplb_params {
                             are held as deviations X_i - w_i ref[k] (k = 0, 2, 3:
                             phi_ref, c1_ref, c2_ref), which keeps FP32 and 16-bit
                             rounding relative to the deviation; ref[1] (g) must be 0 */
+  int32_t scalar_bc[6];  /* faces x-, x+, y-, y+, z-, z+ of a walled axis:
+                            CPLB_BC_NOFLUX or CPLB_BC_DIRICHLET (h1, h2)          */
+  double c_wall[6][2];   /* (c1, c2) imposed at each Dirichlet face              */
 } cplb_params;
 
 typedef struct cplb cplb_t; /* opaque handle */

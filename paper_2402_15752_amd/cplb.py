@@ -24,6 +24,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "f32_s16f": 2, "f32_s16b": 3}
 VISC = {"linear": 0, "exp": 1}
 SCALAR_MODELS = {"two": 0, "one": 1}
 CPLB_TWO_SCALAR, CPLB_ONE_SCALAR = 0, 1
+SCALAR_BC = {"noflux": 0, "dirichlet": 1}
 FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
 DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
@@ -57,6 +58,7 @@ class cplb_params(ctypes.Structure):
         ("D1", ctypes.c_double), ("D2", ctypes.c_double), ("Keq", ctypes.c_double),
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
         ("n_eps", ctypes.c_double), ("ref", ctypes.c_double * 4),
+        ("scalar_bc", ctypes.c_int32 * 6), ("c_wall", ctypes.c_double * 12),
     ]
 
 
@@ -174,6 +176,10 @@ def make_params(p: dict) -> cplb_params:
         r.periodic[a] = int(p["periodic"][a])
         r.g[a] = float(p["g"][a])
     r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
+    for f in range(6):
+        r.scalar_bc[f] = SCALAR_BC[p.get("scalar_bc", ("noflux",) * 6)[f]]
+        cw = p.get("c_wall", ((0.0, 0.0),) * 6)[f]
+        r.c_wall[2 * f], r.c_wall[2 * f + 1] = float(cw[0]), float(cw[1])
     for k in ("rho1", "rho2", "mu1", "mu2", "sigma", "W", "M", "D1", "D2", "Keq", "A", "rho_ref",
               "n_eps"):
         setattr(r, k, float(p[k]))

@@ -29,7 +29,7 @@ struct cplb {
   const float* closure;  // caller's per-node extra exchange (2-D), or null
   KParams<double> k64;  // lattice constants (host copies)
   KParams<float> k32;
-  KParams<double>* k64_dev;  // the same, in the workspace, read by the 3-D kernels
+  KParams<double>* k64_dev;  // the same, in the workspace, read by the step kernels
   KParams<float>* k32_dev;
   char err[512];
 };
@@ -52,7 +52,7 @@ hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, const KParams<T>* Kdev,
   const S* src = (const S*)h->lat[h->cur];
   S* dst = (S*)h->lat[h->cur ^ 1];
   if (h->G.dim == 2)
-    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, mode, h->variant,
+    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
                                h->closure, h->stream);
   return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
                              h->stream);

@@ -90,6 +90,11 @@ int validate_batch(const cplb_params* prm, int n, char* err, size_t errn) {
       snprintf(err, errn, "case %d: batches run the two-scalar model only", c);
       return CPLB_EINVAL;
     }
+    for (int f = 0; f < 6; ++f)
+      if (prm[c].scalar_bc[f] != CPLB_BC_NOFLUX) {
+        snprintf(err, errn, "case %d: batches take no-flux scalar walls only", c);
+        return CPLB_EINVAL;
+      }
     if (prm[c].precision != prm[0].precision) {
       snprintf(err, errn, "case %d: every case needs the precision of case 0", c);
       return CPLB_EINVAL;

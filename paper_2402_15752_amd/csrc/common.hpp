@@ -46,6 +46,8 @@ struct KParams {
   T ref_phi, one_minus_ref_phi, ref_c1, ref_c2;  // reference state of the deviations
   int one_scalar;     // 1: one-scalar model, h3 in the h1 planes (Sec. III D)
   T D1K;              // D1 Keq of D_eff = D1 Keq phi + D2 (1 - phi)
+  int dirichlet;      // bit f: face f (x-, x+, y-, y+) holds Dirichlet c1, c2
+  T cw[4][2];         // c_wall - c_ref of (c1, c2) at each face
 };
 
 // ------------------------------------------------------------ storage codec

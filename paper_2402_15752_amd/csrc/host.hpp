@@ -36,6 +36,16 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
   if (p->scalar_model == CPLB_ONE_SCALAR && p->lattice != CPLB_D2Q9)
     return fail("the one-scalar model runs on CPLB_D2Q9 only");
   const int d = p->lattice == CPLB_D2Q9 ? 2 : 3;
+  for (int f = 0; f < 6; ++f) {
+    if (p->scalar_bc[f] != CPLB_BC_NOFLUX && p->scalar_bc[f] != CPLB_BC_DIRICHLET)
+      return fail("unknown scalar boundary");
+    if (p->scalar_bc[f] != CPLB_BC_DIRICHLET) continue;
+    if (d != 2) return fail("Dirichlet faces run on CPLB_D2Q9 only");
+    if (f / 2 >= d || p->periodic[f / 2]) return fail("a Dirichlet face needs a walled axis");
+    if (p->scalar_model != CPLB_TWO_SCALAR) return fail("Dirichlet faces take the two-scalar model");
+    if (!std::isfinite(p->c_wall[f][0]) || !std::isfinite(p->c_wall[f][1]))
+      return fail("non-finite wall value");
+  }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
   if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
   const int n3[3] = {p->nx, p->ny, p->nz};
@@ -142,6 +152,13 @@ KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
   // one-scalar model (Sec. III D): D_eff = D1 Keq phi + D2 (1 - phi)
   K.one_scalar = p->scalar_model == CPLB_ONE_SCALAR;
   K.D1K = T(p->D1 * p->Keq);
+  // Dirichlet faces x-, x+, y-, y+ (bit f) and their values as deviations
+  K.dirichlet = 0;
+  for (int f = 0; f < 4; ++f) {
+    if (f / 2 < G.dim && p->scalar_bc[f] == CPLB_BC_DIRICHLET) K.dirichlet |= 1 << f;
+    K.cw[f][0] = T(p->c_wall[f][0] - p->ref[2]);
+    K.cw[f][1] = T(p->c_wall[f][1] - p->ref[3]);
+  }
   K.neps2 = T(p->n_eps * p->n_eps);
   // reference state of the stored deviations (f, h1, h2; g is stored as is)
   K.ref_phi = T(p->ref[0]);

@@ -9,6 +9,11 @@ namespace pflb {
 
 constexpr int kModeStep = 0;    // collide and stream into the other lattice
 constexpr int kModeMacros = 1;  // write the macroscopic fields, no update
+// compiled scalar-model variants of the 2-D step: the two-scalar model, the
+// one-scalar model (Sec. III D), the two-scalar model with Dirichlet faces
+constexpr int kModelTwo = 0;
+constexpr int kModelOne = 1;
+constexpr int kModelTwoDirichlet = 2;
 
 // planes of the field buffer (same ids as the CPLB_FIELD_* constants)
 constexpr int kFieldPhi = 0, kFieldP = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz = 4, kFieldC1 = 5,
@@ -28,8 +33,9 @@ const char* step3d_variant_name(int v);
 // closure: per-node extra exchange added to the auxiliary scalar source
 // (N FP32 values in node order), or null
 template <class S, class T>
-hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P, int mode,
-                         int variant, const float* closure, hipStream_t stream);
+hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+                         const KParams<T>* Pdev, int mode, int variant, const float* closure,
+                         hipStream_t stream);
 
 // P: host copy of the lattice constants (grid, launch shape); Pdev: the same
 // constants in device memory, read by the kernel

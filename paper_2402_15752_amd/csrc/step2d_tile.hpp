@@ -31,14 +31,17 @@ struct Geo2 {
 // One TX x TY tile of the fused 2-D step (moments, stencils, macros,
 // history, collision, push), shared by the single-lattice and the batched
 // kernels.  `tile` is the tile index in row-major order over the grid.
-// ONE selects the one-scalar model (Sec. III D): h3 in the h1 planes, no h2
-// traffic, no psi stencil, history (u, phi, c).
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, bool ONE = false>
+// MODEL kModelOne selects the one-scalar model (Sec. III D): h3 in the h1
+// planes, no h2 traffic, no psi stencil, history (u, phi, c);
+// kModelTwoDirichlet adds the Dirichlet faces' anti-bounce-back of h1, h2
+// (a compiled variant: the check costs the plain step ~5%).
+template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL = kModelTwo>
 __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ dst,
                                    T* __restrict__ hist, T* __restrict__ fields,
                                    const KParams<T>& P, const Geo2<Off>& G, int tile) {
   using L = D2Q9;
   using Lay = Layout<D2Q9, D2Q9>;
+  constexpr bool ONE = MODEL == kModelOne;
   constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
   constexpr Off BS = sizeof(S);
@@ -192,6 +195,8 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
   S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
   S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
+  // Dirichlet faces this node's links reach (0 for every interior node)
+  const int dmask = MODEL == kModelTwoDirichlet ? push.bits & P.dirichlet : 0;
   if constexpr (ONE) {
     T n[3];
     normal(P, gphi, n);
@@ -212,6 +217,18 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
       [&](int i, T v) { st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
       [&](int i, T a, T b) {
         const Off t = target(i);
+        // half-way anti-bounce-back at a Dirichlet face (the x face first at a
+        // corner): h_opp(i) = -h_i* + 2 w_i c_wall, on the deviations
+        if (MODEL == kModelTwoDirichlet && dmask) {
+          const int hit = push.bits & link_mask(L::cx[i], L::cy[i], 0);
+          if (hit & dmask) {
+            const int f = (hit & 1) ? 0 : (hit & 2) ? 1 : (hit & 4) ? 2 : 3;
+            if ((dmask >> f) & 1) {
+              a = T(2.0 * L::w[i]) * P.cw[f][0] - a;
+              b = T(2.0 * L::w[i]) * P.cw[f][1] - b;
+            }
+          }
+        }
         st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
         st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
       },

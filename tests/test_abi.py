@@ -69,7 +69,12 @@ def test_workspace_bytes_cover_two_lattices(cplb):
                                  dict(rho1=0.0), dict(g=(0, 0, 1e-5)), dict(n_eps=0.0),
                                  dict(periodic=(1, 0, 1), ny=1), dict(nz=2),
                                  dict(precision="f32", sigma=float("nan")),
-                                 dict(scalar_model="one", lattice="d3q19_d3q7", nz=8, nx=8, ny=8)])
+                                 dict(scalar_model="one", lattice="d3q19_d3q7", nz=8, nx=8, ny=8),
+                                 dict(scalar_bc=("dirichlet",) + ("noflux",) * 5),
+                                 dict(periodic=(0, 1, 1), scalar_model="one",
+                                      scalar_bc=("dirichlet",) + ("noflux",) * 5),
+                                 dict(lattice="d3q19_d3q7", nz=8, nx=8, ny=8, periodic=(1, 1, 0),
+                                      scalar_bc=("noflux",) * 4 + ("dirichlet", "noflux"))])
 def test_validation_rejects(cplb, bad):
     p = W.params(**bad)
     with pytest.raises(cplb.CplbError) as e:
@@ -118,6 +123,8 @@ def test_batch_validation_and_workspace(cplb):
                                              precision="f32")],                 # not D2Q9
         [W.params(precision="f32"), W.params(precision="f32", D1=0.0)],         # invalid case
         [W.params(precision="f32"), W.params(precision="f32", scalar_model="one")],  # one-scalar
+        [W.params(precision="f32"), W.params(precision="f32", periodic=(0, 1, 1),
+                                             scalar_bc=("dirichlet",) + ("noflux",) * 5)],
     ]
     for ps in bad_sets:
         with pytest.raises(cplb.CplbError) as e:
