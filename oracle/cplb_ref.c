@@ -202,6 +202,10 @@ static int check_params(const cplb_ref_params* p, char* err) {
       }
     }
   }
+  if (p->scalar_grad != CPLB_REF_GRAD_CENTRAL && p->scalar_grad != CPLB_REF_GRAD_LOCAL) {
+    strcpy(err, "unknown scalar gradient scheme");
+    return -1;
+  }
   if (p->scalar_model != CPLB_REF_TWO_SCALAR && p->scalar_model != CPLB_REF_ONE_SCALAR) {
     strcpy(err, "unknown scalar model");
     return -1;
@@ -504,6 +508,29 @@ static void pass2(cplb_ref_t* h) {
     for (int i = 1; i < L->q; i++) sg += h->g[i * N + n];
     double pr = L->cs2 / (1.0 - L->w[0]) *
                 (sg + 0.5 * (P->rho1 - P->rho2) * dot3(u, gphi) + rho * s_i(L, 0, u));
+    if (P->scalar_grad == CPLB_REF_GRAD_LOCAL && P->scalar_model == CPLB_REF_TWO_SCALAR) {
+      /* local scheme, Eq. (39): grad c_k from the first moment of h_k,
+         with d_t(c_k u) the backward difference against the history */
+      const lattice_t* LF = &h->LF;
+      const double tau1 = 0.5 + P->D1 / LF->cs2, tau2 = 0.5 + P->D2 / LF->cs2;
+      const double c1 = h->c1[n], c2 = h->c2[n];
+      double q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
+      for (int i = 0; i < LF->q; i++)
+        for (int a = 0; a < 3; a++) {
+          q1[a] += LF->c[i][a] * h->h1[i * N + n];
+          q2[a] += LF->c[i][a] * h->h2[i * N + n];
+        }
+      for (int a = 0; a < 3; a++) {
+        const double uo = h->u_old[a * N + n];
+        const double dt1 = c1 * u[a] - h->c1_old[n] * uo;
+        const double dt2 = c2 * u[a] - h->c2_old[n] * uo;
+        const double g1 = (-q1[a] + c1 * u[a] - 0.5 * dt1 +
+                           P->D1 * 4.0 * (1.0 - phi) * c1 / P->W * nv[a]) / (tau1 * LF->cs2);
+        const double g2 = (-q2[a] + c2 * u[a] - 0.5 * dt2 -
+                           P->D2 * 4.0 * phi * c2 / P->W * nv[a]) / (tau2 * LF->cs2);
+        gpsi[a] = g1 + P->Keq * g2;
+      }
+    }
     /* viscosity: linear law, Eq. (1.8), or exponential law, Eq. (4.3) */
     double mu;
     if (P->visc_law == CPLB_REF_VISC_EXP)
@@ -711,6 +738,9 @@ int cplb_ref_field(cplb_ref_t* h, int field, double* out) {
     case CPLB_REF_C2: src = h->c2; break;
     case CPLB_REF_MU: src = h->mu; break;
     case CPLB_REF_PSI: src = h->psi; break;
+    case CPLB_REF_GPSI_X: src = h->gpsi; break;
+    case CPLB_REF_GPSI_Y: src = h->gpsi + N; break;
+    case CPLB_REF_GPSI_Z: src = h->gpsi + 2 * N; break;
     default: set_err(h, "unknown field id"); return CPLB_REF_EINVAL;
   }
   memcpy(out, src, N * sizeof(double));

@@ -36,6 +36,14 @@ enum { CPLB_REF_TWO_SCALAR = 0, CPLB_REF_ONE_SCALAR = 1 };
  * wall.  A link leaving through two walls (a corner) takes the boundary of
  * the x face, then of the y face. */
 enum { CPLB_REF_NOFLUX = 0, CPLB_REF_DIRICHLET = 1 };
+/* Gradient of psi = c1 + Keq c2 in the auxiliary source ~H: the isotropic
+ * central stencil (the default), or the local scheme of Eq. (39), which
+ * takes grad c_k from the first moment of the node's own h_k:
+ *   grad c1 = [-sum c_i h1_i + c1 u - d_t(c1 u)/2 + D1 4 (1-phi) c1 n / W] / (tau_h1 cs^2)
+ *   grad c2 = [-sum c_i h2_i + c2 u - d_t(c2 u)/2 - D2 4 phi c2 n / W] / (tau_h2 cs^2)
+ * with u and n of the step (n from the central grad phi, which the
+ * Laplacian's stencil gives anyway). */
+enum { CPLB_REF_GRAD_CENTRAL = 0, CPLB_REF_GRAD_LOCAL = 1 };
 enum {
   CPLB_REF_OK = 0,
   CPLB_REF_EINVAL = -1,
@@ -47,7 +55,9 @@ enum {
 enum {
   CPLB_REF_PHI = 0, CPLB_REF_P = 1, CPLB_REF_UX = 2, CPLB_REF_UY = 3,
   CPLB_REF_UZ = 4, CPLB_REF_C1 = 5, CPLB_REF_C2 = 6, CPLB_REF_MU = 7,
-  CPLB_REF_PSI = 8
+  CPLB_REF_PSI = 8,
+  /* the grad psi of the last step's auxiliary source (test access) */
+  CPLB_REF_GPSI_X = 9, CPLB_REF_GPSI_Y = 10, CPLB_REF_GPSI_Z = 11
 };
 
 typedef struct cplb_ref_params {
@@ -67,6 +77,8 @@ typedef struct cplb_ref_params {
   int32_t scalar_bc[6];     /* faces x-, x+, y-, y+, z-, z+ of a walled axis:
                                CPLB_REF_NOFLUX or CPLB_REF_DIRICHLET (h1, h2)   */
   double c_wall[6][2];      /* (c1, c2) imposed at each Dirichlet face          */
+  int32_t scalar_grad;      /* grad(c1 + Keq c2) of ~H: CPLB_REF_GRAD_CENTRAL or
+                               CPLB_REF_GRAD_LOCAL (two-scalar model)           */
 } cplb_ref_params;
 
 typedef struct cplb_ref cplb_ref_t;

@@ -13,12 +13,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcplb_ref.so")
 
-FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
+FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8,
+          "gpsi_x": 9, "gpsi_y": 10, "gpsi_z": 11}
 SETS = {"f": 0, "g": 1, "h1": 2, "h2": 3}
 LATTICES = {"d2q9": 0, "d3q19_d3q7": 1}
 VISC = {"linear": 0, "exp": 1}
 SCALAR_MODELS = {"two": 0, "one": 1}
 SCALAR_BC = {"noflux": 0, "dirichlet": 1}
+SCALAR_GRAD = {"central": 0, "local": 1}
 
 
 class RefParams(ctypes.Structure):
@@ -33,6 +35,7 @@ class RefParams(ctypes.Structure):
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
         ("n_eps", ctypes.c_double), ("scalar_model", ctypes.c_int32),
         ("scalar_bc", ctypes.c_int32 * 6), ("c_wall", ctypes.c_double * 12),
+        ("scalar_grad", ctypes.c_int32),
     ]
 
 
@@ -84,6 +87,7 @@ def make_params(p: dict) -> RefParams:
               "rho_ref", "n_eps"):
         setattr(r, k, float(p[k]))
     r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
+    r.scalar_grad = SCALAR_GRAD[p.get("scalar_grad", "central")]
     for f in range(6):
         r.scalar_bc[f] = SCALAR_BC[p.get("scalar_bc", ("noflux",) * 6)[f]]
         cw = p.get("c_wall", ((0.0, 0.0),) * 6)[f]

@@ -1,0 +1,76 @@
+"""Pins of the oracle's local scheme for grad(c1 + Keq c2) (Eq. (39)): the
+gradient taken from the first moment of each node's own h1, h2.
+
+  - on a smooth drop (W = 8) it equals a central difference of the same psi
+    to within the schemes' truncation (0.7 % here; a dropped or mis-signed
+    term of Eq. (39) is an O(1) error there);
+  - the auxiliary source stays antisymmetric, so c1 + c2 is conserved to
+    round-off whatever the gradient;
+  - the paper's linear-equilibrium case reaches the same analytic steady
+    state as with the central stencil (bulk slopes from flux continuity and
+    the interfacial jump)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ref
+
+
+def smooth_drop(grad, steps=400):
+    p = W.params(nx=96, ny=96, periodic=(1, 1, 1), sigma=1e-3, D1=0.08, D2=0.03, Keq=0.5,
+                 A=0.1, W=8.0, scalar_grad=grad)
+    x, y = np.meshgrid(np.arange(96) + 0.5, np.arange(96) + 0.5)
+    o = ref.Oracle(p)
+    o.init_sdf(24.0 - np.hypot(x - 48.0, y - 48.0), c1=(0.0, 0.3), c2=(0.5, -0.5))
+    o.step(steps)
+    return o
+
+
+def test_local_gradient_matches_central_differences():
+    o = smooth_drop("local")
+    gx, gy = o.field("gpsi_x"), o.field("gpsi_y")
+    psi = o.field("psi")
+    cx = (np.roll(psi, -1, 1) - np.roll(psi, 1, 1)) / 2.0
+    cy = (np.roll(psi, -1, 0) - np.roll(psi, 1, 0)) / 2.0
+    e = np.sqrt(((gx - cx) ** 2 + (gy - cy) ** 2).sum() / (cx ** 2 + cy ** 2).sum())
+    assert e <= 2e-2, e
+    # the central run's stencil gradient is the same field to the same order
+    oc = smooth_drop("central")
+    ex = np.sqrt(((gx - oc.field("gpsi_x")) ** 2).sum() / (oc.field("gpsi_x") ** 2).sum())
+    assert ex <= 3e-2, ex
+
+
+def test_local_gradient_conserves_solute():
+    p = W.params(nx=23, ny=19, periodic=(1, 0, 1), sigma=3e-3, rho1=3.0, rho2=1.0,
+                 visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07, D2=0.02, Keq=0.6,
+                 g=(0.0, -2e-5, 0.0), rho_ref=1.5, scalar_grad="local")
+    f = W.random_fields(p, seed=8)
+    o = ref.Oracle(p)
+    o.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    r0 = o.reduce()
+    o.step(300)
+    r = o.reduce()
+    assert r["nonfinite"] == 0
+    assert abs(r["sum_c"] - r0["sum_c"]) <= 1e-13 * abs(r0["sum_c"])
+
+
+@pytest.mark.parametrize("D1,D2,K", [(0.15, 0.05, 1.0), (0.15, 0.15, 1.0 / 3.0)])
+def test_linear_equilibrium_with_local_gradient(D1, D2, K):
+    N = 64
+    p = W.params(nx=N, ny=1, periodic=(0, 1, 1), sigma=0.0, D1=D1, D2=D2, Keq=K, A=0.1,
+                 n_eps=1e-9, scalar_grad="local",
+                 scalar_bc=("dirichlet", "dirichlet") + ("noflux",) * 4,
+                 c_wall=((0.0, 0.0), (2.0, 0.0)) + ((0.0, 0.0),) * 4)
+    x = np.arange(N, dtype=float)
+    xi = (N - 1) / 2.0
+    o = ref.Oracle(p)
+    o.init_sdf((x - xi).reshape(1, N), c1=(0.0, 2.0), c2=(0.0, 0.0))
+    o.step(80000)
+    c1, c2 = o.field("c1")[0], o.field("c2")[0]
+    left, right = x < xi - 12, x > xi + 12
+    a2 = np.polyfit(x[left], c2[left], 1)
+    a1 = np.polyfit(x[right], c1[right], 1)
+    L2, L1 = xi + 0.5, N - 0.5 - xi
+    ct2i = 2.0 * D1 * L2 / (D2 * L1 + K * D1 * L2)
+    assert abs(a2[0] / (ct2i / L2) - 1.0) <= 5e-3, a2[0]
+    assert abs(a1[0] / ((2.0 - K * ct2i) / L1) - 1.0) <= 5e-3, a1[0]
