@@ -89,6 +89,11 @@ def make_workload(name):
     if name == "rising_bubble_one_256x1024":
         # the one-scalar model (h3) on the same bubble, Keq = 2
         return W.rising_bubble_2d(256, 1024, "f32", scalar_model="one")
+    if name == "rising_bubble_local_256x1024":
+        # grad(c1 + Keq c2) by the local scheme of Eq. (39): no h halo
+        return W.rising_bubble_2d(256, 1024, "f32", scalar_grad="local")
+    if name == "rising_bubble_local_2048x4096":
+        return W.rising_bubble_2d(2048, 4096, "f32", scalar_grad="local")
     if name == "rising_bubble_2048x4096":
         # the same bubble 8x wider: 8.4M nodes, 2.75 GB per step, far beyond the
         # Infinity Cache -- the 2-D step against HBM
@@ -333,6 +338,20 @@ def main():
         if t1 is not None:
             out["also_one_scalar"]["traffic_GBs"] = round(t1 / (r1["avg_kernel_ms"] * 1e-3) / 1e9, 1)
         del w1
+        extra2 = {}
+        for name, steps in (("rising_bubble_local_256x1024", 2000), ("rising_bubble_2048x4096", 200),
+                            ("rising_bubble_local_2048x4096", 200)):
+            w2 = make_workload(name)
+            r2 = time_gpu(w2, steps, 20)
+            a2 = alg_bytes_per_node(w2["params"]) * r2["n"] / (r2["avg_kernel_ms"] * 1e-3) / 1e9
+            extra2[w2["name"]] = {"avg_kernel_ms": round(r2["avg_kernel_ms"], 5),
+                                  "achieved_GBs": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4),
+                                  "nonfinite": r2["reduce"]["nonfinite"]}
+            t2 = measured_traffic(w2["name"])
+            if t2 is not None:
+                extra2[w2["name"]]["traffic_GBs"] = round(t2 / (r2["avg_kernel_ms"] * 1e-3) / 1e9, 1)
+            del w2
+        out["also_2d"] = extra2
         out["also_batch_512"] = time_batch(40, 5)
         out["closure"] = closure_speedup()
     if not args.no_cpu_baseline:

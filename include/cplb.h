@@ -87,6 +87,18 @@ extern "C" {
 #define CPLB_BC_NOFLUX 0
 #define CPLB_BC_DIRICHLET 1
 
+/* Gradient of psi = c1 + Keq c2 in the auxiliary source ~H_k
+ * (cplb_params.scalar_grad): the isotropic central stencil (Sec. III C, the
+ * default), or the local scheme of Eq. (39), which takes grad c_k from the
+ * first moment of the node's own h_k,
+ *   grad c1 = [-sum c_i h1_i + c1 u - d_t(c1 u)/2 + D1 4 (1-phi) c1 n / W] / (tau_h1 cs^2),
+ *   grad c2 = [-sum c_i h2_i + c2 u - d_t(c2 u)/2 - D2 4 phi c2 n / W] / (tau_h2 cs^2),
+ * with u and n of the step.  The local scheme needs no psi stencil, so the
+ * step reads no h1, h2 of the halo.  CPLB_D2Q9, the two-scalar model and
+ * no-flux scalar walls only. */
+#define CPLB_GRAD_CENTRAL 0
+#define CPLB_GRAD_LOCAL 1
+
 /* field ids for cplb_read_field */
 #define CPLB_FIELD_PHI 0
 #define CPLB_FIELD_P 1
@@ -128,6 +140,7 @@ typedef struct cplb_params {
   int32_t scalar_bc[6];  /* faces x-, x+, y-, y+, z-, z+ of a walled axis:
                             CPLB_BC_NOFLUX or CPLB_BC_DIRICHLET (h1, h2)          */
   double c_wall[6][2];   /* (c1, c2) imposed at each Dirichlet face              */
+  int32_t scalar_grad;   /* grad(c1 + Keq c2) of ~H: CPLB_GRAD_CENTRAL | CPLB_GRAD_LOCAL */
 } cplb_params;
 
 typedef struct cplb cplb_t; /* opaque handle */

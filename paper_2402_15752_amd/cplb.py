@@ -25,6 +25,7 @@ VISC = {"linear": 0, "exp": 1}
 SCALAR_MODELS = {"two": 0, "one": 1}
 CPLB_TWO_SCALAR, CPLB_ONE_SCALAR = 0, 1
 SCALAR_BC = {"noflux": 0, "dirichlet": 1}
+SCALAR_GRAD = {"central": 0, "local": 1}
 FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
 DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
@@ -59,6 +60,7 @@ class cplb_params(ctypes.Structure):
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
         ("n_eps", ctypes.c_double), ("ref", ctypes.c_double * 4),
         ("scalar_bc", ctypes.c_int32 * 6), ("c_wall", ctypes.c_double * 12),
+        ("scalar_grad", ctypes.c_int32),
     ]
 
 
@@ -176,6 +178,7 @@ def make_params(p: dict) -> cplb_params:
         r.periodic[a] = int(p["periodic"][a])
         r.g[a] = float(p["g"][a])
     r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
+    r.scalar_grad = SCALAR_GRAD[p.get("scalar_grad", "central")]
     for f in range(6):
         r.scalar_bc[f] = SCALAR_BC[p.get("scalar_bc", ("noflux",) * 6)[f]]
         cw = p.get("c_wall", ((0.0, 0.0),) * 6)[f]

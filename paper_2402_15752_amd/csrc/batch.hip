@@ -90,6 +90,10 @@ int validate_batch(const cplb_params* prm, int n, char* err, size_t errn) {
       snprintf(err, errn, "case %d: batches run the two-scalar model only", c);
       return CPLB_EINVAL;
     }
+    if (prm[c].scalar_grad != CPLB_GRAD_CENTRAL) {
+      snprintf(err, errn, "case %d: batches take the central gradient scheme only", c);
+      return CPLB_EINVAL;
+    }
     for (int f = 0; f < 6; ++f)
       if (prm[c].scalar_bc[f] != CPLB_BC_NOFLUX) {
         snprintf(err, errn, "case %d: batches take no-flux scalar walls only", c);

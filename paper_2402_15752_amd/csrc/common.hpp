@@ -48,6 +48,9 @@ struct KParams {
   T D1K;              // D1 Keq of D_eff = D1 Keq phi + D2 (1 - phi)
   int dirichlet;      // bit f: face f (x-, x+, y-, y+) holds Dirichlet c1, c2
   T cw[4][2];         // c_wall - c_ref of (c1, c2) at each face
+  int local_grad;     // 1: grad c_k from the moments of h_k (Eq. (39))
+  T itc1, itc2;       // 1 / (tau_hk cs^2)
+  T d1w, d2w;         // 4 D_k / W
 };
 
 // ------------------------------------------------------------ storage codec

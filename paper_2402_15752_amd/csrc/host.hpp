@@ -46,6 +46,15 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
     if (!std::isfinite(p->c_wall[f][0]) || !std::isfinite(p->c_wall[f][1]))
       return fail("non-finite wall value");
   }
+  if (p->scalar_grad != CPLB_GRAD_CENTRAL && p->scalar_grad != CPLB_GRAD_LOCAL)
+    return fail("unknown scalar gradient scheme");
+  if (p->scalar_grad == CPLB_GRAD_LOCAL) {
+    if (d != 2) return fail("the local gradient scheme runs on CPLB_D2Q9 only");
+    if (p->scalar_model != CPLB_TWO_SCALAR) return fail("the local gradient scheme takes the two-scalar model");
+    for (int f = 0; f < 6; ++f)
+      if (p->scalar_bc[f] != CPLB_BC_NOFLUX)
+        return fail("the local gradient scheme takes no-flux scalar walls");
+  }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("grid sizes must be >= 1");
   if (d == 2 && p->nz != 1) return fail("2-D lattice needs nz = 1");
   const int n3[3] = {p->nx, p->ny, p->nz};
@@ -152,6 +161,12 @@ KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
   // one-scalar model (Sec. III D): D_eff = D1 Keq phi + D2 (1 - phi)
   K.one_scalar = p->scalar_model == CPLB_ONE_SCALAR;
   K.D1K = T(p->D1 * p->Keq);
+  // local scheme for grad c_k (Eq. (39)): 1 / (tau_hk cs^2) and 4 D_k / W
+  K.local_grad = p->scalar_grad == CPLB_GRAD_LOCAL;
+  K.itc1 = T(1.0 / (tau_h1 * csf));
+  K.itc2 = T(1.0 / (tau_h2 * csf));
+  K.d1w = T(4.0 * p->D1 / p->W);
+  K.d2w = T(4.0 * p->D2 / p->W);
   // Dirichlet faces x-, x+, y-, y+ (bit f) and their values as deviations
   K.dirichlet = 0;
   for (int f = 0; f < 4; ++f) {

@@ -14,6 +14,7 @@ constexpr int kModeMacros = 1;  // write the macroscopic fields, no update
 constexpr int kModelTwo = 0;
 constexpr int kModelOne = 1;
 constexpr int kModelTwoDirichlet = 2;
+constexpr int kModelTwoLocal = 3;  // the two-scalar model, grad psi by Eq. (39)
 
 // planes of the field buffer (same ids as the CPLB_FIELD_* constants)
 constexpr int kFieldPhi = 0, kFieldP = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz = 4, kFieldC1 = 5,

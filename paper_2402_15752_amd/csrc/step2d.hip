@@ -113,6 +113,9 @@ hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams
   if (P.one_scalar)
     return launch_model<S, T, kModelOne>(src, dst, hist, fields, P, Pdev, mode, variant, nullptr,
                                          stream);
+  if (P.local_grad)
+    return launch_model<S, T, kModelTwoLocal>(src, dst, hist, fields, P, Pdev, mode, variant,
+                                              closure, stream);
   if (P.dirichlet)
     return launch_model<S, T, kModelTwoDirichlet>(src, dst, hist, fields, P, Pdev, mode, variant,
                                                   closure, stream);

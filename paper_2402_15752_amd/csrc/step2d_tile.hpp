@@ -42,6 +42,8 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   using L = D2Q9;
   using Lay = Layout<D2Q9, D2Q9>;
   constexpr bool ONE = MODEL == kModelOne;
+  constexpr bool LOC = MODEL == kModelTwoLocal;  // no psi stencil, no h halo
+  constexpr bool HALO_H = !ONE && !LOC;
   constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
   constexpr Off BS = sizeof(S);
@@ -93,7 +95,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   }
   if (halo) {
     load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
-    if (!ONE) {
+    if (HALO_H) {
       load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
       load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
     }
@@ -107,12 +109,12 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
       moments_one<L>(P, f, h1, s);
     } else {
       moments<L>(P, f, h1, h2, s);
-      spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+      if (HALO_H) spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
     }
     sphi[ty + 1][tx + 1] = s.dphi;
   }
   if (halo) {
-    if constexpr (ONE) {
+    if constexpr (!HALO_H) {
       T d = hf[0];
 #pragma unroll
       for (int i = 1; i < 9; ++i) d += hf[i];
@@ -132,7 +134,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const T a = sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
-    const T b = ONE ? T(0) : spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
+    const T b = HALO_H ? spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]] : T(0);
     const T wc = T(L::w[i] / L::cs2);
     if (L::cx[i]) {
       gphi[0] += wc * T(L::cx[i]) * a;
@@ -210,6 +212,31 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
       st_pop<NTS>(at(dH1, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
     });
     return;
+  }
+  if constexpr (LOC) {
+    // local scheme, Eq. (39): grad c_k from the first moment of the own h_k
+    // (deviations carry the same first moment), u, d_t(c_k u) and n of the step
+    T n[3];
+    normal(P, gphi, n);
+    T q1[3] = {T(0), T(0), T(0)}, q2[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (L::cx[i]) {
+        q1[0] += T(L::cx[i]) * h1[i];
+        q2[0] += T(L::cx[i]) * h2[i];
+      }
+      if (L::cy[i]) {
+        q1[1] += T(L::cy[i]) * h1[i];
+        q2[1] += T(L::cy[i]) * h2[i];
+      }
+    }
+    const T f1 = P.d1w * s.omphi * s.c1, f2 = P.d2w * s.phi * s.c2;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T g1 = (s.c1 * fl.u[a] - q1[a] - T(0.5) * dJ1[a] + f1 * n[a]) * P.itc1;
+      const T g2 = (s.c2 * fl.u[a] - q2[a] - T(0.5) * dJ2[a] - f2 * n[a]) * P.itc2;
+      gpsi[a] = g1 + P.Keq * g2;
+    }
   }
   collide<L, L>(
       P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,

@@ -131,7 +131,8 @@ def static_drop_64():
                 init=dict(c1=(0.0, 1.0), c2=(0.0, 0.0)), steps=2000)
 
 
-def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=None):
+def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=None,
+                     scalar_grad="central"):
     """2-D rising bubble with interfacial mass transfer: nx x ny, periodic in x,
     half-way bounce-back walls at the y faces, gravity along -y, bubble
     (fluid 2) of radius nx/16 centred at (nx/2, 3nx/8); density ratio 10,
@@ -149,9 +150,9 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=N
                D1=1e-3, D2=0.1, A=0.1, g=(0.0, -gmag, 0.0), rho_ref=rho1,
                Keq=Keq if Keq is not None else (2.0 if scalar_model == "one" else 0.2),
                precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0,
-               scalar_model=scalar_model)
+               scalar_model=scalar_model, scalar_grad=scalar_grad)
     l = sdf_sphere(p, (nx / 2.0, 3.0 * nx / 8.0), R, inside_positive=False)
-    tag = "_one" if scalar_model == "one" else ""
+    tag = ("_one" if scalar_model == "one" else "") + ("_local" if scalar_grad == "local" else "")
     return dict(name=f"rising_bubble{tag}_{nx}x{ny}_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=20000)
 
