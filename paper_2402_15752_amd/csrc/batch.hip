@@ -540,6 +540,32 @@ int cplb_batch_gather_fields(cplb_batch_t* b, const int* fields, int nf, int npl
       return set_err(b, CPLB_EINVAL, "unknown field id %d", fields[k]);
     ids[k] = fields[k];
   }
+  bool local = true;  // every field from the node's own moments
+  for (int k = 0; k < nf; ++k)
+    local = local && (ids[k] == CPLB_FIELD_PHI || ids[k] == CPLB_FIELD_C1 ||
+                      ids[k] == CPLB_FIELD_C2 || ids[k] == CPLB_FIELD_PSI);
+  if (local) {
+    hipError_t e;
+    switch (b->precision) {
+      case CPLB_F64:
+        e = launch_batch_gather_moments<double, double>(b->d_cases, b->d_k64, b->cur, b->n,
+                                                        b->max_n, ids, nf, nplanes, dev_dst, b->stream);
+        break;
+      case CPLB_F32:
+        e = launch_batch_gather_moments<float, float>(b->d_cases, b->d_k32, b->cur, b->n, b->max_n,
+                                                      ids, nf, nplanes, dev_dst, b->stream);
+        break;
+      case CPLB_F32_S16F:
+        e = launch_batch_gather_moments<__half, float>(b->d_cases, b->d_k32, b->cur, b->n,
+                                                       b->max_n, ids, nf, nplanes, dev_dst, b->stream);
+        break;
+      default:
+        e = launch_batch_gather_moments<__hip_bfloat16, float>(b->d_cases, b->d_k32, b->cur, b->n,
+                                                               b->max_n, ids, nf, nplanes, dev_dst,
+                                                               b->stream);
+    }
+    return hip_check(b, e, "moment gather");
+  }
   for (int cls = 0; cls < kBatchClasses; ++cls) {
     const int rc = hip_check(b, run_class(b, cls, kModeMacros, 0), "batch macros kernel");
     if (rc) return rc;

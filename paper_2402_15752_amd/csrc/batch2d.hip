@@ -109,7 +109,62 @@ __global__ void gather_kernel(CPtr<BatchCase> cases, GatherIds ids, int nplanes,
   dst[D->out_off * nplanes + f * n + i] = (float)src[i];
 }
 
+// Fields that need only the node's own moments (phi, c1, c2, psi): f, h1,
+// h2 of each node, the recovery of Sec. III C, straight into the gathered
+// planes -- no stencils, no flow macros, no field buffer.  The values are
+// those the macros mode writes (the same moments() arithmetic).
+template <class S, class T>
+__global__ void gather_moments_kernel(CPtr<BatchCase> cases, KPtr<T> kps, int parity,
+                                      GatherIds ids, int nf, int nplanes,
+                                      float* __restrict__ dst) {
+  using L = D2Q9;
+  using Lay = Layout<D2Q9, D2Q9>;
+  const int c = blockIdx.y;
+  CPtr<BatchCase> D = cases + c;
+  const int n = D->nx * D->ny;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const KParams<T>& P = *(const KParams<T>*)(kps + c);
+  const S* lat = (const S*)D->lat[parity];
+  const uint32_t sS = D->sS, node = uint32_t(i) * uint32_t(sizeof(S));
+  T f[9], h1[9], h2[9];
+  load_q<L, false, false>(at(lat, uint32_t(Lay::F0) * sS), sS, node, f);
+  load_q<L, false, false>(at(lat, uint32_t(Lay::H10) * sS), sS, node, h1);
+  load_q<L, false, false>(at(lat, uint32_t(Lay::H20) * sS), sS, node, h2);
+  Node<T> s{};
+  moments<L>(P, f, h1, h2, s);
+  float* out = dst + D->out_off * nplanes + i;
+  for (int k = 0; k < nf; ++k) {
+    const int id = ids.id[k];
+    const T v = id == kFieldPhi ? s.phi : id == kFieldC1 ? s.c1 : id == kFieldC2 ? s.c2
+                                                                                 : s.c1 + P.Keq * s.c2;
+    out[(long long)k * n] = (float)v;
+  }
+}
+
 }  // namespace
+
+template <class S, class T>
+hipError_t launch_batch_gather_moments(const BatchCase* cases, const KParams<T>* kps, int parity,
+                                       int ncases, long long max_n, const int (&ids)[9], int nf,
+                                       int nplanes, float* dst, hipStream_t stream) {
+  GatherIds g;
+  for (int k = 0; k < 9; ++k) g.id[k] = ids[k];
+  const dim3 grid((unsigned)((max_n + 255) / 256), ncases);
+  hipLaunchKernelGGL((gather_moments_kernel<S, T>), grid, dim3(256), 0, stream,
+                     (CPtr<BatchCase>)cases, (KPtr<T>)kps, parity, g, nf, nplanes, dst);
+  return hipGetLastError();
+}
+
+#define PFLB_GM_INST(S, T)                                                                      \
+  template hipError_t launch_batch_gather_moments<S, T>(const BatchCase*, const KParams<T>*, int, \
+                                                        int, long long, const int (&)[9], int,  \
+                                                        int, float*, hipStream_t);
+PFLB_GM_INST(double, double)
+PFLB_GM_INST(float, float)
+PFLB_GM_INST(__half, float)
+PFLB_GM_INST(__hip_bfloat16, float)
+#undef PFLB_GM_INST
 
 template <class T>
 hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max_n,

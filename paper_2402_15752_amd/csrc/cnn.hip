@@ -50,18 +50,23 @@ __device__ inline float4v mfma(short4v a, short4v b, float4v c) {
 
 enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2, kInfAct = 3, kInfOut = 4 };
 
-constexpr int kConvGroups = 2;  // 16-pixel groups per wave
+// Tile of the convolution kernels: kConvRows rows x kConvCols pixels, one
+// row per wave (4 waves), kConvCols / 16 groups of 16 pixels per wave.
+constexpr int kConvRows = 4;
+constexpr int kConvCols = 32;
 
-// One wave: G groups of 16 consecutive pixels of a row x all COUT channels;
-// the weight operand of each (tap, channel group) is loaded once for the G
-// groups.  Waves are laid over (row, segment of 16 G pixels), so short rows
-// still fill every wave of a block.
+// Each block stages its input rows (with a one-pixel halo, periodic in x)
+// and the layer's BF16 weights in LDS once, then every wave runs its row x
+// all COUT channels with both MFMA operands read from LDS.  Pixel and weight
+// rows are padded by 8 bytes so that the 16 lanes of a 64-bit LDS read hit
+// distinct banks.  The accumulation order (tap, channel group, MFMA) is that
+// of a direct loop over the taps.
 // kFwdAct / kFwdLinear: Z = conv(X) + b (FP32), A = act(Z) (BF16).
 // kInfAct: A = lrelu(conv(X) + b) only (inference: no FP32 copy).
 // kInfOut: out[p] = scale * (conv(X) + b)[channel 0], written to Z.
 // kBwd: X is dZ of the layer above, W its flipped transpose; the result is
 // dA of the layer below, written as dZ = dA * lrelu'(Zprev) in BF16.
-template <int CIN, int COUT, int MODE, int G>
+template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restrict__ X,
                                                    const unsigned short* __restrict__ Wg,
                                                    const float* __restrict__ bias,
@@ -69,14 +74,42 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restr
                                                    unsigned short* __restrict__ A,
                                                    const float* __restrict__ Zprev, int H, int W,
                                                    int rows, float scale) {
-  constexpr int NT = COUT / 16, K = 9 * CIN;
+  constexpr int NT = COUT / 16, K = 9 * CIN, G = kConvCols / 16;
+  constexpr int PS = CIN + 4;            // LDS pixel stride (BF16 values)
+  constexpr int KS = K + 4;              // LDS weight-row stride
+  constexpr int LC = kConvCols + 2, LR = kConvRows + 2;
   static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
-  const int lane = threadIdx.x & 63;
-  const int segs = (W + 16 * G - 1) / (16 * G);
-  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int R = wid / segs;  // global row (sample * H + y)
+  __shared__ __align__(16) unsigned short sx[LR * LC * PS];
+  __shared__ __align__(16) unsigned short sw[COUT * KS];
+  typedef unsigned long long u64;
+
+  const int tiles_x = (W + kConvCols - 1) / kConvCols;
+  const int x0 = (blockIdx.x % tiles_x) * kConvCols;
+  const int R0 = (blockIdx.x / tiles_x) * kConvRows;
+  // stage the input rows R0-1 .. R0+kConvRows and columns x0-1 .. x0+kConvCols
+  // (wrapped in x; columns past x = W and rows outside the batch are zero;
+  // the zero padding in y between samples is applied per tap below)
+  for (int e = threadIdx.x; e < LR * LC * (CIN / 4); e += 256) {
+    const int c4 = e % (CIN / 4), pix = e / (CIN / 4);
+    const int lr = pix / LC, lc = pix % LC;
+    const int Rg = R0 + lr - 1;
+    int xs = x0 + lc - 1;
+    u64 v = 0;
+    if (Rg >= 0 && Rg < rows && xs <= W) {
+      xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+      v = *(const u64*)(X + ((long long)Rg * W + xs) * CIN + c4 * 4);
+    }
+    *(u64*)(sx + (lr * LC + lc) * PS + c4 * 4) = v;
+  }
+  for (int e = threadIdx.x; e < COUT * (K / 4); e += 256) {
+    const int k4 = e % (K / 4), co = e / (K / 4);
+    *(u64*)(sw + co * KS + k4 * 4) = *(const u64*)(Wg + (long long)co * K + k4 * 4);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = R0 + wave;  // global row (sample * H + y) of this wave
   if (R >= rows) return;
-  const int xw = (wid - R * segs) * 16 * G;  // first pixel of the wave
   const int m = lane & 15, g = lane >> 4;
   const int y = R % H;
   float4v acc[G][NT];
@@ -87,21 +120,19 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restr
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const bool rowok = y + dy >= 0 && y + dy < H;
-    const long long rowbase = (long long)(R + dy) * W;
+    if (y + dy < 0 || y + dy >= H) continue;  // zero padding in y (uniform per wave)
+    const unsigned short* xrow = sx + (wave + 1 + dy) * LC * PS;
 #pragma unroll
     for (int cg = 0; cg < CIN / 16; ++cg) {
       const int k = tap * CIN + cg * 16 + 4 * g;
       short4v b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = load4(Wg + (long long)(t * 16 + m) * K + k);
+      for (int t = 0; t < NT; ++t) b[t] = __builtin_bit_cast(short4v, *(const u64*)(sw + (t * 16 + m) * KS + k));
 #pragma unroll
       for (int q = 0; q < G; ++q) {
-        const int x = xw + q * 16 + m;  // pixel of this lane's A row
-        int xs = x + dx;
-        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-        const short4v a = rowok && x < W ? load4(X + (rowbase + xs) * CIN + cg * 16 + 4 * g)
-                                         : short4v{0, 0, 0, 0};
+        const int col = q * 16 + m + dx + 1;  // LDS column of this lane's A row
+        const short4v a =
+            __builtin_bit_cast(short4v, *(const u64*)(xrow + col * PS + cg * 16 + 4 * g));
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[q][t] = mfma(a, b[t], acc[q][t]);
       }
@@ -110,14 +141,14 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restr
   // D[pixel 4 g + j][channel l % 16]
 #pragma unroll
   for (int q = 0; q < G; ++q) {
-    const int x0 = xw + q * 16;
+    const int xq = x0 + q * 16;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + m;
       if (MODE == kInfOut && co != 0) continue;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int xp = x0 + 4 * g + j;
+        const int xp = xq + 4 * g + j;
         if (xp >= W) continue;
         const long long p = (long long)R * W + xp;
         float v = acc[q][t][j];
@@ -352,11 +383,11 @@ __global__ void weights_kernel(const float* __restrict__ W, int cin, int cout,
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
                     int W, int rows, float scale, hipStream_t s) {
-  constexpr int G = kConvGroups;
-  const long long waves = (long long)rows * ((W + 16 * G - 1) / (16 * G));
-  const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+  const long long blocks =
+      (long long)((W + kConvCols - 1) / kConvCols) * ((rows + kConvRows - 1) / kConvRows);
+  const dim3 grid((unsigned)blocks), blk(256);
 #define PFLB_CONV(CI, CO, MO) \
-  hipLaunchKernelGGL((conv_kernel<CI, CO, MO, G>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, scale)
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MO>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, scale)
   // forward: layer l maps C_in(l) -> C_out(l); backward (the adjoint of
   // layer l) maps C_out(l) -> C_in(l)
   switch (mode) {

@@ -75,6 +75,12 @@ int step2d_tiles(int nx, int ny, int variant);
 // into dst as FP32: case c starts at dst[out_off(c) * nplanes] and holds
 // nplanes >= nf planes of its N values, the first nf of them written.
 // max_n: the largest N of a case.
+// Gather of fields that need only the node's own moments (phi, c1, c2, psi)
+// straight from the populations of the current parity.
+template <class S, class T>
+hipError_t launch_batch_gather_moments(const BatchCase* cases, const KParams<T>* kps, int parity,
+                                       int ncases, long long max_n, const int (&ids)[9], int nf,
+                                       int nplanes, float* dst, hipStream_t stream);
 template <class T>
 hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max_n,
                                const int (&ids)[9], int nf, int nplanes, float* dst,

@@ -266,3 +266,24 @@ def test_batch_gather_layout_and_init_planes(cplb):
         gk.close()
     with pytest.raises(AssertionError):
         b2.init_planes(planes.cuda()[:-1], nplanes)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f32_s16f"])
+def test_batch_moment_gather_equals_field_readout(cplb, precision):
+    """Fields that need only the node's own moments (phi, c1, c2, psi) are
+    gathered straight from the populations; they equal the read-out through
+    the macros kernel bit for bit (as float32)."""
+    import torch
+    cases = mixed_cases(precision, seed=21)
+    b = make_batch(cplb, cases)
+    b.step(9)
+    names = ("c2", "phi", "psi", "c1")
+    g = b.gather(names, nplanes=5).cpu().numpy()
+    off = 0
+    for k, c in enumerate(cases):
+        nx, ny = c["params"]["nx"], c["params"]["ny"]
+        blk = g[off * 5:(off + nx * ny) * 5].reshape(5, ny, nx)
+        for f, name in enumerate(names):
+            want = b.field(k, name, dtype=torch.float32).cpu().numpy()
+            assert np.array_equal(blk[f], want), (precision, k, name)
+        off += nx * ny
