@@ -46,8 +46,9 @@ TRAFFIC = {
 }
 
 
-# the sources that define the single-lattice step kernels and their launch
-STEP_SOURCES = ("addr.hpp", "common.hpp", "step2d.hip", "step2d_tile.hpp", "step3d.hip")
+# the sources that define the single-lattice step kernels, their launch and
+# the default variant
+STEP_SOURCES = ("addr.hpp", "api.hip", "common.hpp", "step2d.hip", "step2d_tile.hpp", "step3d.hip")
 
 
 def kernel_source_hash():
@@ -101,6 +102,10 @@ def make_workload(name):
     if name.startswith("rising_droplet_256c"):
         prec = name[len("rising_droplet_256c_"):] or "f32"
         return W.rising_droplet_3d(256, prec)
+    if name.startswith("rising_droplet_local_256c"):
+        # grad(c1 + Keq c2) by the local scheme of Eq. (39): no h halo, no psi ring
+        prec = name[len("rising_droplet_local_256c_"):] or "f32"
+        return W.rising_droplet_3d(256, prec, scalar_grad="local")
     if name == "static_drop_64x64":
         return W.static_drop_64()
     raise SystemExit(f"unknown workload {name}")
@@ -310,8 +315,10 @@ def main():
     out["check"] = {"nonfinite": r["nonfinite"], "sum_phi": r["sum_phi"], "step": r["step"]}
     if not args.no_extra and args.workload == "rising_bubble_256x1024":
         extra = {}
-        for prec in ("f32", "f32_s16f", "f32_s16b"):
-            w3 = make_workload(f"rising_droplet_256c_{prec}")
+        for wname in ("rising_droplet_256c_f32", "rising_droplet_256c_f32_s16f",
+                      "rising_droplet_256c_f32_s16b", "rising_droplet_local_256c_f32",
+                      "rising_droplet_local_256c_f32_s16f"):
+            w3 = make_workload(wname)
             r3 = time_gpu(w3, 100, 10)
             b3 = alg_bytes_per_node(w3["params"])
             a3 = b3 * r3["n"] / (r3["avg_kernel_ms"] * 1e-3) / 1e9

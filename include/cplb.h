@@ -94,8 +94,8 @@ extern "C" {
  *   grad c1 = [-sum c_i h1_i + c1 u - d_t(c1 u)/2 + D1 4 (1-phi) c1 n / W] / (tau_h1 cs^2),
  *   grad c2 = [-sum c_i h2_i + c2 u - d_t(c2 u)/2 - D2 4 phi c2 n / W] / (tau_h2 cs^2),
  * with u and n of the step.  The local scheme needs no psi stencil, so the
- * step reads no h1, h2 of the halo.  CPLB_D2Q9, the two-scalar model and
- * no-flux scalar walls only. */
+ * step reads no h1, h2 of the halo.  The two-scalar model and no-flux
+ * scalar walls only; single lattices (not batches). */
 #define CPLB_GRAD_CENTRAL 0
 #define CPLB_GRAD_LOCAL 1
 

@@ -60,16 +60,25 @@ hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, const KParams<T>* Kdev,
 
 int num_variants(const cplb_t* h) { return h->G.dim == 2 ? kVariants2D : kVariants3D; }
 
-// default variant per lattice and storage width (set from measurements;
-// cplb_tune can pick another for a given grid)
-// Fastest variant measured on MI355X for the rising-bubble (256x1024 D2Q9) and
-// rising-droplet (256^3 D3Q19+D3Q7) workloads; cplb_tune re-checks on the
-// caller's own state.
+// Default step-kernel variant per lattice, storage width and gradient scheme:
+// the fastest measured on MI355X for the rising bubble (D2Q9, 256 x 1024 and
+// 2048 x 4096) and the rising droplet (256^3) with the skewed plane layout
+// (aligned push stores, so non-temporal stores pay off beyond the Infinity
+// Cache); cplb_tune re-checks on the caller's own state.
 int default_variant(const cplb_params* p) {
-  if (p->lattice == CPLB_D2Q9) return 3;  // 128x4
-  // 16-bit storage: 64x4, f / h re-read before their collision (fewer
-  // registers, 3 waves per SIMD); FP32 / FP64: 64x4, registers carried
-  return p->precision >= CPLB_F32_S16F ? 0 : 3;
+  if (p->lattice == CPLB_D2Q9) {
+    // 128x4; with the local gradient scheme a lattice beyond the 256 MB
+    // Infinity Cache streams faster with non-temporal hints (128x4 nt)
+    const int s_pop = p->precision == CPLB_F64 ? 8 : (p->precision == CPLB_F32 ? 4 : 2);
+    const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
+    return p->scalar_grad == CPLB_GRAD_LOCAL && lattice_bytes > 256e6 ? 7 : 3;
+  }
+  // 3-D, 16-bit storage: central stencil 64x4 with f / h re-read before their
+  // collision and non-temporal g loads and stores; local gradient scheme
+  // (fewer registers) 64x4 carried, non-temporal stores
+  if (p->precision >= CPLB_F32_S16F) return p->scalar_grad == CPLB_GRAD_LOCAL ? 4 : 6;
+  // FP32 / FP64: 64x4 carried, non-temporal stores
+  return 4;
 }
 
 hipError_t run_kernel(cplb_t* h, int mode) {

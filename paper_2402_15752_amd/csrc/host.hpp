@@ -49,7 +49,6 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
   if (p->scalar_grad != CPLB_GRAD_CENTRAL && p->scalar_grad != CPLB_GRAD_LOCAL)
     return fail("unknown scalar gradient scheme");
   if (p->scalar_grad == CPLB_GRAD_LOCAL) {
-    if (d != 2) return fail("the local gradient scheme runs on CPLB_D2Q9 only");
     if (p->scalar_model != CPLB_TWO_SCALAR) return fail("the local gradient scheme takes the two-scalar model");
     for (int f = 0; f < 6; ++f)
       if (p->scalar_bc[f] != CPLB_BC_NOFLUX)

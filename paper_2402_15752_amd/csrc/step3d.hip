@@ -59,13 +59,16 @@ struct Geo3 {
 
 __device__ inline int slot_of(int z) { return (z + 4) & 3; }
 
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PSI>
 struct Ring {
   T phi[4][TY + 2][TX + 2];
-  T psi[4][TY + 2][TX + 2];
+  T psi[PSI ? 4 : 1][TY + 2][TX + 2];  // no psi ring with the local gradient scheme
 };
 
-template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off>
+// LOC: grad(c1 + Keq c2) by the local scheme of Eq. (39) from the own h1, h2
+// of the plane being collided -- no psi ring, no h1, h2 of the halo.
+template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off,
+          bool LOC>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst, T* __restrict__ hist,
                                                         T* __restrict__ fields,
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // non-temporal hints: bit 0 f / h loads, bit 1 stores, bit 2 g loads
   constexpr bool NTL = NT & 1, NTW = NT & 2, NTG = NT & 4;
   constexpr Off BS = sizeof(S);
-  __shared__ Ring<T, TX, TY> R;
+  __shared__ Ring<T, TX, TY, !LOC> R;
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -120,19 +123,33 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     if (own_slot) {
       moments<LF>(P, f, h1, h2, s);
       R.phi[sl][ty + 1][tx + 1] = s.dphi;
-      R.psi[sl][ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+      if (!LOC) R.psi[sl][ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
     }
     if (halo) {
-      Node<T> q;
-      moments<LF>(P, hf, hh1, hh2, q);
-      R.phi[sl][hy + 1][hx + 1] = q.dphi;
-      R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+      if constexpr (LOC) {
+        T d = hf[0];
+#pragma unroll
+        for (int i = 1; i < 7; ++i) d += hf[i];
+        R.phi[sl][hy + 1][hx + 1] = d;
+      } else {
+        Node<T> q;
+        moments<LF>(P, hf, hh1, hh2, q);
+        R.phi[sl][hy + 1][hx + 1] = q.dphi;
+        R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+      }
     }
   };
   auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
     load_q<LF, NTL, true>(sF, G.sS, node, f);
     load_q<LF, NTL, true>(sH1, G.sS, node, h1);
     load_q<LF, NTL, true>(sH2, G.sS, node, h2);
+  };
+  // the halo needs h1, h2 only for the psi stencil
+  auto load_halo = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
+    if constexpr (LOC)
+      load_q<LF, NTL, true>(sF, G.sS, node, f);
+    else
+      load_fh(node, f, h1, h2);
   };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
@@ -144,11 +161,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const Off pm = Off(fold(z0 - 1, nz, G.wall_z)) * G.nxy;
     const Off p0 = Off(z0) * G.nxy;
     if (own_slot) load_fh(pm + own_col, af, ah1, ah2);
-    if (halo) load_fh(pm + halo_col, hf, hh1, hh2);
+    if (halo) load_halo(pm + halo_col, hf, hh1, hh2);
     Node<T> tmp;
     put(P, z0 - 1, af, ah1, ah2, tmp, hf, hh1, hh2);
     if (own_slot) load_fh(p0 + own_col, f, h1, h2);
-    if (halo) load_fh(p0 + halo_col, hf, hh1, hh2);
+    if (halo) load_halo(p0 + halo_col, hf, hh1, hh2);
     put(P, z0, f, h1, h2, s, hf, hh1, hh2);
   }
   // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits: the
@@ -175,7 +192,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     };
     if (PREF && active) load_g();
     if (own_slot) load_fh(pn + own_col, nf, nh1, nh2);
-    if (halo) load_fh(pn + halo_col, hf, hh1, hh2);
+    if (halo) load_halo(pn + halo_col, hf, hh1, hh2);
     // ---- 2. moments of plane z+1 into the ring
     Node<T> ns{};
     put(P, z + 1, nf, nh1, nh2, ns, hf, hh1, hh2);
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       for (int i = 1; i < 19; ++i) {
         const int sl = LG::cz[i] < 0 ? sm : (LG::cz[i] > 0 ? sp : s0);
         const T a = R.phi[sl][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]];
-        const T b = R.psi[sl][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]];
+        const T b = LOC ? T(0) : R.psi[sl][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]];
         const T wc = T(LG::w[i] / LG::cs2);
         if (LG::cx[i]) {
           gphi[0] += wc * T(LG::cx[i]) * a;
@@ -276,6 +293,23 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
           load_q<LF, NTL, true>(sH1, G.sS, node, h1);
           load_q<LF, NTL, true>(sH2, G.sS, node, h2);
         }
+        if constexpr (LOC) {
+          // local scheme, Eq. (39): grad c_k from the first moment of the
+          // own h_k (deviations carry the same first moment)
+          T q1[3], q2[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            q1[a] = h1[1 + 2 * a] - h1[2 + 2 * a];  // D3Q7: +axis a, -axis a
+            q2[a] = h2[1 + 2 * a] - h2[2 + 2 * a];
+          }
+          const T f1 = P.d1w * s.omphi * s.c1, f2 = P.d2w * s.phi * s.c2;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const T g1 = (s.c1 * fl.u[a] - q1[a] - T(0.5) * dJ1[a] + f1 * n[a]) * P.itc1;
+            const T g2 = (s.c2 * fl.u[a] - q2[a] - T(0.5) * dJ2[a] - f2 * n[a]) * P.itc2;
+            gpsi[a] = g1 + P.Keq * g2;
+          }
+        }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
           st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
@@ -332,10 +366,10 @@ int choose_chunks(int tiles_xy, int nz, int slots) {
 }
 
 template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE,
-          class Off>
+          class Off, bool LOC = false>
 hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, hipStream_t stream) {
-  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off>;
+  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off, LOC>;
   static std::atomic<int> per_cu{0};
   int groups = per_cu.load(std::memory_order_relaxed);
   if (groups < 1) {
@@ -375,8 +409,11 @@ const char* step3d_variant_name(int v) {
   return v >= 0 && v < kVariants3D ? names[v] : "?";
 }
 
-template <class S, class T>
-hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+namespace {
+
+// the variant switch of one gradient scheme (LOC: Eq. (39))
+template <class S, class T, bool LOC>
+hipError_t launch_scheme(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
   constexpr int M = kModeStep;
   using U = uint32_t;
@@ -385,14 +422,15 @@ hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams
     if (mode == kModeMacros)
       return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t>(
           src, dst, hist, fields, P, Pdev, stream);
-    return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t>(
+    return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t, LOC>(
         src, dst, hist, fields, P, Pdev, stream);
   }
+  // the field read-out does not depend on the gradient scheme
   if (mode == kModeMacros)
     return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U>(
         src, dst, hist, fields, P, Pdev, stream);
 #define PFLB_V3(TX, TY, NT, PREF, LATE, WPE) \
-  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U>(src, dst, hist, fields, P, Pdev, stream)
+  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC>(src, dst, hist, fields, P, Pdev, stream)
   // NT: non-temporal hints (bit 0 f / h loads, bit 1 stores, bit 2 g loads);
   // LATE: f / h re-read before their collision; WPE: minimum waves per SIMD
   // the register allocator must allow (1: free)
@@ -407,6 +445,16 @@ hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams
     default: return PFLB_V3(64, 4, 0, false, true, 1);
   }
 #undef PFLB_V3
+}
+
+}  // namespace
+
+template <class S, class T>
+hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+                         const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
+  if (P.local_grad)
+    return launch_scheme<S, T, true>(src, dst, hist, fields, P, Pdev, mode, variant, stream);
+  return launch_scheme<S, T, false>(src, dst, hist, fields, P, Pdev, mode, variant, stream);
 }
 
 template hipError_t launch_step3d<double, double>(const double*, double*, double*, double*,

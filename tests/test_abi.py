@@ -75,8 +75,7 @@ def test_workspace_bytes_cover_two_lattices(cplb):
                                       scalar_bc=("dirichlet",) + ("noflux",) * 5),
                                  dict(lattice="d3q19_d3q7", nz=8, nx=8, ny=8, periodic=(1, 1, 0),
                                       scalar_bc=("noflux",) * 4 + ("dirichlet", "noflux")),
-                                 dict(scalar_grad="local", scalar_model="one"),
-                                 dict(scalar_grad="local", lattice="d3q19_d3q7", nz=8, nx=8, ny=8)])
+                                 dict(scalar_grad="local", scalar_model="one")])
 def test_validation_rejects(cplb, bad):
     p = W.params(**bad)
     with pytest.raises(cplb.CplbError) as e:

@@ -89,3 +89,49 @@ def test_local_gradient_variants_bitwise(cplb):
     for v in range(1, len(out)):
         for k in out[0]:
             assert np.array_equal(out[0][k], out[v][k]), (v, k)
+
+
+@pytest.mark.parametrize("periodic", [(1, 1, 1), (1, 1, 0), (0, 1, 0), (0, 0, 0)])
+def test_local_gradient_fp64_random_fields_3d(cplb, periodic):
+    say(f"local gradient fp64 3d random periodic={periodic}")
+    p = W.params(nx=35, ny=13, nz=70, lattice="d3q19_d3q7", periodic=periodic, precision="f64",
+                 sigma=2e-3, rho1=3.0, rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07,
+                 D2=0.02, Keq=0.6, A=0.4, g=(1e-5, -2e-5, 3e-5), rho_ref=1.5, scalar_grad="local")
+    f = W.random_fields(p, seed=5)
+    g = cplb.Lattice(p)
+    o = ref.Oracle(p)
+    for x in (g, o):
+        x.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    g.step(3)
+    o.step(3)
+    compare(g, o, FIELDS + ("uz",), 1e-12, "t=3")
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-5), ("f32_s16f", 2e-3)])
+def test_local_gradient_droplet3d(cplb, precision, tol):
+    w = W.rising_droplet_3d(n=64, precision=precision, scalar_grad="local")
+    say(f"local gradient rising droplet 64^3 {precision}, 200 steps")
+    g = cplb.Lattice(w["params"])
+    o = ref.Oracle(dict(w["params"], precision="f64"))
+    for s in (g, o):
+        s.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    g.step(200)
+    o.step(200)
+    names = ("phi", "c1", "c2", "ux", "uy", "uz", "p") if precision == "f32" else ("phi", "c1", "c2")
+    compare(g, o, names, tol, f"{precision} t=200")
+
+
+def test_local_gradient_variants_bitwise_3d(cplb):
+    p = W.params(nx=35, ny=13, nz=30, lattice="d3q19_d3q7", periodic=(1, 0, 0), precision="f32",
+                 ref_f=0.5, sigma=2e-3, D1=0.07, D2=0.02, Keq=0.6, A=0.4, scalar_grad="local")
+    f = W.random_fields(p, seed=29)
+    g = cplb.Lattice(p)
+    out = []
+    for v in range(len(g.variant_names())):
+        g.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+        g.variant = v
+        g.step(4)
+        out.append({k: g.field(k).cpu().numpy() for k in ("phi", "c1", "c2", "uz", "p")})
+    for v in range(1, len(out)):
+        for k in out[0]:
+            assert np.array_equal(out[0][k], out[v][k]), (v, k)

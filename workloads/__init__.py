@@ -157,7 +157,7 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=N
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=20000)
 
 
-def rising_droplet_3d(n=256, precision="f32"):
+def rising_droplet_3d(n=256, precision="f32", scalar_grad="central"):
     """3-D rising droplet with heat transfer: n^3, periodic in x and y, walls at
     the z faces, gravity along -z; droplet (fluid 2) of radius 24 n/256 at
     (n/2, n/2, 3R); density ratio 10, exponential viscosity law, Eo = 10;
@@ -169,9 +169,11 @@ def rising_droplet_3d(n=256, precision="f32"):
     p = params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", visc_law="exp", periodic=(1, 1, 0),
                rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
                D1=0.05, D2=0.01, Keq=10.0, A=0.1, g=(0.0, 0.0, -gmag), rho_ref=rho1,
-               precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0)
+               precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0,
+               scalar_grad=scalar_grad)
     l = sdf_sphere(p, (n / 2.0, n / 2.0, 3.0 * R), R, inside_positive=False)
-    return dict(name=f"rising_droplet_{n}c_{precision}", params=p, sdf=l,
+    tag = "_local" if scalar_grad == "local" else ""
+    return dict(name=f"rising_droplet{tag}_{n}c_{precision}", params=p, sdf=l,
                 init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0)), steps=5000)
 
 
