@@ -33,16 +33,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 45045046, "write": 43037223,
-                                  "src": "91042dd3c39c7e5c"},
-    "rising_droplet_256c_f32": {"read": 3756780808, "write": 3096946272,
-                               "src": "91042dd3c39c7e5c"},
-    "rising_droplet_256c_f32_s16f": {"read": 2477269448, "write": 1749233947,
-                                    "src": "91042dd3c39c7e5c"},
-    "rising_bubble_2048x4096_f32": {"read": 1475349202, "write": 1376897608,
-                                   "src": "91042dd3c39c7e5c"},
-    "rising_bubble_one_256x1024_f32": {"read": 32830240, "write": 32516664,
-                                      "src": "91042dd3c39c7e5c"},
+    "rising_bubble_256x1024_f32": {"read": 44451061, "write": 43033627,
+                                  "src": "c7e76c4e09ce25c6"},
+    "rising_droplet_256c_f32": {"read": 3434632168, "write": 3124257328,
+                               "src": "c7e76c4e09ce25c6"},
+    "rising_droplet_256c_f32_s16f": {"read": 2292812911, "write": 1772127712,
+                                    "src": "c7e76c4e09ce25c6"},
+    "rising_bubble_2048x4096_f32": {"read": 1479781648, "write": 1376907000,
+                                   "src": "c7e76c4e09ce25c6"},
+    "rising_bubble_one_256x1024_f32": {"read": 32782196, "write": 32516141,
+                                      "src": "c7e76c4e09ce25c6"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1768943102, "write": 1379153477,
+                                         "src": "c7e76c4e09ce25c6"},
+    "rising_droplet_local_256c_f32": {"read": 3339978729, "write": 3122301877,
+                                     "src": "c7e76c4e09ce25c6"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1760774334, "write": 1773808149,
+                                          "src": "c7e76c4e09ce25c6"},
 }
 
 
