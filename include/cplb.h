@@ -237,7 +237,7 @@ int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step);
  * The caller owns the workspace and the stream as for a single lattice;
  * icase numbers cases in the order of prm[].  Errors as above.
  */
-#define CPLB_BATCH_CLASSES 3 /* size classes: nx <= 96, nx <= 160, larger */
+#define CPLB_BATCH_CLASSES 5 /* size classes: nx <= 64, 96, 128, 192, larger */
 
 typedef struct cplb_batch cplb_batch_t;
 

@@ -114,8 +114,8 @@ template <class Off>
 struct PushXY {
   Off dxm, dxp, dym, dyp;
   int bits;
-  __device__ PushXY(int x, int y, int nx, int ny, int wall_x, int wall_y, Off bs) {
-    const Off row = Off(nx) * bs;
+  __device__ PushXY(int x, int y, int nx, int ny, int px, int wall_x, int wall_y, Off bs) {
+    const Off row = Off(px) * bs;  // rows are px nodes apart
     dxm = Off(0) - bs;
     dxp = bs;
     dym = Off(0) - row;

@@ -263,10 +263,10 @@ int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype) {
   hipError_t e;
   if (h->G.s_cmp == 8)
     e = launch_convert<double>((const double*)h->fields + field * h->G.stride, dev_dst, dtype, h->G.n,
-                               h->stream);
+                               h->prm.nx, h->G.px, h->stream);
   else
     e = launch_convert<float>((const float*)h->fields + field * h->G.stride, dev_dst, dtype, h->G.n,
-                              h->stream);
+                              h->prm.nx, h->G.px, h->stream);
   return hip_check(h, e, "field conversion");
 }
 
@@ -278,11 +278,11 @@ int cplb_reduce(cplb_t* h, double out[8]) {
   const int nparts = h->G.n < (long long)kReduceBlocks * 256 ? (int)((h->G.n + 255) / 256) : kReduceBlocks;
   hipError_t e;
   if (h->G.s_cmp == 8)
-    e = launch_reduce<double>((const double*)h->fields, h->G.stride, h->G.n, h->prm.rho1,
-                              h->prm.rho2, h->partials, nparts, dout, h->stream);
+    e = launch_reduce<double>((const double*)h->fields, h->G.stride, h->G.n, h->prm.nx, h->G.px,
+                              h->prm.rho1, h->prm.rho2, h->partials, nparts, dout, h->stream);
   else
-    e = launch_reduce<float>((const float*)h->fields, h->G.stride, h->G.n, h->prm.rho1, h->prm.rho2,
-                             h->partials, nparts, dout, h->stream);
+    e = launch_reduce<float>((const float*)h->fields, h->G.stride, h->G.n, h->prm.nx, h->G.px,
+                             h->prm.rho1, h->prm.rho2, h->partials, nparts, dout, h->stream);
   rc = hip_check(h, e, "reduction kernels");
   if (rc) return rc;
   double tmp[8];
@@ -299,8 +299,8 @@ int cplb_reduce(cplb_t* h, double out[8]) {
 
 size_t cplb_state_bytes(const cplb_t* h) {
   if (!h) return 0;
-  return sizeof(StateHeader) + (size_t)h->G.qtot * h->G.n * h->G.s_pop +
-         (size_t)h->G.nhist * h->G.n * h->G.s_cmp;
+  return sizeof(StateHeader) + (size_t)h->G.qtot * h->G.cells * h->G.s_pop +
+         (size_t)h->G.nhist * h->G.cells * h->G.s_cmp;
 }
 
 int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes) {
@@ -316,7 +316,8 @@ int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes) {
   char* o = (char*)host_dst;
   memcpy(o, &hd, sizeof(hd));
   o += sizeof(hd);
-  const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
+  // whole planes of cells (nodes and row padding), from node 0 of each
+  const size_t pb = (size_t)h->G.cells * h->G.s_pop, hb = (size_t)h->G.cells * h->G.s_cmp;
   for (int q = 0; q < h->G.qtot; ++q, o += pb) {
     const long long first = q * h->G.stride + plane_skew_el(h->G.dim, q);  // node 0 of plane q
     rc = hip_check(h, hipMemcpy(o, (char*)h->lat[h->cur] + first * h->G.s_pop, pb,
@@ -342,7 +343,8 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
   int rc = hip_check(h, hipStreamSynchronize(h->stream), "restore synchronise");
   if (rc) return rc;
   const char* o = (const char*)host_src + sizeof(hd);
-  const size_t pb = (size_t)h->G.n * h->G.s_pop, hb = (size_t)h->G.n * h->G.s_cmp;
+  // whole planes of cells (nodes and row padding), from node 0 of each
+  const size_t pb = (size_t)h->G.cells * h->G.s_pop, hb = (size_t)h->G.cells * h->G.s_cmp;
   h->cur = 0;
   for (int q = 0; q < h->G.qtot; ++q, o += pb) {
     const long long first = q * h->G.stride + plane_skew_el(h->G.dim, q);  // node 0 of plane q

@@ -47,30 +47,33 @@ __global__ __launch_bounds__(256) void init_kernel(S* __restrict__ lat, T* __res
   T f[LF::Q], g[LG::Q], h1[LF::Q], h2[LF::Q];
   equilibria<LF, LG>(P, T(phi), T(c1), T(c2), u, p, f, g, h1, h2);
   const long long st = P.stride;
+  const long long pn = pitched(node, P.nx, P.px);  // the node in the planes
 #pragma unroll
   for (int i = 0; i < LF::Q; ++i) {
     // plane skew of the push streaming (addr.hpp)
-    const long long n = node + skew_el<LF>(i);
+    const long long n = pn + skew_el<LF>(i);
     store_one<LF>(lat, (Lay::F0 + i) * st + n, i, f[i]);
     store_one<LF>(lat, (Lay::H10 + i) * st + n, i, h1[i]);
     store_one<LF>(lat, (Lay::H20 + i) * st + n, i, h2[i]);
   }
 #pragma unroll
   for (int i = 0; i < LG::Q; ++i)
-    store_one<LG>(lat, (Lay::G0 + i) * st + node + skew_el<LG>(i), i, g[i]);
+    store_one<LG>(lat, (Lay::G0 + i) * st + pn + skew_el<LG>(i), i, g[i]);
   int k = 0;
-  for (int a = 0; a < LG::D; ++a) hist[(k++) * st + node] = u[a];
-  hist[(k++) * st + node] = T(phi);
-  hist[(k++) * st + node] = T(c1);
-  hist[(k++) * st + node] = T(c2);
+  for (int a = 0; a < LG::D; ++a) hist[(k++) * st + pn] = u[a];
+  hist[(k++) * st + pn] = T(phi);
+  hist[(k++) * st + pn] = T(c1);
+  hist[(k++) * st + pn] = T(c2);
 }
 
 // ------------------------------------------------------------ conversion
 
+// compact dst[i] from a plane of row pitch px
 template <class T, class D>
-__global__ void convert_kernel(const T* __restrict__ src, D* __restrict__ dst, long long n) {
+__global__ void convert_kernel(const T* __restrict__ src, D* __restrict__ dst, long long n, int nx,
+                               int px) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = D(src[i]);
+  if (i < n) dst[i] = D(src[pitched(i, nx, px)]);
 }
 
 // ------------------------------------------------------------- reduction
@@ -111,13 +114,14 @@ __device__ inline void block_reduce(double (&v)[7], double* __restrict__ out) {
 
 template <class T>
 __global__ __launch_bounds__(kRB) void reduce_stage1(const T* __restrict__ fields, long long stride,
-                                                     long long n, double rho1, double rho2,
-                                                     double* __restrict__ partials) {
+                                                     long long n, int nx, int px, double rho1,
+                                                     double rho2, double* __restrict__ partials) {
   const long long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long long lo = (long long)blockIdx.x * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (long long i = lo + threadIdx.x; i < hi; i += kRB) {
+  for (long long ic = lo + threadIdx.x; ic < hi; ic += kRB) {
+    const long long i = pitched(ic, nx, px);
     const double phi = fields[kFieldPhi * stride + i];
     const double c1 = fields[kFieldC1 * stride + i];
     const double c2 = fields[kFieldC2 * stride + i];
@@ -167,22 +171,24 @@ hipError_t launch_init(int dim, S* lat, T* hist, const double* phi_or_l, const d
 }
 
 template <class T>
-hipError_t launch_convert(const T* src, void* dst, int dtype, long long n, hipStream_t stream) {
+hipError_t launch_convert(const T* src, void* dst, int dtype, long long n, int nx, int px,
+                          hipStream_t stream) {
   const int blocks = (int)((n + 255) / 256);
   if (dtype == 0)
     hipLaunchKernelGGL((convert_kernel<T, float>), dim3(blocks), dim3(256), 0, stream, src,
-                       (float*)dst, n);
+                       (float*)dst, n, nx, px);
   else
     hipLaunchKernelGGL((convert_kernel<T, double>), dim3(blocks), dim3(256), 0, stream, src,
-                       (double*)dst, n);
+                       (double*)dst, n, nx, px);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_reduce(const T* fields, long long stride, long long n, double rho1, double rho2,
-                         double* partials, int nparts, double* out, hipStream_t stream) {
-  hipLaunchKernelGGL((reduce_stage1<T>), dim3(nparts), dim3(kRB), 0, stream, fields, stride, n, rho1,
-                     rho2, partials);
+hipError_t launch_reduce(const T* fields, long long stride, long long n, int nx, int px,
+                         double rho1, double rho2, double* partials, int nparts, double* out,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL((reduce_stage1<T>), dim3(nparts), dim3(kRB), 0, stream, fields, stride, n, nx,
+                     px, rho1, rho2, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(kRB), 0, stream, partials, nparts, out);
@@ -198,11 +204,13 @@ CPLB_INST_INIT(float, float)
 CPLB_INST_INIT(__half, float)
 CPLB_INST_INIT(__hip_bfloat16, float)
 
-template hipError_t launch_convert<double>(const double*, void*, int, long long, hipStream_t);
-template hipError_t launch_convert<float>(const float*, void*, int, long long, hipStream_t);
-template hipError_t launch_reduce<double>(const double*, long long, long long, double, double,
-                                          double*, int, double*, hipStream_t);
-template hipError_t launch_reduce<float>(const float*, long long, long long, double, double, double*,
-                                         int, double*, hipStream_t);
+template hipError_t launch_convert<double>(const double*, void*, int, long long, int, int,
+                                           hipStream_t);
+template hipError_t launch_convert<float>(const float*, void*, int, long long, int, int,
+                                          hipStream_t);
+template hipError_t launch_reduce<double>(const double*, long long, long long, int, int, double,
+                                          double, double*, int, double*, hipStream_t);
+template hipError_t launch_reduce<float>(const float*, long long, long long, int, int, double,
+                                         double, double*, int, double*, hipStream_t);
 
 }  // namespace pflb

@@ -15,9 +15,11 @@ using namespace pflb;
 
 namespace {
 
-// size classes by nx: the tile shape that suits a lattice depends on its width
+// size classes by nx, matched to the tile widths (32, 64, 128): a class's
+// cases fill their last tile column well with one tile shape (64, 3 x 32,
+// 128, 3 x 64, 2 x 128 nodes)
 constexpr int kBatchClasses = CPLB_BATCH_CLASSES;
-constexpr int kClassMaxNx[kBatchClasses] = {96, 160, 1 << 30};
+constexpr int kClassMaxNx[kBatchClasses] = {64, 96, 128, 192, 1 << 30};
 
 int class_of(int nx) {
   for (int c = 0; c < kBatchClasses; ++c)
@@ -26,7 +28,7 @@ int class_of(int nx) {
 }
 
 // measured on MI355X for lattices of 64..256 a side; cplb_batch_tune refines
-constexpr int kClassDefaultVariant[kBatchClasses] = {0, 0, 3};
+constexpr int kClassDefaultVariant[kBatchClasses] = {0, 1, 3, 0, 3};
 
 struct Region {
   size_t lat, hist, fields;  // offsets in the workspace
@@ -34,8 +36,17 @@ struct Region {
 
 struct Layout2 {
   std::vector<Region> reg;
-  size_t partials, cases, k64, k32, ids, prefix, iota, single, total;
+  size_t partials, cases, k64, k32, ids, prefix, iota, single, map, total;
 };
+
+// entries of the tile maps: one (case, tile of the case) per tile of every
+// case in every variant's tiling
+long long map_entries(const cplb_params* prm, int n) {
+  long long e = 0;
+  for (int c = 0; c < n; ++c)
+    for (int v = 0; v < kVariants2D; ++v) e += step2d_tiles(prm[c].nx, prm[c].ny, v);
+  return e;
+}
 
 Layout2 layout(const cplb_params* prm, int n) {
   Layout2 L;
@@ -66,6 +77,8 @@ Layout2 layout(const cplb_params* prm, int n) {
   off += align_up((size_t)n * sizeof(int), kAlign);
   L.single = off;
   off += align_up((size_t)2 * n * sizeof(int), kAlign);
+  L.map = off;
+  off += align_up((size_t)map_entries(prm, n) * 2 * sizeof(int), kAlign);
   L.total = off;
   return L;
 }
@@ -126,6 +139,8 @@ struct cplb_batch {
   std::vector<BatchCase> cases;  // host copy of the device table
   std::vector<int> ids;          // case ids grouped by class
   std::vector<int> prefix;       // [class][variant][n + 1]
+  std::vector<int> map;          // (case, tile) of every tile, per class and variant
+  long long map_at[kBatchClasses][kVariants2D];  // first map entry of each
   std::vector<int> iota;         // 0, 1, ..., n - 1: one case as its own work list
   std::vector<int> single;       // per case {0, tiles of the read-out shape}
   std::vector<int> case_cls;
@@ -142,6 +157,7 @@ struct cplb_batch {
   int* d_prefix;
   int* d_iota;
   int* d_single;
+  int* d_map;
   int cur;
   int64_t step;
   char err[512];
@@ -176,7 +192,8 @@ hipError_t launch_class(cplb_batch_t* b, int cls, int mode, int v, const KParams
   const int pv = mode == kModeMacros ? 0 : v;  // the read-out uses the first tile shape
   return launch_batch2d<S, T>(b->d_cases, b->d_ids + b->cls_first[cls],
                               b->d_prefix + prefix_at(b, cls, pv), b->cls_count[cls],
-                              b->total[cls][pv], kdev, b->cur, mode, v, b->stream);
+                              b->d_map + 2 * b->map_at[cls][pv], b->total[cls][pv], kdev, b->cur,
+                              mode, v, b->stream);
 }
 
 hipError_t run_class(cplb_batch_t* b, int cls, int mode, int v) {
@@ -198,19 +215,19 @@ int compute_fields(cplb_batch_t* b, int icase) {
   const int tiles = step2d_tiles(b->prm[icase].nx, b->prm[icase].ny, 0);
   switch (b->precision) {
     case CPLB_F64:
-      e = launch_batch2d<double, double>(b->d_cases, ids, pre, 1, tiles, b->d_k64, b->cur,
+      e = launch_batch2d<double, double>(b->d_cases, ids, pre, 1, nullptr, tiles, b->d_k64, b->cur,
                                          kModeMacros, 0, b->stream);
       break;
     case CPLB_F32:
-      e = launch_batch2d<float, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+      e = launch_batch2d<float, float>(b->d_cases, ids, pre, 1, nullptr, tiles, b->d_k32, b->cur,
                                        kModeMacros, 0, b->stream);
       break;
     case CPLB_F32_S16F:
-      e = launch_batch2d<__half, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+      e = launch_batch2d<__half, float>(b->d_cases, ids, pre, 1, nullptr, tiles, b->d_k32, b->cur,
                                         kModeMacros, 0, b->stream);
       break;
     default:
-      e = launch_batch2d<__hip_bfloat16, float>(b->d_cases, ids, pre, 1, tiles, b->d_k32, b->cur,
+      e = launch_batch2d<__hip_bfloat16, float>(b->d_cases, ids, pre, 1, nullptr, tiles, b->d_k32, b->cur,
                                                 kModeMacros, 0, b->stream);
   }
   return hip_check(b, e, "batch macros kernel");
@@ -284,6 +301,7 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
     D.fields = b->ws + L.reg[c].fields;
     D.nx = prm[c].nx;
     D.ny = prm[c].ny;
+    D.px = G.px;
     D.wall_x = prm[c].periodic[0] ? 0 : 1;
     D.wall_y = prm[c].periodic[1] ? 0 : 1;
     D.sS = (unsigned)(G.stride * G.s_pop);
@@ -296,6 +314,7 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
   }
   // cases grouped by class, and every class's tile prefix for every variant
   b->ids.clear();
+  b->map.clear();
   b->prefix.assign((size_t)kBatchClasses * kVariants2D * (ncases + 1), 0);
   for (int cls = 0; cls < kBatchClasses; ++cls) {
     b->cls_first[cls] = (int)b->ids.size();
@@ -317,6 +336,16 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
       }
       p[b->cls_count[cls]] = (int)acc;
       b->total[cls][v] = (int)acc;
+      // the tile map: global tile g of this class and variant -> (case, tile)
+      b->map_at[cls][v] = (long long)b->map.size() / 2;
+      for (int k = 0; k < b->cls_count[cls]; ++k) {
+        const int c = b->ids[b->cls_first[cls] + k];
+        const int tiles = step2d_tiles(prm[c].nx, prm[c].ny, v);
+        for (int t = 0; t < tiles; ++t) {
+          b->map.push_back(c);
+          b->map.push_back(t);
+        }
+      }
     }
   }
   b->iota.resize(ncases);
@@ -334,6 +363,7 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
   b->d_prefix = (int*)(b->ws + L.prefix);
   b->d_iota = (int*)(b->ws + L.iota);
   b->d_single = (int*)(b->ws + L.single);
+  b->d_map = (int*)(b->ws + L.map);
   b->cur = 0;
   b->step = 0;
   struct Up {
@@ -346,7 +376,8 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
              {b->d_ids, b->ids.data(), ncases * sizeof(int)},
              {b->d_prefix, b->prefix.data(), b->prefix.size() * sizeof(int)},
              {b->d_iota, b->iota.data(), ncases * sizeof(int)},
-             {b->d_single, b->single.data(), 2 * (size_t)ncases * sizeof(int)}};
+             {b->d_single, b->single.data(), 2 * (size_t)ncases * sizeof(int)},
+             {b->d_map, b->map.data(), b->map.size() * sizeof(int)}};
   for (const Up& u : ups) {
     rc = hip_check(b, hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, b->stream),
                    "upload of batch tables");
@@ -423,8 +454,10 @@ int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes
     const float* base = dev_planes + D.out_off * nplanes;
     const int which[3] = {iphi, ic1, ic2};
     for (int k = 0; k < 3; ++k) {
+      // compact planes -> compact FP64 staging (row pitch = nx: no padding)
       const int rc = hip_check(b, launch_convert<float>(base + (size_t)which[k] * G.n, stage + k * G.n,
-                                                        CPLB_DTYPE_F64, G.n, b->stream),
+                                                        CPLB_DTYPE_F64, G.n, b->prm[c].nx,
+                                                        b->prm[c].nx, b->stream),
                                "init staging");
       if (rc) return rc;
     }
@@ -484,8 +517,10 @@ int cplb_batch_read_field(cplb_batch_t* b, int icase, int field, void* dev_dst, 
   const Geometry& G = b->G[icase];
   const char* f = (const char*)b->cases[icase].fields + (size_t)field * G.stride * G.s_cmp;
   hipError_t e = G.s_cmp == 8
-                     ? launch_convert<double>((const double*)f, dev_dst, dtype, G.n, b->stream)
-                     : launch_convert<float>((const float*)f, dev_dst, dtype, G.n, b->stream);
+                     ? launch_convert<double>((const double*)f, dev_dst, dtype, G.n, b->prm[icase].nx,
+                                              G.px, b->stream)
+                     : launch_convert<float>((const float*)f, dev_dst, dtype, G.n, b->prm[icase].nx,
+                                             G.px, b->stream);
   return hip_check(b, e, "field conversion");
 }
 
@@ -500,9 +535,11 @@ int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]) {
   const cplb_params& p = b->prm[icase];
   hipError_t e = G.s_cmp == 8
                      ? launch_reduce<double>((const double*)b->cases[icase].fields, G.stride, G.n,
-                                             p.rho1, p.rho2, b->partials, nparts, dout, b->stream)
+                                             p.nx, G.px, p.rho1, p.rho2, b->partials, nparts, dout,
+                                             b->stream)
                      : launch_reduce<float>((const float*)b->cases[icase].fields, G.stride, G.n,
-                                            p.rho1, p.rho2, b->partials, nparts, dout, b->stream);
+                                            p.nx, G.px, p.rho1, p.rho2, b->partials, nparts, dout,
+                                            b->stream);
   rc = hip_check(b, e, "reduction kernels");
   if (rc) return rc;
   double tmp[8];

@@ -19,23 +19,33 @@ using CPtr = const __attribute__((address_space(4))) X*;
 
 template <class S, class T, int TX, int TY, bool NTS, int MODE>
 __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, CPtr<int> ids,
-                                                         CPtr<int> prefix, int ncls, int total,
-                                                         KPtr<T> kps, int parity) {
+                                                         CPtr<int> prefix, int ncls,
+                                                         CPtr<int> map, int total, KPtr<T> kps,
+                                                         int parity) {
   const int per = (total + 7) / 8;
   const int g = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (g >= total) return;
-  // last k with prefix[k] <= g
-  int lo = 0, hi = ncls;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= g) lo = mid;
-    else hi = mid;
+  int c, tile;
+  if (map) {
+    // (case, tile of the case): one pair of scalar loads
+    c = map[2 * g];
+    tile = map[2 * g + 1];
+  } else {
+    // last k with prefix[k] <= g
+    int lo = 0, hi = ncls;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (prefix[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    c = ids[lo];
+    tile = g - prefix[lo];
   }
-  const int c = ids[lo];
   CPtr<BatchCase> D = cases + c;
   Geo2<uint32_t> G;
   G.nx = D->nx;
   G.ny = D->ny;
+  G.px = D->px;
   G.wall_x = D->wall_x;
   G.wall_y = D->wall_y;
   G.tiles_x = (G.nx + TX - 1) / TX;
@@ -47,16 +57,17 @@ __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, 
   S* dst = (S*)D->lat[parity ^ 1];
   const KParams<T>& P = *(const KParams<T>*)(kps + c);
   step2d_tile<S, T, TX, TY, NTS, MODE, uint32_t>(src, dst, (T*)D->hist, (T*)D->fields, P, G,
-                                                 g - prefix[lo]);
+                                                 tile);
 }
 
 template <class S, class T, int TX, int TY, bool NTS, int MODE>
-hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, int ncls, int total,
-                    const KParams<T>* kps, int parity, hipStream_t stream) {
+hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
+                    const int* map, int total, const KParams<T>* kps, int parity,
+                    hipStream_t stream) {
   const int nblocks = ((total + 7) / 8) * 8;
   hipLaunchKernelGGL((batch2d_kernel<S, T, TX, TY, NTS, MODE>), dim3(nblocks), dim3(TX * TY), 0,
-                     stream, (CPtr<BatchCase>)cases, (CPtr<int>)ids, (CPtr<int>)prefix, ncls, total,
-                     (KPtr<T>)kps, parity);
+                     stream, (CPtr<BatchCase>)cases, (CPtr<int>)ids, (CPtr<int>)prefix, ncls,
+                     (CPtr<int>)map, total, (KPtr<T>)kps, parity);
   return hipGetLastError();
 }
 
@@ -72,22 +83,22 @@ int step2d_tiles(int nx, int ny, int variant) {
 
 template <class S, class T>
 hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
-                          int total, const KParams<T>* kps, int parity, int mode, int variant,
-                          hipStream_t stream) {
+                          const int* map, int total, const KParams<T>* kps, int parity, int mode,
+                          int variant, hipStream_t stream) {
   if (total <= 0) return hipSuccess;
   constexpr int M = kModeStep;
   if (mode == kModeMacros)
-    return launch_b<S, T, 64, 4, false, kModeMacros>(cases, ids, prefix, ncls, total, kps, parity,
-                                                     stream);
+    return launch_b<S, T, 64, 4, false, kModeMacros>(cases, ids, prefix, ncls, map, total, kps,
+                                                     parity, stream);
   switch (variant) {
-    case 1: return launch_b<S, T, 32, 8, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 2: return launch_b<S, T, 32, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 3: return launch_b<S, T, 128, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 4: return launch_b<S, T, 64, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 5: return launch_b<S, T, 32, 8, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 6: return launch_b<S, T, 32, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    case 7: return launch_b<S, T, 128, 4, true, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
-    default: return launch_b<S, T, 64, 4, false, M>(cases, ids, prefix, ncls, total, kps, parity, stream);
+    case 1: return launch_b<S, T, 32, 8, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 2: return launch_b<S, T, 32, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 3: return launch_b<S, T, 128, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 4: return launch_b<S, T, 64, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 5: return launch_b<S, T, 32, 8, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 6: return launch_b<S, T, 32, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 7: return launch_b<S, T, 128, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    default: return launch_b<S, T, 64, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
   }
 }
 
@@ -106,7 +117,7 @@ __global__ void gather_kernel(CPtr<BatchCase> cases, GatherIds ids, int nplanes,
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T* src = (const T*)((const char*)D->fields + (size_t)ids.id[f] * D->sT);
-  dst[D->out_off * nplanes + f * n + i] = (float)src[i];
+  dst[D->out_off * nplanes + f * n + i] = (float)src[pitched(i, D->nx, D->px)];
 }
 
 // Fields that need only the node's own moments (phi, c1, c2, psi): f, h1,
@@ -126,7 +137,8 @@ __global__ void gather_moments_kernel(CPtr<BatchCase> cases, KPtr<T> kps, int pa
   if (i >= n) return;
   const KParams<T>& P = *(const KParams<T>*)(kps + c);
   const S* lat = (const S*)D->lat[parity];
-  const uint32_t sS = D->sS, node = uint32_t(i) * uint32_t(sizeof(S));
+  const uint32_t sS = D->sS;
+  const uint32_t node = uint32_t(pitched(i, D->nx, D->px)) * uint32_t(sizeof(S));
   T f[9], h1[9], h2[9];
   load_q<L, false, false>(at(lat, uint32_t(Lay::F0) * sS), sS, node, f);
   load_q<L, false, false>(at(lat, uint32_t(Lay::H10) * sS), sS, node, h1);
@@ -183,8 +195,9 @@ template hipError_t launch_batch_gather<float>(const BatchCase*, int, long long,
                                                int, int, float*, hipStream_t);
 
 #define PFLB_BATCH_INST(S, T)                                                                    \
-  template hipError_t launch_batch2d<S, T>(const BatchCase*, const int*, const int*, int, int,   \
-                                           const KParams<T>*, int, int, int, hipStream_t);
+  template hipError_t launch_batch2d<S, T>(const BatchCase*, const int*, const int*, int,        \
+                                           const int*, int, const KParams<T>*, int, int, int,      \
+                                           hipStream_t);
 PFLB_BATCH_INST(double, double)
 PFLB_BATCH_INST(float, float)
 PFLB_BATCH_INST(__half, float)

@@ -30,6 +30,7 @@ namespace pflb {
 template <class T>
 struct KParams {
   int nx, ny, nz;
+  int px;             // row pitch of the planes (nodes)
   int wall[3];        // 1: half-way bounce-back walls on both faces of the axis
   long long stride;   // elements between two population / field planes
   // relaxation of the constant-tau sets as delta = 2 - 1/tau = 2 (tau - 1/2)/tau

@@ -20,6 +20,14 @@ constexpr int kModelTwoLocal = 3;  // the two-scalar model, grad psi by Eq. (39)
 constexpr int kFieldPhi = 0, kFieldP = 1, kFieldUx = 2, kFieldUy = 3, kFieldUz = 4, kFieldC1 = 5,
               kFieldC2 = 6, kFieldMu = 7, kFieldPsi = 8, kNumFields = 9;
 
+// Rows of every plane are px >= nx nodes apart (the row pitch; packed,
+// px = nx, by measurement); compact index i (x fastest, nx per row) -> index
+// in a plane.
+__host__ __device__ inline long long pitched(long long i, int nx, int px) {
+  const long long r = i / nx;
+  return r * px + (i - r * nx);
+}
+
 // history planes: u (d of them, stored as 3), phi, c1, c2 of the previous step
 constexpr int kHist2D = 5;  // ux, uy, phi, c1, c2
 constexpr int kHist3D = 6;  // ux, uy, uz, phi, c1, c2
@@ -51,6 +59,7 @@ struct BatchCase {
   void* hist;          // history planes
   void* fields;        // field planes
   int nx, ny;
+  int px;              // row pitch (nodes between two rows of a plane)
   int wall_x, wall_y;  // 1: half-way bounce-back walls on both faces
   unsigned int sS;     // bytes between two population planes
   unsigned int sT;     // bytes between two history / field planes
@@ -61,12 +70,14 @@ struct BatchCase {
 // One step (or the field read-out in kModeMacros) of every case of one size
 // class in a single launch: ids[0..ncls) are the class's case ids and
 // prefix[0..ncls] the first tile of each in the class's tile list for
-// `variant` (prefix[ncls] = total tiles); kps[c] are the constants of case
-// c.  The tile shapes are those of the 2-D step variants.
+// `variant` (prefix[ncls] = total tiles); map (or null) holds (case, tile
+// of the case) for every tile of that list, which spares each work-group
+// the search over prefix; kps[c] are the constants of case c.  The tile
+// shapes are those of the 2-D step variants.
 template <class S, class T>
 hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
-                          int total_tiles, const KParams<T>* kps, int parity, int mode,
-                          int variant, hipStream_t stream);
+                          const int* map, int total_tiles, const KParams<T>* kps, int parity,
+                          int mode, int variant, hipStream_t stream);
 
 // tiles of an nx x ny lattice for a 2-D step variant
 int step2d_tiles(int nx, int ny, int variant);
@@ -123,11 +134,13 @@ hipError_t launch_init(int dim, S* lat, T* hist, const double* phi_or_l, const d
 
 // convert one field plane to FP32 / FP64
 template <class T>
-hipError_t launch_convert(const T* src, void* dst, int dtype, long long n, hipStream_t stream);
+hipError_t launch_convert(const T* src, void* dst, int dtype, long long n, int nx, int px,
+                          hipStream_t stream);
 
 // deterministic two-stage FP64 reduction of the field buffer into out[0..6]
 template <class T>
-hipError_t launch_reduce(const T* fields, long long stride, long long n, double rho1, double rho2,
+hipError_t launch_reduce(const T* fields, long long stride, long long n, int nx, int px,
+                         double rho1, double rho2,
                          double* partials, int nparts, double* out, hipStream_t stream);
 
 constexpr int kReduceBlocks = 1024;

@@ -50,6 +50,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   Geo2<Off> G;
   G.nx = P.nx;
   G.ny = P.ny;
+  G.px = P.px;
   G.wall_x = P.wall[0];
   G.wall_y = P.wall[1];
   G.tiles_x = (P.nx + TX - 1) / TX;

@@ -21,6 +21,7 @@ namespace pflb {
 template <class Off>
 struct Geo2 {
   int nx, ny;
+  int px;  // row pitch (nodes)
   int wall_x, wall_y;
   int tiles_x, ntiles;
   Off sS;  // bytes between two population planes
@@ -66,7 +67,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   // a ragged tile: the slot one past the last node is read by that node's
   // stencil, so its thread fills it with the wrapped or mirrored node
   const bool own_slot = x <= nx && y <= ny;
-  const Off node = Off(fold(y, ny, G.wall_y) * nx + fold(x, nx, G.wall_x)) * BS;
+  const Off node = Off(fold(y, ny, G.wall_y) * G.px + fold(x, nx, G.wall_x)) * BS;
   const Off nodeT = node * Off(sizeof(T) / sizeof(S));  // bytes, history / fields
 
   int hx = 0, hy = 0;
@@ -76,7 +77,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
     halo_pos<TX, TY>(tid, hx, hy);
     const int gx = x0 + hx, gy = y0 + hy;
     halo = gx <= nx && gy <= ny;  // beyond a ragged tile no node reads it
-    halo_node = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
+    halo_node = Off(fold(gy, ny, G.wall_y) * G.px + fold(gx, nx, G.wall_x)) * BS;
   }
 
   // ---- 1. all global loads first
@@ -183,7 +184,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   // push streaming: X_i(x + c_i) <- X_i*(x), or half-way bounce-back into
   // the opposite slot of the own node when the link crosses a wall; each
   // post-collision value is stored as soon as it is formed
-  const PushXY<Off> push(x, y, nx, ny, G.wall_x, G.wall_y, BS);
+  const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
   auto target = [&](int i) -> Off {
     const int cx = L::cx[i], cy = L::cy[i];
     Off t = node;

@@ -49,12 +49,13 @@ using Lay = Layout<D3Q7, D3Q19>;
 template <class Off>
 struct Geo3 {
   int nx, ny, nz;
+  int px;   // row pitch (nodes)
   int wall_x, wall_y, wall_z;
   int tiles_x, tiles_xy, ntiles;
   int nchunks;  // z chunks per column tile
   Off sS;   // bytes between two population planes
   Off sT;   // bytes between two history / field planes
-  Off nxy;  // bytes between two z-planes of a population plane (nx ny sizeof(S))
+  Off nxy;  // bytes between two z-planes of a population plane (px ny sizeof(S))
 };
 
 __device__ inline int slot_of(int z) { return (z + 4) & 3; }
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const int x = x0 + tx, y = y0 + ty;
   const bool active = x < nx && y < ny;
   const bool own_slot = x <= nx && y <= ny;  // ragged tile: fill the slot past the end
-  const Off own_col = Off(fold(y, ny, G.wall_y) * nx + fold(x, nx, G.wall_x)) * BS;
+  const Off own_col = Off(fold(y, ny, G.wall_y) * G.px + fold(x, nx, G.wall_x)) * BS;
 
   int hx = 0, hy = 0;
   bool halo = false;
@@ -111,10 +112,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     halo_pos<TX, TY>(tid, hx, hy);
     const int gx = x0 + hx, gy = y0 + hy;
     halo = gx <= nx && gy <= ny;
-    halo_col = Off(fold(gy, ny, G.wall_y) * nx + fold(gx, nx, G.wall_x)) * BS;
+    halo_col = Off(fold(gy, ny, G.wall_y) * G.px + fold(gx, nx, G.wall_x)) * BS;
   }
 
-  const PushXY<Off> push(x, y, nx, ny, G.wall_x, G.wall_y, BS);
+  const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
 
   // moments of plane zp for the own slot and the halo slot of the ring
   auto put = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7], const T (&h2)[7],
@@ -383,6 +384,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.nx = P.nx;
   G.ny = P.ny;
   G.nz = P.nz;
+  G.px = P.px;
   G.wall_x = P.wall[0];
   G.wall_y = P.wall[1];
   G.wall_z = P.wall[2];
@@ -393,7 +395,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.ntiles = G.tiles_xy * G.nchunks;
   G.sS = Off(P.stride * (long long)sizeof(S));
   G.sT = Off(P.stride * (long long)sizeof(T));
-  G.nxy = Off((long long)P.nx * P.ny * (long long)sizeof(S));
+  G.nxy = Off((long long)P.px * P.ny * (long long)sizeof(S));
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
   hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(TX * TY), 0, stream, src, dst, hist, fields,
                      (KPtr<T>)Pdev, G);

@@ -75,7 +75,7 @@ def test_batch_cases_equal_single_lattices_bitwise(cplb, precision):
     cases = mixed_cases(precision)
     say(f"batch of {len(cases)} mixed cases, {precision}, 25 steps")
     b = make_batch(cplb, cases)
-    assert [n for n, _ in b.classes()] == [3, 3, 1]
+    assert [n for n, _ in b.classes()] == [2, 1, 2, 1, 1]
     b.step(25)
     assert b.step_count == 25
     for k, c in enumerate(cases):
