@@ -73,11 +73,8 @@ int default_variant(const cplb_params* p) {
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
     return p->scalar_grad == CPLB_GRAD_LOCAL && lattice_bytes > 256e6 ? 7 : 3;
   }
-  // 3-D, 16-bit storage: central stencil 64x4 with f / h re-read before their
-  // collision and non-temporal g loads and stores; local gradient scheme
-  // (fewer registers) 64x4 carried, non-temporal stores
-  if (p->precision >= CPLB_F32_S16F) return p->scalar_grad == CPLB_GRAD_LOCAL ? 4 : 6;
-  // FP32 / FP64: 64x4 carried, non-temporal stores
+  // 3-D, every precision and gradient scheme: 64x4 with f, h1, h2 carried in
+  // registers from the previous plane, non-temporal stores
   return 4;
 }
 

@@ -76,7 +76,8 @@ struct Codec<float, float> {
 
 template <>
 struct Codec<__half, float> {
-  __device__ static float ld(__half s, float w) { return w * __half2float(s); }
+  // w x as one fma with the FP16 operand read in place (v_fma_mix_f32)
+  __device__ static float ld(__half s, float w) { return __builtin_fmaf(w, __half2float(s), 0.0f); }
   __device__ static __half st(float x, float inv_w) { return __float2half_rn(x * inv_w); }
 };
 
@@ -88,10 +89,18 @@ struct Codec<__hip_bfloat16, float> {
 
 // --------------------------------------------------------------- helpers
 
+// Quotient, reciprocal square root and exponential of the per-node formulas.
+// FP64 keeps the correctly rounded forms.  In FP32 they are the hardware's
+// one-ulp instructions (v_rcp_f32, v_rsq_f32, v_exp_f32 of x log2 e): a
+// correctly rounded FP32 division expands into 12 instructions and expf
+// into 17, and the step with 16-bit storage is bound by instruction issue
+// about as much as by HBM.
+__device__ inline double div_t(double a, double b) { return a / b; }
+__device__ inline float div_t(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ inline double rsqrt_t(double x) { return 1.0 / sqrt(x); }
-__device__ inline float rsqrt_t(float x) { return 1.0f / sqrtf(x); }
+__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double exp_t(double x) { return exp(x); }
-__device__ inline float exp_t(float x) { return expf(x); }
+__device__ inline float exp_t(float x) { return __expf(x); }
 
 template <class T>
 __device__ inline bool finite_t(T x) {
@@ -146,11 +155,11 @@ __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const 
   s.dphi = s0;
   s.phi = P.ref_phi + s0;
   s.omphi = P.one_minus_ref_phi - s0;
-  s.Dm = P.D1D2 / (P.KD1 * s.omphi + P.D2 * s.phi);
+  s.Dm = div_t(P.D1D2, P.KD1 * s.omphi + P.D2 * s.phi);
   const T a = P.half_A * s.Dm;
   const T S1 = P.ref_c1 + s1, S2 = P.ref_c2 + s2;
   const T Kphi = P.Keq * s.phi;
-  const T e = (Kphi * S2 - s.omphi * S1) / (T(1) + a * (Kphi + s.omphi));
+  const T e = div_t(Kphi * S2 - s.omphi * S1, T(1) + a * (Kphi + s.omphi));
   s.dc1 = s1 + a * e;
   s.dc2 = s2 - a * e;
   s.c1 = P.ref_c1 + s.dc1;
@@ -175,7 +184,7 @@ __device__ inline void moments_one(const KParams<T>& P, const T (&df)[LF::Q],
   s.omphi = P.one_minus_ref_phi - s0;
   s.dc = s1;
   s.c = P.ref_c1 + s1;
-  s.ct = s.c / (P.Keq * s.phi + s.omphi);
+  s.ct = div_t(s.c, P.Keq * s.phi + s.omphi);
   s.c1 = P.Keq * s.phi * s.ct;
   s.c2 = s.omphi * s.ct;
   s.dc1 = s.c1 - P.ref_c1;
@@ -195,6 +204,7 @@ struct Flow {
   T F[3];
   T pi;     // bracket of the pressure formula: p = cs^2 / (1 - w0) * pi
   T p, rho, mu, mu_phi;
+  T inv_rho;  // 1 / rho
 };
 
 template <class LG, class T>
@@ -214,7 +224,8 @@ __device__ inline void flow_macros(const KParams<T>& P, const T (&g)[LG::Q], con
     if (LG::cy[i]) m[1] += T(LG::cy[i]) * g[i];
     if (LG::cz[i]) m[2] += T(LG::cz[i]) * g[i];
   }
-  const T inv_rho = T(1) / fl.rho;
+  const T inv_rho = div_t(T(1), fl.rho);
+  fl.inv_rho = inv_rho;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     fl.F[a] = fl.mu_phi * gphi[a] + buoy * P.grav[a];
@@ -222,7 +233,7 @@ __device__ inline void flow_macros(const KParams<T>& P, const T (&g)[LG::Q], con
   }
   const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
   const T udg = fl.u[0] * gphi[0] + fl.u[1] * gphi[1] + fl.u[2] * gphi[2];
-  const T s0 = T(LG::w[0]) * (-uu / (T(2) * cs2));
+  const T s0 = T(LG::w[0]) * (-uu * T(0.5 / LG::cs2));
   fl.pi = sg + T(0.5) * P.drho * udg + fl.rho * s0;
   fl.p = T(cs2 / (1.0 - LG::w[0])) * fl.pi;
   if (P.visc_exp)
@@ -331,9 +342,9 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
                                  const Flow<T>& fl, Emit&& emit) {
   constexpr T inv_csg = T(1.0 / LG::cs2);
   constexpr T half_inv_csg2 = T(0.5 / (LG::cs2 * LG::cs2));
-  const T nu = fl.mu * inv_csg / fl.rho;  // tau_g - 1/2
+  const T nu = fl.mu * inv_csg * fl.inv_rho;  // tau_g - 1/2
   const T tau_g = T(0.5) + nu;
-  const T del_g = T(2) * nu / tau_g;
+  const T del_g = div_t(T(2) * nu, tau_g);
   const T hdel_g = T(0.5) * del_g;
   const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
   const T iso = uu * T(0.5) * inv_csg;
@@ -407,7 +418,7 @@ template <class LF, class T, class Emit>
 __device__ inline void collide_h3(const KParams<T>& P, const T (&dh3)[LF::Q], const Node<T>& s,
                                   const Flow<T>& fl, const T (&dJ)[3], Emit&& emit) {
   const T nu = s.Dm * T(1.0 / LF::cs2);  // tau_h3 - 1/2
-  const T del = T(2) * nu / (T(0.5) + nu);
+  const T del = div_t(T(2) * nu, T(0.5) + nu);
   const T hdel = T(0.5) * del;
   const T dct = s.ct - P.ref_c1;
   auto eq = [&](int i) {

@@ -103,7 +103,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const int x = x0 + tx, y = y0 + ty;
   const bool active = x < nx && y < ny;
   const bool own_slot = x <= nx && y <= ny;  // ragged tile: fill the slot past the end
-  const Off own_col = Off(fold(y, ny, G.wall_y) * G.px + fold(x, nx, G.wall_x)) * BS;
+  // Every lane loads its own column, lanes past the slot that of node 0 (its
+  // values are not used): unconditional loads, so the compiler need not
+  // zero their registers for a skipped branch.
+  const Off own_col =
+      own_slot ? Off(fold(y, ny, G.wall_y) * G.px + fold(x, nx, G.wall_x)) * BS : Off(0);
 
   int hx = 0, hy = 0;
   bool halo = false;
@@ -117,40 +121,42 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
   const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
 
-  // moments of plane zp for the own slot and the halo slot of the ring
-  auto put = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7], const T (&h2)[7],
-                 Node<T>& s, const T (&hf)[7], const T (&hh1)[7], const T (&hh2)[7]) {
-    const int sl = slot_of(zp);
-    if (own_slot) {
-      moments<LF>(P, f, h1, h2, s);
-      R.phi[sl][ty + 1][tx + 1] = s.dphi;
-      if (!LOC) R.psi[sl][ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
-    }
-    if (halo) {
-      if constexpr (LOC) {
-        T d = hf[0];
-#pragma unroll
-        for (int i = 1; i < 7; ++i) d += hf[i];
-        R.phi[sl][hy + 1][hx + 1] = d;
-      } else {
-        Node<T> q;
-        moments<LF>(P, hf, hh1, hh2, q);
-        R.phi[sl][hy + 1][hx + 1] = q.dphi;
-        R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
-      }
-    }
-  };
   auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
     load_q<LF, NTL, true>(sF, G.sS, node, f);
     load_q<LF, NTL, true>(sH1, G.sS, node, h1);
     load_q<LF, NTL, true>(sH2, G.sS, node, h2);
   };
-  // the halo needs h1, h2 only for the psi stencil
-  auto load_halo = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
-    if constexpr (LOC)
-      load_q<LF, NTL, true>(sF, G.sS, node, f);
-    else
-      load_fh(node, f, h1, h2);
+  // moments of plane zp of the own node into the ring
+  auto put_own = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7],
+                     const T (&h2)[7], Node<T>& s) {
+    moments<LF>(P, f, h1, h2, s);
+    if (own_slot) {
+      const int sl = slot_of(zp);
+      R.phi[sl][ty + 1][tx + 1] = s.dphi;
+      if (!LOC) R.psi[sl][ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+    }
+  };
+  // load plane zp of the lane's halo node and put its moments in the ring,
+  // in one conditional block (the halo needs h1, h2 only for the psi stencil)
+  auto halo_plane = [&](const KParams<T>& P, int zp, Off pbase) {
+    if (!halo) return;
+    const int sl = slot_of(zp);
+    T hf[7];
+    load_q<LF, NTL, true>(sF, G.sS, pbase + halo_col, hf);
+    if constexpr (LOC) {
+      T d = hf[0];
+#pragma unroll
+      for (int i = 1; i < 7; ++i) d += hf[i];
+      R.phi[sl][hy + 1][hx + 1] = d;
+    } else {
+      T hh1[7], hh2[7];
+      load_q<LF, NTL, true>(sH1, G.sS, pbase + halo_col, hh1);
+      load_q<LF, NTL, true>(sH2, G.sS, pbase + halo_col, hh2);
+      Node<T> q;
+      moments<LF>(P, hf, hh1, hh2, q);
+      R.phi[sl][hy + 1][hx + 1] = q.dphi;
+      R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+    }
   };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
@@ -158,16 +164,16 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   {
     // prologue: planes z0-1 and z0
     const KParams<T>& P = params(Pg);
-    T af[7], ah1[7], ah2[7], hf[7], hh1[7], hh2[7];
+    T af[7], ah1[7], ah2[7];
     const Off pm = Off(fold(z0 - 1, nz, G.wall_z)) * G.nxy;
     const Off p0 = Off(z0) * G.nxy;
-    if (own_slot) load_fh(pm + own_col, af, ah1, ah2);
-    if (halo) load_halo(pm + halo_col, hf, hh1, hh2);
+    load_fh(pm + own_col, af, ah1, ah2);
+    halo_plane(P, z0 - 1, pm);
     Node<T> tmp;
-    put(P, z0 - 1, af, ah1, ah2, tmp, hf, hh1, hh2);
-    if (own_slot) load_fh(p0 + own_col, f, h1, h2);
-    if (halo) load_halo(p0 + halo_col, hf, hh1, hh2);
-    put(P, z0, f, h1, h2, s, hf, hh1, hh2);
+    put_own(P, z0 - 1, af, ah1, ah2, tmp);
+    load_fh(p0 + own_col, f, h1, h2);
+    halo_plane(P, z0, p0);
+    put_own(P, z0, f, h1, h2, s);
   }
   // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits: the
   // same lines were read for the moments one plane earlier) right before
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const Off nodeT = node * Off(sizeof(T) / sizeof(S));   // bytes, history / fields
     const Off pn = Off(fold(z + 1, nz, G.wall_z)) * G.nxy;
     // ---- 1. global loads of this plane
-    T g[19], hs[kHist3D], nf[7], nh1[7], nh2[7], hf[7], hh1[7], hh2[7];
+    T g[19], hs[kHist3D], nf[7], nh1[7], nh2[7];
     auto load_g = [&] {
 #pragma unroll
       for (int i = 0; i < 19; ++i)
@@ -192,11 +198,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane<true>(k, G.sT) + nodeT);
     };
     if (PREF && active) load_g();
-    if (own_slot) load_fh(pn + own_col, nf, nh1, nh2);
-    if (halo) load_halo(pn + halo_col, hf, hh1, hh2);
+    load_fh(pn + own_col, nf, nh1, nh2);
     // ---- 2. moments of plane z+1 into the ring
-    Node<T> ns{};
-    put(P, z + 1, nf, nh1, nh2, ns, hf, hh1, hh2);
+    halo_plane(P, z + 1, pn);
+    Node<T> ns;
+    put_own(P, z + 1, nf, nh1, nh2, ns);
     __syncthreads();
     // ---- 3. collide plane z
     if (active) {
