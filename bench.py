@@ -33,22 +33,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44451061, "write": 43033627,
-                                  "src": "c7e76c4e09ce25c6"},
-    "rising_droplet_256c_f32": {"read": 3434632168, "write": 3124257328,
-                               "src": "c7e76c4e09ce25c6"},
-    "rising_droplet_256c_f32_s16f": {"read": 2292812911, "write": 1772127712,
-                                    "src": "c7e76c4e09ce25c6"},
-    "rising_bubble_2048x4096_f32": {"read": 1479781648, "write": 1376907000,
-                                   "src": "c7e76c4e09ce25c6"},
-    "rising_bubble_one_256x1024_f32": {"read": 32782196, "write": 32516141,
-                                      "src": "c7e76c4e09ce25c6"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1768943102, "write": 1379153477,
-                                         "src": "c7e76c4e09ce25c6"},
-    "rising_droplet_local_256c_f32": {"read": 3339978729, "write": 3122301877,
-                                     "src": "c7e76c4e09ce25c6"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1760774334, "write": 1773808149,
-                                          "src": "c7e76c4e09ce25c6"},
+    "rising_bubble_256x1024_f32": {"read": 44599977, "write": 43034733,
+                                  "src": "8cc3404cd809ccc1"},
+    "rising_droplet_256c_f32": {"read": 3233814205, "write": 3120747157,
+                               "src": "8cc3404cd809ccc1"},
+    "rising_droplet_256c_f32_s16f": {"read": 1787570653, "write": 1775671707,
+                                    "src": "8cc3404cd809ccc1"},
+    "rising_bubble_2048x4096_f32": {"read": 1484365255, "write": 1376878891,
+                                   "src": "8cc3404cd809ccc1"},
+    "rising_bubble_one_256x1024_f32": {"read": 32772997, "write": 32530041,
+                                      "src": "8cc3404cd809ccc1"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1767063515, "write": 1379164656,
+                                         "src": "8cc3404cd809ccc1"},
+    "rising_droplet_local_256c_f32": {"read": 3266934125, "write": 3120274309,
+                                     "src": "8cc3404cd809ccc1"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1781633374, "write": 1775368576,
+                                          "src": "8cc3404cd809ccc1"},
 }
 
 
