@@ -54,6 +54,65 @@ enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2, kInfAct = 3, kInfOut = 4 };
 // row per wave (4 waves), kConvCols / 16 groups of 16 pixels per wave.
 constexpr int kConvRows = 4;
 constexpr int kConvCols = 32;
+// pixel tiles per work-group of the weight gradient (one partial each)
+constexpr int kWgradTiles = 2;
+
+// LDS staging of the convolution tiles.  Each thread issues all of its
+// global loads before its LDS stores (fixed trip counts, unrolled), so a
+// tile's loads are in flight together instead of one round trip per slot.
+//
+// stage_rows: rows R0-1 .. R0+kConvRows and columns x0-1 .. x0+kConvCols of
+// an NHWC BF16 tensor of C channels (pixel stride PS in LDS), wrapped in x;
+// columns past x = W and rows outside [0, rows) are zero.
+template <int C, int PS>
+__device__ inline void stage_rows(const unsigned short* __restrict__ X, unsigned short* sx, int R0,
+                                  int x0, int W, int rows) {
+  typedef unsigned long long u64;
+  constexpr int LC = kConvCols + 2, LR = kConvRows + 2, N = LR * LC * (C / 4);
+  constexpr int IT = (N + 255) / 256;
+  u64 v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int c4 = e % (C / 4), pix = e / (C / 4);
+    const int lr = pix / LC, lc = pix % LC;
+    const int Rg = R0 + lr - 1;
+    int xs = x0 + lc - 1;
+    v[it] = 0;
+    if (e < N && Rg >= 0 && Rg < rows && xs <= W) {
+      xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+      v[it] = *(const u64*)(X + ((long long)Rg * W + xs) * C + c4 * 4);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    if (e < N) *(u64*)(sx + (e / (C / 4)) * PS + (e % (C / 4)) * 4) = v[it];
+  }
+}
+
+// stage_matrix: NR rows of NC BF16 values (NC % 4 == 0, row i starts at
+// src + i * src_stride) into LDS rows of stride LS; rows with valid(i) false
+// are zero.
+template <int NR, int NC, int LS, class Valid, class Src>
+__device__ inline void stage_matrix(Src src_row, unsigned short* dst, Valid valid) {
+  typedef unsigned long long u64;
+  constexpr int N = NR * (NC / 4), IT = (N + 255) / 256;
+  u64 v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int i = e / (NC / 4), c4 = e % (NC / 4);
+    v[it] = 0;
+    if (e < N && valid(i)) v[it] = *(const u64*)(src_row(i) + c4 * 4);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    if (e < N) *(u64*)(dst + (e / (NC / 4)) * LS + (e % (NC / 4)) * 4) = v[it];
+  }
+}
+
 
 // Each block stages its input rows (with a one-pixel halo, periodic in x)
 // and the layer's BF16 weights in LDS once, then every wave runs its row x
@@ -87,24 +146,11 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restr
   const int x0 = (blockIdx.x % tiles_x) * kConvCols;
   const int R0 = (blockIdx.x / tiles_x) * kConvRows;
   // stage the input rows R0-1 .. R0+kConvRows and columns x0-1 .. x0+kConvCols
-  // (wrapped in x; columns past x = W and rows outside the batch are zero;
-  // the zero padding in y between samples is applied per tap below)
-  for (int e = threadIdx.x; e < LR * LC * (CIN / 4); e += 256) {
-    const int c4 = e % (CIN / 4), pix = e / (CIN / 4);
-    const int lr = pix / LC, lc = pix % LC;
-    const int Rg = R0 + lr - 1;
-    int xs = x0 + lc - 1;
-    u64 v = 0;
-    if (Rg >= 0 && Rg < rows && xs <= W) {
-      xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-      v = *(const u64*)(X + ((long long)Rg * W + xs) * CIN + c4 * 4);
-    }
-    *(u64*)(sx + (lr * LC + lc) * PS + c4 * 4) = v;
-  }
-  for (int e = threadIdx.x; e < COUT * (K / 4); e += 256) {
-    const int k4 = e % (K / 4), co = e / (K / 4);
-    *(u64*)(sw + co * KS + k4 * 4) = *(const u64*)(Wg + (long long)co * K + k4 * 4);
-  }
+  // (the zero padding in y between samples is applied per tap below) and the
+  // layer's weights
+  stage_rows<CIN, PS>(X, sx, R0, x0, W, rows);
+  stage_matrix<COUT, K, KS>([&](int co) { return Wg + (long long)co * K; }, sw,
+                            [](int) { return true; });
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -168,114 +214,142 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short* __restr
   }
 }
 
-// Weight and bias gradients, per chunk of pixels:
-//   partial[chunk][co][k] = sum_p dZ[p][co] * X(p shifted by tap(k))[ci(k)],
-//   bpart[chunk][co]      = sum_p dZ[p][co].
-// One wave per 16-wide tile of k = tap * CIN + ci and chunk, all output
-// channels at once (the shifted-X operand is loaded once for every co tile);
-// the pixel sum is the MFMA's K dimension.  Each lane walks its four pixels
-// p = pb + 4 g + j with 32-bit row / column counters instead of dividing.
-// The k tile 0 also sums its dZ operand for the bias.
+// Weight and bias gradients, per work-group of kWgradTiles pixel tiles
+// (kConvRows x kConvCols pixels each, the convolution's tiles):
+//   partial[g][co][k] = sum_p dZ[p][co] * X(p shifted by tap(k))[ci(k)],
+//   bpart[g][co]      = sum_p dZ[p][co],
+// with k = tap * CIN + ci.  Per tile the group stages its input rows with a
+// one-pixel halo (periodic in x, as the convolution) and its dZ rows in LDS;
+// then wave w accumulates the k tiles w, w + 4, ... for all output channels,
+// 16 pixels (one MFMA K step, within one row) at a time: the A operand is
+// dZ transposed, the B operand the shifted input.  A K step whose row has
+// tap's neighbour row outside its sample is skipped (zero padding in y).
+// Pixels past the lattice have dZ = 0 in LDS.  The accumulators stay in
+// registers across the group's tiles.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void wgrad_kernel(const unsigned short* __restrict__ X,
                                                     const unsigned short* __restrict__ dZ,
                                                     float* __restrict__ partial,
                                                     float* __restrict__ bpart, int H, int W,
-                                                    int P, int chunk) {
-  constexpr int K = 9 * CIN, MT = COUT / 16, NTL = K / 16;
-  const int lane = threadIdx.x & 63;
-  const int nt = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (nt >= NTL) return;
-  const int c = blockIdx.y;
+                                                    int rows) {
+  constexpr int K = 9 * CIN, MT = COUT / 16, NTL = K / 16, KPW = (NTL + 3) / 4;
+  constexpr int PS = CIN + 4, DS = COUT + 4;  // LDS pixel strides (BF16 values)
+  constexpr int LC = kConvCols + 2, LR = kConvRows + 2, TP = kConvRows * kConvCols;
+  constexpr int NG = 256 / COUT, GP = TP / NG;  // bias: pixel groups, pixels per group
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && 256 % COUT == 0, "channel counts");
+  __shared__ __align__(16) unsigned short sx[LR * LC * PS];
+  __shared__ __align__(16) unsigned short sdz[TP * DS];
+  __shared__ float sb[256];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
-  const int kk = nt * 16 + m;  // B column of this lane
-  const int tap = kk / CIN, ci = kk % CIN;
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const int p0 = c * chunk;
-  const int p1 = p0 + chunk < P ? p0 + chunk : P;
-  // row R (sample * H + y), column x and y of the lane's pixel p0 + 4 g + j
-  int R[4], xc[4], yc[4];
+  const int tiles_x = (W + kConvCols - 1) / kConvCols;
+  const int ntiles = tiles_x * ((rows + kConvRows - 1) / kConvRows);
+  float4v acc[KPW][MT];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int p = p0 + 4 * g + j;
-    R[j] = p / W;
-    xc[j] = p - R[j] * W;
-    yc[j] = R[j] % H;
-  }
-  float4v acc[MT];
-  float bsum[MT];
+  for (int i = 0; i < KPW; ++i)
 #pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
-    bsum[t] = 0.f;
-  }
-  for (int pb = p0; pb < p1; pb += 16) {
-    short4v a[MT], b;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = pb + 4 * g + j;
-      const bool valid = p < p1;
-      unsigned short bv = 0;
-      if (valid && yc[j] + dy >= 0 && yc[j] + dy < H) {
-        int xs = xc[j] + dx;
-        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-        bv = X[((long long)(R[j] + dy) * W + xs) * CIN + ci];
-      }
-      b[j] = (short)bv;
+    for (int t = 0; t < MT; ++t) acc[i][t] = float4v{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  const int bco = threadIdx.x % COUT, bgrp = threadIdx.x / COUT;
+
+  for (int q = 0; q < kWgradTiles; ++q) {
+    const int tile = blockIdx.x * kWgradTiles + q;
+    if (tile >= ntiles) break;  // uniform over the group
+    const int x0 = (tile % tiles_x) * kConvCols;
+    const int R0 = (tile / tiles_x) * kConvRows;
+    // input rows R0-1 .. R0+kConvRows, columns x0-1 .. x0+kConvCols, and dZ
+    // of the tile's pixels (local pixel r * kConvCols + c)
+    stage_rows<CIN, PS>(X, sx, R0, x0, W, rows);
+    stage_matrix<TP, COUT, DS>(
+        [&](int pix) {
+          return dZ + ((long long)(R0 + pix / kConvCols) * W + x0 + pix % kConvCols) * COUT;
+        },
+        sdz, [&](int pix) { return R0 + pix / kConvCols < rows && x0 + pix % kConvCols < W; });
+    __syncthreads();
+#pragma unroll 4
+    for (int p = bgrp * GP; p < (bgrp + 1) * GP; ++p) bacc += from_bf16(sdz[p * DS + bco]);
+#pragma unroll 1
+    for (int st = 0; st < TP / 16; ++st) {
+      const int r = st / (kConvCols / 16), cb = (st % (kConvCols / 16)) * 16;
+      if (R0 + r >= rows) break;  // uniform; later steps are past the batch too
+      const int y = (R0 + r) % H;
+      const unsigned short* dzp = sdz + (r * kConvCols + cb + 4 * g) * DS;
+      short4v a[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        a[t][j] = (short)(valid ? dZ[(long long)p * COUT + t * 16 + m] : (unsigned short)0);
-      // advance to pixel p + 16
-      xc[j] += 16;
-      while (xc[j] >= W) {
-        xc[j] -= W;
-        ++R[j];
-        if (++yc[j] == H) yc[j] = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[t][j] = (short)dzp[j * DS + t * 16 + m];
+#pragma unroll
+      for (int i = 0; i < KPW; ++i) {
+        const int kt = wave + 4 * i;
+        if (kt >= NTL) break;
+        const int tap = kt * 16 / CIN, ci = kt * 16 % CIN + m;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        if (y + dy < 0 || y + dy >= H) continue;  // uniform
+        const unsigned short* xp = sx + ((r + 1 + dy) * LC + cb + 4 * g + dx + 1) * PS + ci;
+        short4v b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = (short)xp[j * PS];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[i][t] = mfma(a[t], b, acc[i][t]);
       }
     }
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      acc[t] = mfma(a[t], b, acc[t]);
-      if (nt == 0)
-        bsum[t] += (from_bf16((unsigned short)a[t][0]) + from_bf16((unsigned short)a[t][1])) +
-                   (from_bf16((unsigned short)a[t][2]) + from_bf16((unsigned short)a[t][3]));
-    }
+    __syncthreads();
   }
-  // D[co row 4 g + j][k column l % 16]
-  float* out = partial + (long long)c * COUT * K;
+  // D[co row 4 g + j][k column m] of k tile wave + 4 i
+  float* out = partial + (long long)blockIdx.x * COUT * K;
 #pragma unroll
-  for (int t = 0; t < MT; ++t)
+  for (int i = 0; i < KPW; ++i) {
+    const int kt = wave + 4 * i;
+    if (kt >= NTL) break;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) out[(t * 16 + 4 * g + j) * K + nt * 16 + m] = acc[t][j];
-  if (nt == 0) {
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      float v = bsum[t];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
-      if (g == 0) bpart[c * COUT + t * 16 + m] = v;
-    }
+      for (int j = 0; j < 4; ++j) out[(t * 16 + 4 * g + j) * K + kt * 16 + m] = acc[i][t][j];
+  }
+  sb[threadIdx.x] = bacc;
+  __syncthreads();
+  if (threadIdx.x < COUT) {
+    float v = 0.f;
+    for (int k = 0; k < NG; ++k) v += sb[k * COUT + threadIdx.x];
+    bpart[blockIdx.x * COUT + threadIdx.x] = v;
   }
 }
 
-// grad W[co][ci][ky][kx] = sum over chunks of partial[chunk][co][tap * CIN + ci];
-// grad b[co] = sum over chunks of bpart[chunk][co]
-__global__ void wgrad_reduce(const float* __restrict__ partial, const float* __restrict__ bpart,
-                             int nchunks, int cin, int cout, float* __restrict__ gradW,
-                             float* __restrict__ gradb) {
-  const int K = 9 * cin;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // oracle layout index
-  if (i < cout * K) {
-    const int co = i / K, r = i % K, ci = r / 9, tap = r % 9;
-    const long long src = (long long)co * K + tap * cin + ci;
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += partial[(long long)c * cout * K + src];
-    gradW[i] = s;
-  } else if (i < cout * K + cout) {
-    const int co = i - cout * K;
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += bpart[c * cout + co];
-    gradb[co] = s;
+// grad W[co][ci][ky][kx] = sum over parts of partial[part][co][tap * CIN + ci];
+// grad b[co] = sum over parts of bpart[part][co].  A work-group takes 64
+// consecutive partial columns (read coalesced); wave w of its kRedWaves
+// sums the parts w, w + kRedWaves, ... in order and the wave sums are added
+// in wave order.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void wgrad_reduce(const float* __restrict__ partial,
+                                                    const float* __restrict__ bpart, int nparts,
+                                                    int cin, int cout, float* __restrict__ gradW,
+                                                    float* __restrict__ gradb) {
+  __shared__ float red[kRedWaves][64];
+  const int K = 9 * cin, nW = cout * K;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;  // partial column: co * K + tap * cin + ci
+  float s = 0.f;
+  if (col < nW) {
+#pragma unroll 8
+    for (int c = wave; c < nparts; c += kRedWaves) s += partial[(long long)c * nW + col];
+  } else if (col < nW + cout) {
+    for (int c = wave; c < nparts; c += kRedWaves) s += bpart[c * cout + (col - nW)];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && col < nW + cout) {
+    float v = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRedWaves; ++w) v += red[w][lane];
+    if (col < nW) {
+      const int co = col / K, r = col % K, tap = r / cin, ci = r % cin;
+      gradW[(co * cin + ci) * 9 + tap] = v;
+    } else {
+      gradb[col - nW] = v;
+    }
   }
 }
 
@@ -418,22 +492,27 @@ hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned
   return hipGetLastError();
 }
 
+int cnn_wgrad_parts(int W, long long rows) {
+  const long long tiles =
+      (long long)((W + kConvCols - 1) / kConvCols) * ((rows + kConvRows - 1) / kConvRows);
+  return (int)((tiles + kWgradTiles - 1) / kWgradTiles);
+}
+
 hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
-                     float* bpart, int nchunks, int chunk, int H, int W, long long P, float* gradW,
-                     float* gradb, hipStream_t s) {
+                     float* bpart, int H, int W, int rows, float* gradW, float* gradb,
+                     hipStream_t s) {
   const int cin = layer == 0 ? 16 : 32, cout = layer == 3 ? 16 : 32;
-  const int ntiles = 9 * cin / 16;
-  const dim3 grid((ntiles + 3) / 4, nchunks), blk(256);
-  const int Pi = (int)P;
+  const int nparts = cnn_wgrad_parts(W, rows);
+  const dim3 grid(nparts), blk(256);
   switch (layer) {
-    case 0: hipLaunchKernelGGL((wgrad_kernel<16, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk); break;
-    case 1: case 2: hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk); break;
-    default: hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, Pi, chunk);
+    case 0: hipLaunchKernelGGL((wgrad_kernel<16, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, rows); break;
+    case 1: case 2: hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, rows); break;
+    default: hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, blk, 0, s, X, dZ, partial, bpart, H, W, rows);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = cout * cin * 9 + cout;
-  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, bpart, nchunks,
+  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 63) / 64), dim3(64 * kRedWaves), 0, s, partial, bpart, nparts,
                      cin, cout, gradW, gradb);
   return hipGetLastError();
 }

@@ -19,7 +19,6 @@ namespace {
 constexpr int kLayers = 4;
 constexpr int kCin[kLayers] = {16, 32, 32, 32};
 constexpr int kCout[kLayers] = {32, 32, 32, 16};
-constexpr int kChunk = 2048;      // pixels per weight-gradient partial
 constexpr int kLossParts = 256;   // FP64 loss partials
 
 int num_params() {
@@ -39,7 +38,7 @@ struct CnnLayout {
       dz[kLayers], wpart, bpart, lpart, loss, total;
 };
 
-CnnLayout cnn_layout(long long P) {
+CnnLayout cnn_layout(long long P, int W) {
   CnnLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -63,9 +62,9 @@ CnnLayout cnn_layout(long long P) {
     L.a[l] = take((size_t)P * kCout[l] * 2);
     L.dz[l] = take((size_t)P * kCout[l] * 2);
   }
-  const long long nchunks = (P + kChunk - 1) / kChunk;
-  L.wpart = take((size_t)nchunks * 32 * 9 * 32 * 4);
-  L.bpart = take((size_t)nchunks * 32 * 4);
+  const long long nparts = cnn_wgrad_parts(W, P / W);
+  L.wpart = take((size_t)nparts * 32 * 9 * 32 * 4);
+  L.bpart = take((size_t)nparts * 32 * 4);
   L.lpart = take(kLossParts * 8);
   L.loss = take(8);
   L.total = off;
@@ -143,7 +142,7 @@ int cplb_cnn_num_params(void) { return num_params(); }
 int cplb_cnn_workspace_bytes(int nsamples, int H, int W, size_t* bytes) {
   if (!bytes || nsamples < 1 || H < 1 || W < 1) return CPLB_EINVAL;
   if ((double)nsamples * H * W > 2.0e8) return CPLB_EINVAL;
-  *bytes = cnn_layout((long long)nsamples * H * W).total;
+  *bytes = cnn_layout((long long)nsamples * H * W, W).total;
   return CPLB_OK;
 }
 
@@ -164,7 +163,7 @@ int cplb_cnn_create(int nsamples, int H, int W, void* dev_workspace, size_t byte
   c->P = (long long)nsamples * H * W;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)dev_workspace;
-  c->L = cnn_layout(c->P);
+  c->L = cnn_layout(c->P, W);
   c->used_P = 0;
   c->adam_t = 0;
   c->out_scale = 1.f;
@@ -304,7 +303,6 @@ int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
   if (c->used_P == 0) return set_err(c, CPLB_EINVAL, "backward needs a forward first");
   const long long P = c->used_P;
   const int rows = (int)(P / c->W);
-  const int nchunks = (int)((P + kChunk - 1) / kChunk);
   double* dloss = c->at<double>(c->L.loss);
   int rc = hip_check(c, cnn_loss(c->at<float>(c->L.z[kLayers - 1]), dev_target, P,
                                  c->at<unsigned short>(c->L.dz[kLayers - 1]),
@@ -316,7 +314,7 @@ int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
     const unsigned short* xin = l == 0 ? c->at<unsigned short>(c->L.x0) : c->at<unsigned short>(c->L.a[l - 1]);
     const int wo = w_offset(l);
     rc = hip_check(c, cnn_wgrad(l, xin, c->at<unsigned short>(c->L.dz[l]), c->at<float>(c->L.wpart),
-                                c->at<float>(c->L.bpart), nchunks, kChunk, c->H, c->W, P, grad + wo,
+                                c->at<float>(c->L.bpart), c->H, c->W, rows, grad + wo,
                                 grad + wo + kCout[l] * kCin[l] * 9, c->stream),
                    "weight gradient");
     if (rc || l == 0) break;

@@ -108,9 +108,13 @@ enum { kConvForward = 0, kConvAdjoint = 2, kConvInfer = 3, kConvInferOut = 4 };
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
                     int W, int rows, float scale, hipStream_t s);
+// weight and bias gradients of layer l over `rows` rows of width W; partial
+// and bpart hold cnn_wgrad_parts(W, rows) partial sums of COUT x 9 CIN and
+// COUT floats
+int cnn_wgrad_parts(int W, long long rows);
 hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
-                     float* bpart, int nchunks, int chunk, int H, int W, long long P, float* gradW,
-                     float* gradb, hipStream_t s);
+                     float* bpart, int H, int W, int rows, float* gradW, float* gradb,
+                     hipStream_t s);
 hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
                     unsigned short* X0, hipStream_t s);
 hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s);
