@@ -271,15 +271,24 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         }
         // byte offset of the push target of direction i (plane i of its set),
         // or of the bounce-back target (plane opp(i), this node); the plane
-        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix
+        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix.  Walls
+        // is uniform over the wave: true only where a lane of it has a wall
+        // link (the first and last planes of a walled z axis, the columns
+        // of walled x / y faces); elsewhere every store takes its push
+        // target without a select.  With walls both offsets are formed and
+        // selected per lane (the plane offsets are opaque to the compiler,
+        // which would otherwise branch around each one).
+        const bool walls = __ballot(bits != 0) != 0;
         auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
           const Off sk = cx > 0 ? Off(0) - BS : (cx < 0 ? BS : Off(0));
           Off t = node;
           if (cx) t += cx < 0 ? push.dxm : push.dxp;
           if (cy) t += cy < 0 ? push.dym : push.dyp;
           if (cz) t += cz < 0 ? dzm : dzp;
-          return (bits & link_mask(cx, cy, cz)) ? plane<true>(o, G.sS) + node - sk
-                                                : plane<true>(i, G.sS) + t + sk;
+          const Off push_t = plane<true>(i, G.sS) + t + sk;
+          if (!walls) return push_t;
+          const Off back_t = plane<true>(o, G.sS) + node - sk;
+          return (bits & link_mask(cx, cy, cz)) ? back_t : push_t;
         };
         S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
         S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
