@@ -33,22 +33,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44599977, "write": 43034733,
-                                  "src": "8cc3404cd809ccc1"},
-    "rising_droplet_256c_f32": {"read": 3233814205, "write": 3120747157,
-                               "src": "8cc3404cd809ccc1"},
-    "rising_droplet_256c_f32_s16f": {"read": 1787570653, "write": 1775671707,
-                                    "src": "8cc3404cd809ccc1"},
-    "rising_bubble_2048x4096_f32": {"read": 1484365255, "write": 1376878891,
-                                   "src": "8cc3404cd809ccc1"},
-    "rising_bubble_one_256x1024_f32": {"read": 32772997, "write": 32530041,
-                                      "src": "8cc3404cd809ccc1"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1767063515, "write": 1379164656,
-                                         "src": "8cc3404cd809ccc1"},
-    "rising_droplet_local_256c_f32": {"read": 3266934125, "write": 3120274309,
-                                     "src": "8cc3404cd809ccc1"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1781633374, "write": 1775368576,
-                                          "src": "8cc3404cd809ccc1"},
+    "rising_bubble_256x1024_f32": {"read": 44600947, "write": 43035964,
+                                  "src": "ddfe7f2148e823ea"},
+    "rising_droplet_256c_f32": {"read": 3272538956, "write": 3120015696,
+                               "src": "ddfe7f2148e823ea"},
+    "rising_droplet_256c_f32_s16f": {"read": 1791466362, "write": 1776066251,
+                                    "src": "ddfe7f2148e823ea"},
+    "rising_bubble_2048x4096_f32": {"read": 1484596930, "write": 1376889419,
+                                   "src": "ddfe7f2148e823ea"},
+    "rising_bubble_one_256x1024_f32": {"read": 32773100, "write": 32527935,
+                                      "src": "ddfe7f2148e823ea"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1766492580, "write": 1379170344,
+                                         "src": "ddfe7f2148e823ea"},
+    "rising_droplet_local_256c_f32": {"read": 3319307608, "write": 3120038704,
+                                     "src": "ddfe7f2148e823ea"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1790263236, "write": 1774675856,
+                                          "src": "ddfe7f2148e823ea"},
 }
 
 

@@ -40,10 +40,6 @@ __device__ inline unsigned short to_bf16(float f) {
 }
 __device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ inline short4v load4(const unsigned short* p) {
-  return __builtin_bit_cast(short4v, *(const unsigned long long*)p);
-}
-
 __device__ inline float4v mfma(short4v a, short4v b, float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
