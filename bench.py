@@ -162,6 +162,38 @@ def time_gpu(w, steps, warmup, graph=True):
     return dict(n=n, total_ms=total_ms, avg_kernel_ms=total_ms / steps, graph=use_graph, reduce=r)
 
 
+def time_gpu_with_reduce(w, steps, warmup, every=100):
+    """The same step loop with the FP64 reduction (phase and scalar masses,
+    max |u|, kinetic energy, the non-finite check) every `every` steps, as a
+    run that monitors its conservation would do.  Each reduction copies its
+    eight values to the host and synchronises, so the region is timed on the
+    host clock; the steps between reductions are one graph replay."""
+    import torch
+
+    from paper_2402_15752_amd import cplb
+    assert every % 2 == 0 and steps % every == 0
+    stream = torch.cuda.Stream()
+    lat = cplb.Lattice(w["params"], stream=stream)
+    lat.init_sdf(w["sdf"], c1=w["init"]["c1"], c2=w["init"]["c2"])
+    lat.step(warmup)
+    n = int(w["params"]["nx"]) * int(w["params"]["ny"]) * int(w["params"]["nz"])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        lat.step(every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // every):
+        with torch.cuda.stream(stream):
+            g.replay()
+        r = lat.reduce()
+    dt = time.perf_counter() - t0
+    lat.close()
+    del g
+    return dict(mlups=round(n * steps / dt / 1e6, 2), ms_per_step=round(dt * 1e3 / steps, 5),
+                reduce_every=every, nonfinite=r["nonfinite"])
+
+
 def time_batch(steps, warmup, tune_steps=5):
     """The batched sweep: 512 independent 2-D cases (sizes 64..256 a side)
     advanced together, one launch per size class per step, the tile variant
@@ -243,6 +275,19 @@ def cpu_baseline(w, seconds=25.0):
                       f"OpenMP over {threads} threads, {dt:.1f} s"}
 
 
+def cpu_baseline_one_thread(name, seconds=8.0):
+    """The oracle on one thread (OMP_NUM_THREADS=1), in a child process that
+    touches no GPU: the bounded sample of cpu_baseline, shorter."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench.cpu_baseline(bench.make_workload(%r), %r)))"
+            % (ROOT, name, seconds))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=300, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +365,9 @@ def main():
     r = res["reduce"]
     out["check"] = {"nonfinite": r["nonfinite"], "sum_phi": r["sum_phi"], "step": r["step"]}
     if not args.no_extra and args.workload == "rising_bubble_256x1024":
+        wr = time_gpu_with_reduce(w, args.steps - args.steps % 100 or 100, args.warmup)
+        wr["overhead"] = round(wr["ms_per_step"] / out["ms_per_step"] - 1.0, 4)
+        out["with_reduce"] = wr
         extra = {}
         for wname in ("rising_droplet_256c_f32", "rising_droplet_256c_f32_s16f",
                       "rising_droplet_256c_f32_s16b", "rising_droplet_local_256c_f32",
@@ -369,6 +417,9 @@ def main():
         out["closure"] = closure_speedup()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        one = cpu_baseline_one_thread(args.workload)
+        out["cpu_baseline"]["one_thread_value"] = one["value"]
+        out["cpu_baseline"]["one_thread_sample"] = one["sample"]
     print(json.dumps(out), flush=True)
 
 
