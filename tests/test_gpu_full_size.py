@@ -124,3 +124,54 @@ def test_one_scalar_bubble_full_size(cplb):
     w = W.rising_bubble_2d(scalar_model="one")
     say("one-scalar rising bubble 256x1024 f32, 200 steps")
     run_pair(cplb, w, 200, FP32_2D, 1e-5, "t=200")
+
+
+# --------------------------------------------- sets beyond 4 GiB (64-bit path)
+
+def _random_field_pair(cplb, p, steps, names, tol, label):
+    f = W.random_fields(p, seed=23)
+    g = cplb.Lattice(p)
+    o = ref.Oracle(dict(p, precision="f64"))
+    for s in (g, o):
+        s.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
+    del f
+    g.step(steps)
+    o.step(steps)
+    errs = {}
+    for k in names:
+        a = g.field(k).cpu().numpy()
+        assert np.all(np.isfinite(a)), k
+        errs[k] = rel_err(a, o.field(k))
+        del a
+    say(f"  {label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    g.close()
+    del g, o
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, bad, tol)
+
+
+def test_64bit_offsets_3d_fp32(cplb):
+    """384^3 FP32: the 19 planes of g span more than 4 GiB, so the step takes
+    its 64-bit-offset instantiation (every smaller case takes the 32-bit
+    one).  Random fields, walls on x and z, 2 steps, every field."""
+    n = 384
+    assert 19 * n ** 3 * 4 > 1 << 32
+    p = W.params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", periodic=(0, 1, 0), precision="f32",
+                 sigma=2e-3, rho1=3.0, rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07,
+                 D2=0.02, Keq=0.6, A=0.4, g=(1e-5, -2e-5, 3e-5), rho_ref=1.5,
+                 ref_f=W.phase_reference("f32"))
+    say("384^3 f32 random fields (64-bit offsets), 2 steps")
+    _random_field_pair(cplb, p, 2, FP32_3D + ("psi",), 1e-5, "t=2")
+
+
+def test_64bit_offsets_2d_fp64(cplb):
+    """8000 x 8000 FP64: each 9-plane set spans more than 4 GiB, so the 2-D
+    step takes its 64-bit-offset instantiation.  Random fields, walls on y,
+    3 steps, every field to FP64 round-off."""
+    n = 8000
+    assert 9 * n * n * 8 > 1 << 32
+    p = W.params(nx=n, ny=n, periodic=(1, 0, 1), precision="f64", sigma=2e-3, rho1=3.0,
+                 rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07, D2=0.02, Keq=0.6, A=0.4,
+                 g=(2e-5, -3e-5, 0.0), rho_ref=1.5)
+    say("8000x8000 f64 random fields (64-bit offsets), 3 steps")
+    _random_field_pair(cplb, p, 3, FP32_2D + ("mu", "psi"), 1e-12, "t=3")
