@@ -127,6 +127,24 @@ def test_fp64_random_fields_3d(cplb, periodic):
     compare(g, o, ALL3, 1e-12, "t=3")
 
 
+@pytest.mark.parametrize("kw", [
+    dict(nx=1, ny=24, periodic=(1, 0, 1)),
+    dict(nx=19, ny=1, periodic=(0, 1, 1)),
+    dict(nx=1, ny=6, nz=20, lattice="d3q19_d3q7", periodic=(1, 1, 0)),
+], ids=["2d-nx1", "2d-ny1", "3d-nx1"])
+def test_fp64_one_node_wide_periodic_axis(cplb, kw):
+    """Degenerate lattices: a periodic axis one node wide, so every stencil
+    neighbour and push target along it is the node itself (the gradient
+    along it vanishes).  FP64 random fields, 3 steps."""
+    say(f"fp64 one node wide {kw}")
+    p = W.params(precision="f64", sigma=2e-3, rho1=3.0, rho2=1.0, visc_law="exp", mu1=0.3,
+                 mu2=0.08, D1=0.07, D2=0.02, Keq=0.6, A=0.4, rho_ref=1.5,
+                 g=(1e-5, -2e-5, 3e-5 if "nz" in kw else 0.0), **kw)
+    f = W.random_fields(p, seed=31)
+    g, o = pair_fields(cplb, p, f, 3)
+    compare(g, o, ALL3 if "nz" in kw else ALL2, 1e-12, "t=3")
+
+
 def test_static_drop_fp64_full_run(cplb):
     """Static drop, 64 x 64 periodic, FP64, 2000 steps."""
     w = W.static_drop_64()
