@@ -1,8 +1,8 @@
 """End-to-end test of the learned closure: fine-grid runs of the plain
 method generate the training data, the closure network is trained on the
 GPU by its own kernels, and held-out cases run freely on the coarse grid
-with and without it, against the restricted fine run (the judge of its
-error).
+with and without it, against the restricted fine run (the reference for
+its error).
 
 Static drops with interfacial transfer, coarse 64 x 64 against fine
 256 x 256 (F = 4 in space, 16 in time), 100 coarse steps.  The test
