@@ -305,8 +305,9 @@ def main():
                          "(for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the step is "
-              "single-GPU by design, see DESIGN.md for how it would shard", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the step is "
+              "built and measured on one GPU; across GPUs it would shard as slabs with one "
+              "halo exchange per step, which is not built", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
