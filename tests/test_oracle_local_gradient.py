@@ -74,3 +74,24 @@ def test_linear_equilibrium_with_local_gradient(D1, D2, K):
     ct2i = 2.0 * D1 * L2 / (D2 * L1 + K * D1 * L2)
     assert abs(a2[0] / (ct2i / L2) - 1.0) <= 5e-3, a2[0]
     assert abs(a1[0] / ((2.0 - K * ct2i) / L1) - 1.0) <= 5e-3, a1[0]
+
+
+def test_local_gradient_in_uniform_flow():
+    """The same smooth drop carried by a uniform flow u0 = (0.1, 0): Eq. (39)
+    then leans on its u and d_t(c_k u) terms, and the local gradient stays
+    within 8 % of central differences of psi (4.3 % measured; with the sign
+    of the d_t term reversed it is 23 %)."""
+    n = 96
+    p = W.params(nx=n, ny=n, periodic=(1, 1, 1), sigma=1e-3, D1=0.08, D2=0.03, Keq=0.5,
+                 A=0.1, W=8.0, scalar_grad="local")
+    x, y = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5)
+    phi = 0.5 + 0.5 * np.tanh(2 * (24.0 - np.hypot(x - 48.0, y - 48.0)) / 8.0)
+    u = np.stack([np.full(phi.shape, 0.1), np.zeros(phi.shape)])
+    o = ref.Oracle(p)
+    o.init_fields(phi, 0.3 * phi, 0.5 - 0.5 * phi, u=u)
+    o.step(400)
+    gx, gy, psi = o.field("gpsi_x"), o.field("gpsi_y"), o.field("psi")
+    cx = (np.roll(psi, -1, 1) - np.roll(psi, 1, 1)) / 2.0
+    cy = (np.roll(psi, -1, 0) - np.roll(psi, 1, 0)) / 2.0
+    e = np.sqrt(((gx - cx) ** 2 + (gy - cy) ** 2).sum() / (cx ** 2 + cy ** 2).sum())
+    assert e <= 8e-2, e
