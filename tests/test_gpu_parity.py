@@ -394,3 +394,45 @@ def test_graph_replays_match_eager_steps(cplb, lattice):
         assert ra["sum_phi"] == re_["sum_phi"] and ra["max_u"] == re_["max_u"], rep
         for k in names:
             assert np.array_equal(a.field(k).cpu().numpy(), e.field(k).cpu().numpy()), (rep, k)
+
+
+def test_entry_points_reject_bad_arguments(cplb):
+    """Every entry point checks its arguments before touching the device and
+    returns the documented code with a message (no launch happens)."""
+    import ctypes
+
+    import torch
+    L = cplb.library()
+    lat = cplb.Lattice(W.params(nx=16, ny=8, precision="f32"))
+    h = lat.handle
+    buf = torch.empty(lat.N, dtype=torch.float32, device="cuda")
+    EINVAL, ENOMEM, ESTATE = cplb.CPLB_EINVAL, cplb.CPLB_ENOMEM, cplb.CPLB_ESTATE
+    F32 = cplb.DTYPE_F32
+    cases = [
+        (L.cplb_step(h, -1), EINVAL),
+        (L.cplb_read_field(h, 99, buf.data_ptr(), F32), EINVAL),
+        (L.cplb_read_field(h, 0, buf.data_ptr(), 7), EINVAL),
+        (L.cplb_read_field(h, 0, None, F32), EINVAL),
+        (L.cplb_init_fields(h, None, None, None, None, None), EINVAL),
+        (L.cplb_init_sdf(h, None, 0.0, 0.0, 0.0, 0.0), EINVAL),
+        (L.cplb_set_variant(h, 99), EINVAL),
+        (L.cplb_tune(h, 0, None), EINVAL),
+    ]
+    small = ctypes.create_string_buffer(16)
+    cases += [(L.cplb_save_state(h, small, 16), ENOMEM), (L.cplb_load_state(h, small, 16), ESTATE)]
+    for rc, want in cases:
+        assert rc == want, (rc, want)
+        assert L.cplb_last_error(h).decode(), rc
+        assert L.cplb_strerror(rc).decode()
+    # a null handle is refused without a message to write
+    assert L.cplb_step(None, 1) == EINVAL
+    assert L.cplb_reduce(None, None) == EINVAL
+    # the lattice is unharmed: it still steps and reduces
+    lat.init_sdf(np.zeros(lat.shape), c1=(0.5, 0.0), c2=(0.5, 0.0))
+    lat.step(2)
+    assert lat.reduce()["rc"] == 0
+    # a closure applies to D2Q9 lattices only
+    lat3 = cplb.Lattice(W.params(nx=8, ny=8, nz=8, lattice="d3q19_d3q7", precision="f32"))
+    assert L.cplb_set_closure(lat3.handle, ctypes.c_void_p(buf.data_ptr())) == EINVAL
+    lat.close()
+    lat3.close()
