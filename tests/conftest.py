@@ -20,3 +20,15 @@ def _oracle_built():
     if not os.path.exists(obuild.LIB):
         obuild.build()
     yield
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _library_built():
+    """Build libcplb.so (hipcc cross-compiles for gfx950 without a GPU) once
+    per session if a fresh checkout lacks it; a GPU run never builds."""
+    from paper_2402_15752_amd import build as lbuild
+    if not os.path.exists(lbuild.LIB) and os.path.exists("/opt/rocm/bin/hipcc"):
+        import torch
+        if not torch.cuda.is_available():
+            lbuild.build()
+    yield
