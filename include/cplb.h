@@ -311,7 +311,8 @@ int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step);
 
 const char* cplb_batch_last_error(const cplb_batch_t* b);
 
-/* Release the batch (not the caller's workspace or stream). */
+/* Release the batch (not the caller's workspace or stream).  Does not wait:
+ * synchronise the stream before freeing or reusing the workspace. */
 void cplb_batch_destroy(cplb_batch_t* b);
 
 /* ------------------------------------------------------------------------
@@ -384,13 +385,17 @@ int cplb_cnn_restrict(void* hip_stream, const float* dev_fine, int nsamples, int
                       float* dev_coarse);
 
 const char* cplb_cnn_last_error(const cplb_cnn_t* c);
+/* Release the network (not the caller's workspace or stream); does not wait
+ * for queued work. */
 void cplb_cnn_destroy(cplb_cnn_t* c);
 
 /* Error text of the last failed call on h, and of a return code. */
 const char* cplb_last_error(const cplb_t* h);
 const char* cplb_strerror(int code);
 
-/* Release the handle (not the caller's workspace or stream). */
+/* Release the handle (not the caller's workspace or stream).  Does not wait
+ * for work queued on the stream: synchronise it before freeing or reusing the
+ * workspace. */
 void cplb_destroy(cplb_t* h);
 
 #ifdef __cplusplus

@@ -321,7 +321,10 @@ class Lattice:
         self._h = cplb_create(self._prm, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
 
     def close(self):
+        """Release the handle once the work queued on its stream has finished
+        (the workspace tensor may be reused by torch as soon as it is freed)."""
         if getattr(self, "_h", None):
+            self.stream.synchronize()
             cplb_destroy(self._h)
             self._h = None
 
@@ -551,7 +554,9 @@ class Batch:
                                     self.stream.cuda_stream)
 
     def close(self):
+        """Release the batch once the work queued on its stream has finished."""
         if getattr(self, "_b", None):
+            self.stream.synchronize()
             cplb_batch_destroy(self._b)
             self._b = None
 
@@ -759,7 +764,9 @@ class ClosureNet:
             cplb_cnn_init_params(self._c, seed)
 
     def close(self):
+        """Release the network once the work queued on its stream has finished."""
         if getattr(self, "_c", None):
+            self.stream.synchronize()
             cplb_cnn_destroy(self._c)
             self._c = None
 
