@@ -15,7 +15,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Geometry {
   int dim, qtot, nhist;
-  int px;            // row pitch: nx rounded up to 32 nodes
+  int px;            // row pitch (nodes between two rows); rows are packed, px = nx
   long long n;       // nodes
   long long cells;   // px ny nz: the nodes and the row padding of a plane
   long long stride;  // elements per plane
@@ -75,6 +75,23 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
   for (double v : all)
     if (!std::isfinite(v)) return fail("non-finite parameter");
   return CPLB_OK;
+}
+
+// Field-by-field equality of two parameter sets (== on every double, so
+// -0.0 equals +0.0; the struct's padding bytes take no part).
+inline bool same_params(const cplb_params& a, const cplb_params& b) {
+  bool eq = a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lattice == b.lattice &&
+            a.precision == b.precision && a.visc_law == b.visc_law &&
+            a.scalar_model == b.scalar_model && a.scalar_grad == b.scalar_grad;
+  for (int k = 0; k < 3; ++k) eq = eq && a.periodic[k] == b.periodic[k] && a.g[k] == b.g[k];
+  eq = eq && a.rho1 == b.rho1 && a.rho2 == b.rho2 && a.mu1 == b.mu1 && a.mu2 == b.mu2 &&
+       a.sigma == b.sigma && a.W == b.W && a.M == b.M && a.D1 == b.D1 && a.D2 == b.D2 &&
+       a.Keq == b.Keq && a.A == b.A && a.rho_ref == b.rho_ref && a.n_eps == b.n_eps;
+  for (int k = 0; k < 4; ++k) eq = eq && a.ref[k] == b.ref[k];
+  for (int f = 0; f < 6; ++f)
+    eq = eq && a.scalar_bc[f] == b.scalar_bc[f] && a.c_wall[f][0] == b.c_wall[f][0] &&
+         a.c_wall[f][1] == b.c_wall[f][1];
+  return eq;
 }
 
 inline Geometry geometry(const cplb_params* p) {

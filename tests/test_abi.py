@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import workloads as W
@@ -150,17 +151,24 @@ def test_batched_sweep_recipe():
     assert len(full["cases"]) == 512 and full["nodes"] == sum(
         x["params"]["nx"] * x["params"]["ny"] for x in full["cases"])
     cs2 = 1.0 / 3.0
+    ratios = []
     for x in full["cases"]:
         p = x["params"]
         assert 64 <= p["nx"] <= 256 and 64 <= p["ny"] <= 256
         assert 0.1 <= p["Keq"] <= 10.0
         for d in (p["D1"], p["D2"]):
             tau = 0.5 + d / cs2
-            assert 0.5 + 1e-3 - 1e-12 <= tau <= 1.0 + 1e-12
+            assert 0.5 + 1e-3 - 1e-12 <= tau <= 2.0 + 1e-12
         assert p["D2"] >= p["D1"]
+        ratios.append(p["D2"] / p["D1"])
         assert x["sdf"].shape == (p["ny"], p["nx"])
-    # every clamp is recorded with the value asked for and the value used
-    for k, name, asked, used in full["clamps"]:
-        assert asked != used and (used == cs2 * 1e-3 or used == cs2 * 0.5)
+    # the diffusivity ratio is never clipped: log-uniform over [1, 1000]
+    lr = np.log10(np.array(ratios))
+    assert lr.min() >= -1e-12 and lr.max() <= 3.0 + 1e-12
+    assert lr.max() > 2.95 and lr.min() < 0.05
+    assert abs(np.median(lr) - 1.5) < 0.2
+    # a case whose diffusivities were moved keeps its ratio; only Pe changes
+    for k, pe_asked, pe_used in full["shifted"]:
+        assert pe_asked != pe_used
     kinds = {x["params"]["periodic"][1] for x in full["cases"]}
     assert kinds == {0, 1}  # both static (periodic) and rising (walled) cases

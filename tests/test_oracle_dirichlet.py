@@ -1,5 +1,5 @@
 """Pins of the oracle's Dirichlet scalar boundary (half-way anti-bounce-back
-of h1, h2, Sec. IV) on the paper's linear-equilibrium case (Sec. V A 3):
+of h1, h2, Sec. IV) on the paper's linear-equilibrium case (Sec. IV A 3):
 a planar interface in the middle of a walled 1-D domain, phase 1 on the
 right, c1 = c2 = 0 imposed on the left face and c1 = 2, c2 = 0 on the right.
 

@@ -4,7 +4,7 @@ h3^eq built on c / K_eff and a per-node relaxation time from
 D_eff = D1 Keq phi + D2 (1 - phi).
 
 Each pin is fixed by the mathematics or by the paper's own 1-D tests
-(Sec. V A), not by the oracle's code:
+(Sec. IV A), not by the oracle's code:
   - sum_i h3^eq = c and sum_i H3 = 0: total solute conserved to round-off;
   - in a bulk phase (phi = 1 with Keq = 1, or phi = 0 with any Keq) the
     one-scalar model is the two-scalar model's c1 (resp. c2) equation, so
@@ -14,10 +14,10 @@ Each pin is fixed by the mathematics or by the paper's own 1-D tests
   - the steady state is c / K_eff uniform (Eq. (31) has zero flux there),
     at the value fixed by the total solute;
   - pseudo-single-phase case (D1 = D2, Keq = 1): one- and two-scalar
-    models agree (Sec. V A 1);
+    models agree (Sec. IV A 1);
   - large diffusivity ratio (D1 / D2 = 10^4, Keq = 1): the one-scalar
     model leaks solute into phase 2, the two-scalar model does not
-    (Sec. V A 4).
+    (Sec. IV A 4).
 """
 import numpy as np
 import pytest
@@ -117,7 +117,7 @@ def test_steady_state_is_uniform_c_over_keff(keq):
 
 
 def test_pseudo_single_phase_one_and_two_scalar_agree():
-    """Sec. V A 1: D1 = D2, Keq = 1, c1 = 5 exp(-4 x^2) phi,
+    """Sec. IV A 1: D1 = D2, Keq = 1, c1 = 5 exp(-4 x^2) phi,
     c2 = 5 exp(-4 x^2) (1 - phi) on [-1, 1] (N = 200)."""
     N = 200
     x, l = one_d(N)
@@ -137,7 +137,7 @@ def test_pseudo_single_phase_one_and_two_scalar_agree():
 
 
 def test_large_diffusivity_ratio_one_scalar_leaks():
-    """Sec. V A 4: D1 = 1, D2 = 1e-4 (here 0.1 and 1e-5 in lattice units),
+    """Sec. IV A 4: D1 = 1, D2 = 1e-4 (here 0.1 and 1e-5 in lattice units),
     Keq = 1, solute initially c1 = phi (two-scalar) or c = phi (one-scalar).
     Leakage: the share of the solute at nodes of phase 2 (phi < 0.01)."""
     N, T = 200, 5000

@@ -136,8 +136,11 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=N
     """2-D rising bubble with interfacial mass transfer: nx x ny, periodic in x,
     half-way bounce-back walls at the y faces, gravity along -y, bubble
     (fluid 2) of radius nx/16 centred at (nx/2, 3nx/8); density ratio 10,
-    exponential viscosity law with mu1/mu2 = 10, Eo = 10, Keq = 0.2,
-    D2/D1 = 100; c1 = 0, c2 = 1 - phi0 (all solute starts in the bubble).
+    exponential viscosity law mu = exp(c1 ln mu1 + c2 ln mu2), Eo = 10,
+    Keq = 0.2, D2/D1 = 100; c1 = 0, c2 = 1 - phi0 (all solute starts in the
+    bubble).  With mu2 = 0.1 the viscosity is exp(0) = 1 in the solute-free
+    liquid and mu2 = 0.1 in the bubble at t = 0, a ratio of 10 (tau_g = 0.8
+    in both phases); mu1 = 2 takes over where solute enters the liquid.
 
     scalar_model="one" runs the one-scalar model; its default Keq is 2
     (the model needs K_eff >= 5/9 in the liquid, see the one-scalar notes
@@ -146,7 +149,7 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=N
     rho1, rho2, sigma, Eo = 10.0, 1.0, 0.01, 10.0
     gmag = Eo * sigma / ((rho1 - rho2) * (2 * R) ** 2)
     p = params(nx=nx, ny=ny, nz=1, lattice="d2q9", visc_law="exp", periodic=(1, 0, 1),
-               rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
+               rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.1, sigma=sigma, W=4.0, M=0.01,
                D1=1e-3, D2=0.1, A=0.1, g=(0.0, -gmag, 0.0), rho_ref=rho1,
                Keq=Keq if Keq is not None else (2.0 if scalar_model == "one" else 0.2),
                precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0,
@@ -160,14 +163,15 @@ def rising_bubble_2d(nx=256, ny=1024, precision="f32", scalar_model="two", Keq=N
 def rising_droplet_3d(n=256, precision="f32", scalar_grad="central"):
     """3-D rising droplet with heat transfer: n^3, periodic in x and y, walls at
     the z faces, gravity along -z; droplet (fluid 2) of radius 24 n/256 at
-    (n/2, n/2, 3R); density ratio 10, exponential viscosity law, Eo = 10;
+    (n/2, n/2, 3R); density ratio 10, exponential viscosity law with the
+    bases of the 2-D bubble (viscosity ratio 10 at t = 0), Eo = 10;
     heat: Keq = rho1 Cp1/(rho2 Cp2) = 10 (equal Cp), conductivity ratio 50
     so D1/D2 = 5; q1 = 0, q2 = 1 - phi0 (hot droplet)."""
     R = 24.0 * n / 256.0
     rho1, rho2, sigma, Eo = 10.0, 1.0, 0.01, 10.0
     gmag = Eo * sigma / ((rho1 - rho2) * (2 * R) ** 2)
     p = params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", visc_law="exp", periodic=(1, 1, 0),
-               rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.2, sigma=sigma, W=4.0, M=0.01,
+               rho1=rho1, rho2=rho2, mu1=2.0, mu2=0.1, sigma=sigma, W=4.0, M=0.01,
                D1=0.05, D2=0.01, Keq=10.0, A=0.1, g=(0.0, 0.0, -gmag), rho_ref=rho1,
                precision=precision, ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0,
                scalar_grad=scalar_grad)
@@ -188,16 +192,19 @@ def batched_sweep(ncases=512, seed=0, precision="f32", side=(64, 256), velocity=
     exponential viscosity law, Eo = 10).  The drop (fluid 2, radius
     min(nx, ny)/8) carries the solute: c1 = 0, c2 = 1 - phi0.
 
-    The Peclet number fixes the fast diffusivity through a velocity scale:
-    D_hi = U 2R / Pe with U = ``velocity``; D_lo = D_hi / ratio.  Both are
-    clamped so that tau = 1/2 + D/cs^2 stays in [1/2 + 1e-3, 1]; every clamp
-    is listed in ``clamps`` (case, name, asked, used).
+    The Peclet number fixes the fast diffusivity through a velocity scale,
+    D_hi = U 2R / Pe with U = ``velocity``, and D_lo = D_hi / ratio.  The
+    diffusivity ratio is always kept as drawn: where D_lo would fall below
+    the smallest diffusivity the scalar lattice resolves (tau = 1/2 + 1e-3)
+    or D_hi above tau = 2, both move together by one factor, which changes
+    Pe only; each such case is listed in ``shifted`` (case, Pe asked,
+    Pe used).
 
-    Returns dict(name, cases=[dict(params, sdf, init)], clamps, nodes)."""
+    Returns dict(name, cases=[dict(params, sdf, init)], shifted, nodes)."""
     rng = np.random.default_rng(seed)
     cs2 = 1.0 / 3.0
-    d_lo_lim, d_hi_lim = cs2 * 1e-3, cs2 * 0.5
-    cases, clamps = [], []
+    d_lo_lim, d_hi_lim = cs2 * 1e-3, cs2 * 1.5
+    cases, shifted = [], []
 
     def loguni(a, b):
         return float(np.exp(rng.uniform(np.log(a), np.log(b))))
@@ -212,14 +219,10 @@ def batched_sweep(ncases=512, seed=0, precision="f32", side=(64, 256), velocity=
         R = min(nx, ny) / 8.0
         d_hi = velocity * 2.0 * R / pe
         d_lo = d_hi / ratio
-        for name, d in (("D_hi", d_hi), ("D_lo", d_lo)):
-            dc = min(max(d, d_lo_lim), d_hi_lim)
-            if dc != d:
-                clamps.append((k, name, d, dc))
-            if name == "D_hi":
-                d_hi = dc
-            else:
-                d_lo = dc
+        shift = max(d_lo_lim / d_lo, 1.0) * min(d_hi_lim / d_hi, 1.0)
+        if shift != 1.0:
+            d_lo, d_hi = d_lo * shift, d_hi * shift
+            shifted.append((k, pe, velocity * 2.0 * R / d_hi))
         common = dict(nx=nx, ny=ny, nz=1, lattice="d2q9", sigma=0.01, W=4.0, M=0.01, A=0.1,
                       Keq=keq, D1=d_lo, D2=d_hi, precision=precision,
                       ref_f=phase_reference(precision), ref_h1=0.0, ref_h2=0.0)
@@ -227,7 +230,7 @@ def batched_sweep(ncases=512, seed=0, precision="f32", side=(64, 256), velocity=
             rho1, rho2, sigma, eo = 10.0, 1.0, 0.01, 10.0
             gmag = eo * sigma / ((rho1 - rho2) * (2 * R) ** 2)
             p = params(**common, visc_law="exp", periodic=(1, 0, 1), rho1=rho1, rho2=rho2,
-                       mu1=2.0, mu2=0.2, g=(0.0, -gmag, 0.0), rho_ref=rho1)
+                       mu1=2.0, mu2=0.1, g=(0.0, -gmag, 0.0), rho_ref=rho1)
             centre = (nx / 2.0, 3.0 * R)
         else:
             p = params(**common, visc_law="linear", periodic=(1, 1, 1), rho1=1.0, rho2=1.0,
@@ -237,7 +240,7 @@ def batched_sweep(ncases=512, seed=0, precision="f32", side=(64, 256), velocity=
         cases.append(dict(name=f"case{k}_{nx}x{ny}_{'rising' if rising else 'static'}",
                           params=p, sdf=l, init=dict(c1=(0.0, 0.0), c2=(1.0, -1.0))))
     nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
-    return dict(name=f"batched_sweep_{ncases}_{precision}", cases=cases, clamps=clamps,
+    return dict(name=f"batched_sweep_{ncases}_{precision}", cases=cases, shifted=shifted,
                 nodes=nodes, steps=5000)
 
 
