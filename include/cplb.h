@@ -192,6 +192,22 @@ int cplb_read_field(cplb_t* h, int field, void* dev_dst, int dtype);
  * Synchronises the stream; returns CPLB_EUNSTABLE if out[6] > 0. */
 int cplb_reduce(cplb_t* h, double out[8]);
 
+/* Allocation-free form of cplb_reduce, for callers that cannot allocate or
+ * synchronise (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation): the same FP64 values out[0..6], bit for bit, written
+ * asynchronously on the stream to dev_out (device memory, caller-owned, at
+ * least 7 doubles; dev_out[7] is not written -- the step counter is host
+ * state, see cplb_step_count).  The per-block partials go to a fixed array
+ * of the library (1024 partials of 8 doubles, 64 KiB per GPU, held until the
+ * process ends) instead of the handle's workspace; the call allocates
+ * nothing and does not synchronise, and it does not return CPLB_EUNSTABLE
+ * (it does not see the values: dev_out[6] counts the non-finite nodes).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (different streams, no ordering between them) race.
+ * Errors: CPLB_EINVAL (null handle or dev_out), CPLB_ENOMEM (more partials
+ * than the array holds), CPLB_EHIP. */
+int cplb_reduce_device(cplb_t* h, double* dev_out);
+
 /* Number of steps taken since the last init or load. */
 int64_t cplb_step_count(const cplb_t* h);
 

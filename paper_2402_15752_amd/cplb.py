@@ -29,7 +29,7 @@ SCALAR_GRAD = {"central": 0, "local": 1}
 FIELDS = {"phi": 0, "p": 1, "ux": 2, "uy": 3, "uz": 4, "c1": 5, "c2": 6, "mu": 7, "psi": 8}
 DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = ("cplb_workspace_bytes", "cplb_create", "cplb_init_fields", "cplb_init_sdf", "cplb_step",
-           "cplb_read_field", "cplb_reduce", "cplb_step_count", "cplb_state_bytes",
+           "cplb_read_field", "cplb_reduce", "cplb_reduce_device", "cplb_step_count", "cplb_state_bytes",
            "cplb_save_state", "cplb_load_state", "cplb_last_error", "cplb_strerror",
            "cplb_destroy", "cplb_num_variants", "cplb_get_variant", "cplb_set_variant",
            "cplb_variant_name", "cplb_tune",
@@ -90,6 +90,7 @@ def library():
         L.cplb_step.argtypes = [vp, ctypes.c_int64]
         L.cplb_read_field.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         L.cplb_reduce.argtypes = [vp, dp]
+        L.cplb_reduce_device.argtypes = [vp, vp]
         L.cplb_step_count.argtypes = [vp]
         L.cplb_step_count.restype = ctypes.c_int64
         L.cplb_state_bytes.argtypes = [vp]

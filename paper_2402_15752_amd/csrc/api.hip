@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/cplb.h"
@@ -23,6 +24,7 @@ struct cplb {
   void* hist;
   void* fields;
   double* partials;
+  double* scratch_dev;  // this device's copy of `scratch` (cplb_reduce_device)
   int cur;
   int64_t step;
   int variant;  // compiled step-kernel variant in use
@@ -34,7 +36,38 @@ struct cplb {
   char err[512];
 };
 
+// Reduction partials of cplb_reduce_device: a fixed array of the library
+// instead of the handle's workspace, so that call allocates nothing.  One
+// copy per GPU (kReduceBlocks per-block partials of 8 doubles, 64 KiB), held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel -- on the host it only names the symbol -- but the device address
+// that hipGetSymbolAddress returns for the current device.
+constexpr int kScratchParts = kReduceBlocks;
+static __device__ __align__(256) double scratch[8 * kScratchParts];
+
 namespace {
+
+std::mutex scratch_mu;
+void* scratch_addr[64];  // device address of `scratch` per device ordinal, once looked up
+
+// address of this device's `scratch`, looked up once per device with that
+// device current (cplb_create)
+hipError_t scratch_address(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[dev] = p;
+  }
+  *out = (double*)scratch_addr[dev];
+  return hipSuccess;
+}
 
 int set_err(cplb_t* h, int code, const char* fmt, const char* a = "") {
   if (h) snprintf(h->err, sizeof(h->err), fmt, a);
@@ -204,6 +237,11 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   h->k64 = make_kparams<double>(prm, G);
   h->k32 = make_kparams<float>(prm, G);
   h->err[0] = 0;
+  rc = hip_check(h, scratch_address(&h->scratch_dev), "lookup of the reduction scratch array");
+  if (rc) {
+    delete h;
+    return rc;
+  }
   rc = hip_check(h, hipMemcpyAsync(h->k64_dev, &h->k64, sizeof(h->k64), hipMemcpyHostToDevice,
                                    h->stream), "upload of lattice constants");
   if (!rc)
@@ -292,6 +330,26 @@ int cplb_reduce(cplb_t* h, double out[8]) {
   out[7] = (double)h->step;
   if (out[6] > 0) return set_err(h, CPLB_EUNSTABLE, "non-finite values in %s fields", "the");
   return CPLB_OK;
+}
+
+int cplb_reduce_device(cplb_t* h, double* dev_out) {
+  if (!h) return CPLB_EINVAL;
+  if (!dev_out) return set_err(h, CPLB_EINVAL, "null device destination%s", "");
+  const int nparts = h->G.n < (long long)kReduceBlocks * 256 ? (int)((h->G.n + 255) / 256) : kReduceBlocks;
+  if (nparts > kScratchParts)
+    return set_err(h, CPLB_ENOMEM, "%s: more reduction partials than the fixed array holds",
+                   "cplb_reduce_device");
+  if (!h->scratch_dev) return set_err(h, CPLB_EHIP, "reduction scratch array not available%s", "");
+  int rc = compute_fields(h);
+  if (rc) return rc;
+  hipError_t e;
+  if (h->G.s_cmp == 8)
+    e = launch_reduce<double>((const double*)h->fields, h->G.stride, h->G.n, h->prm.nx, h->G.px,
+                              h->prm.rho1, h->prm.rho2, h->scratch_dev, nparts, dev_out, h->stream);
+  else
+    e = launch_reduce<float>((const float*)h->fields, h->G.stride, h->G.n, h->prm.nx, h->G.px,
+                             h->prm.rho1, h->prm.rho2, h->scratch_dev, nparts, dev_out, h->stream);
+  return hip_check(h, e, "reduction kernels");
 }
 
 size_t cplb_state_bytes(const cplb_t* h) {
