@@ -133,10 +133,13 @@ typedef struct cplb_params {
   double g[3];           /* gravity; body force G = (rho - rho_ref) g            */
   double rho_ref;        /* reference density of the body force                  */
   double n_eps;          /* normal n = grad phi / sqrt(|grad phi|^2 + n_eps^2)   */
-  double ref[4];         /* reference state of the stored populations: f, h1, h2
-                            are held as deviations X_i - w_i ref[k] (k = 0, 2, 3:
-                            phi_ref, c1_ref, c2_ref), which keeps FP32 and 16-bit
-                            rounding relative to the deviation; ref[1] (g) must be 0 */
+  double ref[4];         /* uniform references of the stored scalar populations:
+                            where h1, h2 have no per-node reference (one-scalar
+                            model, local gradient scheme) they are held as
+                            X_i - w_i ref[k] (k = 2, 3: c1_ref, c2_ref).  f, and
+                            h1, h2 otherwise, are held relative to the moments of
+                            the node they are stored at, g relative to a pressure
+                            bracket, so ref[0] has no effect; ref[1] must be 0 */
   int32_t scalar_bc[6];  /* faces x-, x+, y-, y+, z-, z+ of a walled axis:
                             CPLB_BC_NOFLUX or CPLB_BC_DIRICHLET (h1, h2)          */
   double c_wall[6][2];   /* (c1, c2) imposed at each Dirichlet face              */

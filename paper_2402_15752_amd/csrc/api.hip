@@ -21,7 +21,7 @@ struct cplb {
   hipStream_t stream;
   char* ws;
   void* lat[2];
-  void* hist;
+  void* hist[2];  // histories, alternating with the lattices: hist[cur] goes with lat[cur]
   void* fields;
   double* partials;
   double* scratch_dev;  // this device's copy of `scratch` (cplb_reduce_device)
@@ -84,10 +84,12 @@ template <class S, class T>
 hipError_t dispatch_step(cplb_t* h, const KParams<T>& K, const KParams<T>* Kdev, int mode) {
   const S* src = (const S*)h->lat[h->cur];
   S* dst = (S*)h->lat[h->cur ^ 1];
+  const T* hin = (const T*)h->hist[h->cur];
+  T* hout = (T*)h->hist[h->cur ^ 1];
   if (h->G.dim == 2)
-    return launch_step2d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
+    return launch_step2d<S, T>(src, dst, hin, hout, (T*)h->fields, K, Kdev, mode, h->variant,
                                h->closure, h->stream);
-  return launch_step3d<S, T>(src, dst, (T*)h->hist, (T*)h->fields, K, Kdev, mode, h->variant,
+  return launch_step3d<S, T>(src, dst, hin, hout, (T*)h->fields, K, Kdev, mode, h->variant,
                              h->stream);
 }
 
@@ -155,19 +157,19 @@ int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, cons
   hipError_t e;
   switch (h->prm.precision) {
     case CPLB_F64:
-      e = launch_init<double, double>(d, (double*)h->lat[0], (double*)h->hist, da, dc1, dc2, du, dp,
+      e = launch_init<double, double>(d, (double*)h->lat[0], (double*)h->hist[0], da, dc1, dc2, du, dp,
                                       from_sdf, W, cab, h->k64, h->stream);
       break;
     case CPLB_F32:
-      e = launch_init<float, float>(d, (float*)h->lat[0], (float*)h->hist, da, dc1, dc2, du, dp,
+      e = launch_init<float, float>(d, (float*)h->lat[0], (float*)h->hist[0], da, dc1, dc2, du, dp,
                                     from_sdf, W, cab, h->k32, h->stream);
       break;
     case CPLB_F32_S16F:
-      e = launch_init<__half, float>(d, (__half*)h->lat[0], (float*)h->hist, da, dc1, dc2, du, dp,
+      e = launch_init<__half, float>(d, (__half*)h->lat[0], (float*)h->hist[0], da, dc1, dc2, du, dp,
                                      from_sdf, W, cab, h->k32, h->stream);
       break;
     default:
-      e = launch_init<__hip_bfloat16, float>(d, (__hip_bfloat16*)h->lat[0], (float*)h->hist, da,
+      e = launch_init<__hip_bfloat16, float>(d, (__hip_bfloat16*)h->lat[0], (float*)h->hist[0], da,
                                              dc1, dc2, du, dp, from_sdf, W, cab, h->k32, h->stream);
   }
   int rc = hip_check(h, e, "init kernel");
@@ -178,8 +180,9 @@ int do_init(cplb_t* h, const double* a, const double* c1, const double* c2, cons
   return CPLB_OK;
 }
 
-// "CLP2": lattices with the skewed plane layout of the push streaming
-constexpr uint32_t kStateMagic = 0x32504C43u;
+// "CLP3": lattices with the skewed plane layout of the push streaming, f, h1,
+// h2 relative to the history of the node they are stored at
+constexpr uint32_t kStateMagic = 0x33504C43u;
 
 struct StateHeader {
   uint32_t magic, abi;
@@ -221,7 +224,9 @@ int cplb_create(const cplb_params* prm, void* dev_workspace, size_t bytes, void*
   off += G.lat_bytes;
   h->lat[1] = h->ws + off;
   off += G.lat_bytes;
-  h->hist = h->ws + off;
+  h->hist[0] = h->ws + off;
+  off += G.hist_bytes;
+  h->hist[1] = h->ws + off;
   off += G.hist_bytes;
   h->fields = h->ws + off;
   off += G.field_bytes;
@@ -380,7 +385,7 @@ int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes) {
     if (rc) return rc;
   }
   for (int k = 0; k < h->G.nhist; ++k, o += hb) {
-    rc = hip_check(h, hipMemcpy(o, (char*)h->hist + k * h->G.stride * h->G.s_cmp, hb,
+    rc = hip_check(h, hipMemcpy(o, (char*)h->hist[h->cur] + k * h->G.stride * h->G.s_cmp, hb,
                                 hipMemcpyDeviceToHost), "checkpoint copy");
     if (rc) return rc;
   }
@@ -393,7 +398,7 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
   StateHeader hd;
   memcpy(&hd, host_src, sizeof(hd));
   if (hd.magic != kStateMagic || hd.abi != CPLB_ABI_VERSION ||
-      memcmp(&hd.prm, &h->prm, sizeof(cplb_params)) != 0)
+      !same_params(hd.prm, h->prm))
     return set_err(h, CPLB_ESTATE, "checkpoint was written for other parameters%s", "");
   int rc = hip_check(h, hipStreamSynchronize(h->stream), "restore synchronise");
   if (rc) return rc;
@@ -408,7 +413,7 @@ int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes) {
     if (rc) return rc;
   }
   for (int k = 0; k < h->G.nhist; ++k, o += hb) {
-    rc = hip_check(h, hipMemcpy((char*)h->hist + k * h->G.stride * h->G.s_cmp, o, hb,
+    rc = hip_check(h, hipMemcpy((char*)h->hist[0] + k * h->G.stride * h->G.s_cmp, o, hb,
                                 hipMemcpyHostToDevice), "restore copy");
     if (rc) return rc;
   }
@@ -444,15 +449,10 @@ int cplb_set_variant(cplb_t* h, int v) {
 int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step) {
   if (!h) return CPLB_EINVAL;
   if (probe_steps < 1) return set_err(h, CPLB_EINVAL, "probe_steps must be >= 1%s", "");
-  // The probes read the current lattice and write the idle one, which is
-  // scratch; they also overwrite the history, so it is parked in the field
-  // buffer (at least as many planes, same type) and put back afterwards.
-  const size_t hb = (size_t)h->G.nhist * h->G.stride * h->G.s_cmp;
-  int rc = hip_check(h, hipMemcpyAsync(h->fields, h->hist, hb, hipMemcpyDeviceToDevice, h->stream),
-                     "tune: park history");
-  if (rc) return rc;
+  // The probes read the current lattice and history and write only the idle
+  // ones, which are scratch: the state is left as it was.
   hipEvent_t e0, e1;
-  rc = hip_check(h, hipEventCreate(&e0), "tune: event");
+  int rc = hip_check(h, hipEventCreate(&e0), "tune: event");
   if (rc) return rc;
   rc = hip_check(h, hipEventCreate(&e1), "tune: event");
   if (rc) {
@@ -485,9 +485,7 @@ int cplb_tune(cplb_t* h, int probe_steps, double* ms_per_step) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->variant = rc == CPLB_OK ? best : keep;
-  int rc2 = hip_check(h, hipMemcpyAsync(h->hist, h->fields, hb, hipMemcpyDeviceToDevice, h->stream),
-                      "tune: restore history");
-  if (rc2 == CPLB_OK) rc2 = hip_check(h, hipStreamSynchronize(h->stream), "tune: synchronise");
+  const int rc2 = hip_check(h, hipStreamSynchronize(h->stream), "tune: synchronise");
   if (rc) return rc;
   if (rc2) return rc2;
   if (ms_per_step) *ms_per_step = best_ms / probe_steps;

@@ -46,6 +46,35 @@ __global__ __launch_bounds__(256) void init_kernel(S* __restrict__ lat, T* __res
   const T p = in_p ? T(in_p[node]) : T(0);
   T f[LF::Q], g[LG::Q], h1[LF::Q], h2[LF::Q];
   equilibria<LF, LG>(P, T(phi), T(c1), T(c2), u, p, f, g, h1, h2);
+  // The flow population i at a node is read as coming from the node x - c_i
+  // and relative to that node's pressure bracket (the node itself across a
+  // wall): store it so.  g[0] is this node's bracket; a neighbour's is formed
+  // from its initial p by the same arithmetic, as its own rest slot holds it.
+  {
+    constexpr T kpi = T((1.0 - LG::w[0]) / LG::cs2);
+    const T w0 = T(LG::w[0]), inv_w0 = T(1.0 / LG::w[0]);
+    const T pi_own = stored<S, T>(g[0], w0, inv_w0);
+    const int n3[3] = {P.nx, P.ny, P.nz};
+    const long long xyz[3] = {node % P.nx, (node / P.nx) % P.ny, node / ((long long)P.nx * P.ny)};
+#pragma unroll
+    for (int i = 1; i < LG::Q; ++i) {
+      const int c[3] = {LG::cx[i], LG::cy[i], LG::cz[i]};
+      long long src = 0, mul = 1;
+      bool back = false;
+      for (int a = 0; a < 3; ++a) {
+        long long v = xyz[a] - c[a];
+        if (v < 0 || v >= n3[a]) {
+          if (P.wall[a]) back = true;
+          v = v < 0 ? v + n3[a] : v - n3[a];
+        }
+        src += v * mul;
+        mul *= n3[a];
+      }
+      T pi_src = pi_own;
+      if (!back) pi_src = stored<S, T>((in_p ? T(in_p[src]) : T(0)) * kpi, w0, inv_w0);
+      g[i] += kp<LG, T>(i) * (g[0] - pi_src);
+    }
+  }
   const long long st = P.stride;
   const long long pn = pitched(node, P.nx, P.px);  // the node in the planes
 #pragma unroll

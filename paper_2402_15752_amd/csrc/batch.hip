@@ -56,8 +56,8 @@ Layout2 layout(const cplb_params* prm, int n) {
     const Geometry G = geometry(&prm[c]);
     L.reg[c].lat = off;
     off += 2 * G.lat_bytes;
-    L.reg[c].hist = off;
-    off += G.hist_bytes;
+    L.reg[c].hist = off;  // two histories, alternating like the lattices
+    off += 2 * G.hist_bytes;
     L.reg[c].fields = off;
     off += G.field_bytes;
   }
@@ -235,22 +235,6 @@ int compute_fields(cplb_batch_t* b, int icase) {
 
 bool valid_case(const cplb_batch_t* b, int icase) { return b && icase >= 0 && icase < b->n; }
 
-// copy the history planes of every case of a class to (dir 0) or from
-// (dir 1) that case's field planes
-int park_history(cplb_batch_t* b, int cls, int dir) {
-  for (int k = 0; k < b->cls_count[cls]; ++k) {
-    const int c = b->ids[b->cls_first[cls] + k];
-    const Geometry& G = b->G[c];
-    const size_t hb = (size_t)G.nhist * G.stride * G.s_cmp;
-    void* h = b->cases[c].hist;
-    void* f = b->cases[c].fields;
-    int rc = hip_check(b, hipMemcpyAsync(dir ? h : f, dir ? f : h, hb, hipMemcpyDeviceToDevice,
-                                         b->stream), "tune: park history");
-    if (rc) return rc;
-  }
-  return CPLB_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -297,7 +281,8 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
     BatchCase& D = b->cases[c];
     D.lat[0] = b->ws + L.reg[c].lat;
     D.lat[1] = b->ws + L.reg[c].lat + G.lat_bytes;
-    D.hist = b->ws + L.reg[c].hist;
+    D.hist[0] = b->ws + L.reg[c].hist;
+    D.hist[1] = b->ws + L.reg[c].hist + G.hist_bytes;
     D.fields = b->ws + L.reg[c].fields;
     D.nx = prm[c].nx;
     D.ny = prm[c].ny;
@@ -417,19 +402,19 @@ int cplb_batch_init_sdf(cplb_batch_t* b, int icase, const double* l, double c1_a
   hipError_t e;
   switch (b->precision) {
     case CPLB_F64:
-      e = launch_init<double, double>(2, (double*)lat, (double*)D.hist, stage, nullptr, nullptr,
+      e = launch_init<double, double>(2, (double*)lat, (double*)D.hist[b->cur], stage, nullptr, nullptr,
                                       nullptr, nullptr, 1, W, cab, b->k64[icase], b->stream);
       break;
     case CPLB_F32:
-      e = launch_init<float, float>(2, (float*)lat, (float*)D.hist, stage, nullptr, nullptr, nullptr,
+      e = launch_init<float, float>(2, (float*)lat, (float*)D.hist[b->cur], stage, nullptr, nullptr, nullptr,
                                     nullptr, 1, W, cab, b->k32[icase], b->stream);
       break;
     case CPLB_F32_S16F:
-      e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist, stage, nullptr, nullptr,
+      e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist[b->cur], stage, nullptr, nullptr,
                                      nullptr, nullptr, 1, W, cab, b->k32[icase], b->stream);
       break;
     default:
-      e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist, stage, nullptr,
+      e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist[b->cur], stage, nullptr,
                                              nullptr, nullptr, nullptr, 1, W, cab, b->k32[icase],
                                              b->stream);
   }
@@ -466,22 +451,22 @@ int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes
     hipError_t e;
     switch (b->precision) {
       case CPLB_F64:
-        e = launch_init<double, double>(2, (double*)lat, (double*)D.hist, stage, stage + G.n,
+        e = launch_init<double, double>(2, (double*)lat, (double*)D.hist[b->cur], stage, stage + G.n,
                                         stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k64[c],
                                         b->stream);
         break;
       case CPLB_F32:
-        e = launch_init<float, float>(2, (float*)lat, (float*)D.hist, stage, stage + G.n,
+        e = launch_init<float, float>(2, (float*)lat, (float*)D.hist[b->cur], stage, stage + G.n,
                                       stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k32[c],
                                       b->stream);
         break;
       case CPLB_F32_S16F:
-        e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist, stage, stage + G.n,
+        e = launch_init<__half, float>(2, (__half*)lat, (float*)D.hist[b->cur], stage, stage + G.n,
                                        stage + 2 * G.n, nullptr, nullptr, 0, W, cab, b->k32[c],
                                        b->stream);
         break;
       default:
-        e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist, stage,
+        e = launch_init<__hip_bfloat16, float>(2, (__hip_bfloat16*)lat, (float*)D.hist[b->cur], stage,
                                                stage + G.n, stage + 2 * G.n, nullptr, nullptr, 0, W,
                                                cab, b->k32[c], b->stream);
     }
@@ -641,9 +626,8 @@ int cplb_batch_set_variant(cplb_batch_t* b, int cls, int v) {
 int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
   if (!b) return CPLB_EINVAL;
   if (probe_steps < 1) return set_err(b, CPLB_EINVAL, "probe_steps must be >= 1");
-  // Per class: the probes read the current lattices and write the idle
-  // ones (scratch), and overwrite the histories, which are parked in the
-  // field planes and put back.
+  // Per class: the probes read the current lattices and histories and write
+  // only the idle ones (scratch), so the state is left as it was.
   hipEvent_t e0, e1;
   int rc = hip_check(b, hipEventCreate(&e0), "tune: event");
   if (rc) return rc;
@@ -655,8 +639,6 @@ int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
   double total_ms = 0;
   for (int cls = 0; cls < kBatchClasses && rc == CPLB_OK; ++cls) {
     if (b->cls_count[cls] == 0) continue;
-    rc = park_history(b, cls, 0);
-    if (rc) break;
     const int keep = b->variant[cls];
     int best = keep;
     float best_ms = 0;
@@ -679,8 +661,6 @@ int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
     }
     b->variant[cls] = rc == CPLB_OK ? best : keep;
     total_ms += best_ms;
-    const int rc2 = park_history(b, cls, 1);
-    if (!rc) rc = rc2;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, 
   const S* src = (const S*)D->lat[parity];
   S* dst = (S*)D->lat[parity ^ 1];
   const KParams<T>& P = *(const KParams<T>*)(kps + c);
-  step2d_tile<S, T, TX, TY, NTS, MODE, uint32_t>(src, dst, (T*)D->hist, (T*)D->fields, P, G,
+  step2d_tile<S, T, TX, TY, NTS, MODE, uint32_t>(src, dst, (const T*)D->hist[parity],
+                                                 (T*)D->hist[parity ^ 1], (T*)D->fields, P, G,
                                                  tile);
 }
 
@@ -143,8 +144,14 @@ __global__ void gather_moments_kernel(CPtr<BatchCase> cases, KPtr<T> kps, int pa
   load_q<L, false, false>(at(lat, uint32_t(Lay::F0) * sS), sS, node, f);
   load_q<L, false, false>(at(lat, uint32_t(Lay::H10) * sS), sS, node, h1);
   load_q<L, false, false>(at(lat, uint32_t(Lay::H20) * sS), sS, node, h2);
+  // references of the stored populations: the history planes phi, c1, c2
+  const T* hist = (const T*)D->hist[parity];
+  const uint32_t nodeT = node * uint32_t(sizeof(T) / sizeof(S));
+  const T rphi = *at(hist, 2u * D->sT + nodeT);
+  const T rc1 = *at(hist, 3u * D->sT + nodeT);
+  const T rc2 = *at(hist, 4u * D->sT + nodeT);
   Node<T> s{};
-  moments<L>(P, f, h1, h2, s);
+  moments<L>(P, f, h1, h2, rphi, rc1, rc2, s);
   float* out = dst + D->out_off * nplanes + i;
   for (int k = 0; k < nf; ++k) {
     const int id = ids.id[k];

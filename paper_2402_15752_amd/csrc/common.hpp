@@ -7,14 +7,20 @@
 // (chemical potential), F (total force), p, u, rho, mu.
 //
 // Deviation form.  The f, h1, h2 populations are held, stored and streamed
-// as deviations from a uniform reference state, dX_i = X_i - w_i X_ref
-// (X_ref = phi_ref, c1_ref, c2_ref; g needs none, it vanishes at rest).
-// The algebra of the method is unchanged -- X_i - X_i^eq = dX_i - dX_i^eq,
-// streaming and bounce-back move a uniform w_i X_ref onto itself -- but
-// every rounding is now relative to the deviation: phi - phi_ref,
-// 1 - phi = (1 - phi_ref) - dphi and the stencils of phi are formed from
-// small numbers, which keeps FP32 and 16-bit storage accurate in the bulk
-// phases that fill most of the domain.
+// as deviations from a reference, dX_i = X_i - w_i R.  The reference of the
+// populations that arrive at a node is that node's own moment of the
+// previous time level -- phi, c1, c2 as the time-derivative history keeps
+// them -- so the stored values are the change of a population over one
+// step plus its flux part: small numbers, resolved well by FP32 and even by
+// 16-bit storage, and their sum is the change of the moment (phi = R +
+// sum dX_i), which keeps the conserved sums accurate.  A node writing
+// population i to its neighbour y = x + c_i stores X_i* - w_i R(y), with
+// R(y) the neighbour's moment at this level (the stencils already hold it);
+// the reader at y adds back w_i R(y) from its history.  The scalar sets of
+// the one-scalar model and of the local gradient scheme, which have no
+// scalar halo, keep a uniform reference (c1_ref, c2_ref).  g is held
+// relative to a per-node pressure bracket carried in its rest slot (see
+// Flow below).
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -44,11 +50,13 @@ struct KParams {
   T D1D2, KD1, D2, Keq, A, half_A;
   T four_over_W;
   T neps2;            // n_eps^2 of the regularised normal
-  T ref_phi, one_minus_ref_phi, ref_c1, ref_c2;  // reference state of the deviations
+  T ref_c1, ref_c2;   // uniform reference of h1, h2 where they have no per-node one
+  int href;           // 1: h1, h2 stored relative to the node's own c1, c2 (two-scalar,
+                      // central stencil); 0: relative to ref_c1, ref_c2
   int one_scalar;     // 1: one-scalar model, h3 in the h1 planes (Sec. III D)
   T D1K;              // D1 Keq of D_eff = D1 Keq phi + D2 (1 - phi)
   int dirichlet;      // bit f: face f (x-, x+, y-, y+) holds Dirichlet c1, c2
-  T cw[4][2];         // c_wall - c_ref of (c1, c2) at each face
+  T cw[4][2];         // (c1, c2) imposed at each face
   int local_grad;     // 1: grad c_k from the moments of h_k (Eq. (39))
   T itc1, itc2;       // 1 / (tau_hk cs^2)
   T d1w, d2w;         // 4 D_k / W
@@ -86,6 +94,13 @@ struct Codec<__hip_bfloat16, float> {
   __device__ static float ld(__hip_bfloat16 s, float w) { return w * __bfloat162float(s); }
   __device__ static __hip_bfloat16 st(float x, float inv_w) { return __float2bfloat16(x * inv_w); }
 };
+
+// the value a population of weight w stored as x reads back as (x itself
+// for FP64 and FP32 storage)
+template <class S, class T>
+__device__ inline T stored(T x, T w, T inv_w) {
+  return Codec<S, T>::ld(Codec<S, T>::st(x, inv_w), w);
+}
 
 // --------------------------------------------------------------- helpers
 
@@ -142,28 +157,41 @@ struct Node {
 // (Sec. II C).  The implicit recovery c1 = S1 + a e, c2 = S2 - a e with
 // a = A D_m / 2 and e = Keq c2 phi - c1 (1-phi) (Sec. III C) is linear; its
 // exact solution is e = (Keq phi S2 - (1-phi) S1) / (1 + a (Keq phi + 1 - phi)).
+// rphi, rc1, rc2: the references of the node's stored f, h1, h2.
+
+// phi of a node from its stored f: the same additions, in the same order,
+// wherever a kernel needs it (own node, halo node, field read-out), so that
+// every copy of a node's phi is bitwise the value its history keeps
+template <class LF, class T>
+__device__ inline T phase_sum(const T (&df)[LF::Q]) {
+  T s0 = df[0];
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) s0 += df[i];
+  return s0;
+}
+
 template <class LF, class T>
 __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const T (&dh1)[LF::Q],
-                               const T (&dh2)[LF::Q], Node<T>& s) {
-  T s0 = df[0], s1 = dh1[0], s2 = dh2[0];
+                               const T (&dh2)[LF::Q], T rphi, T rc1, T rc2, Node<T>& s) {
+  const T s0 = phase_sum<LF>(df);
+  T s1 = dh1[0], s2 = dh2[0];
 #pragma unroll
   for (int i = 1; i < LF::Q; ++i) {
-    s0 += df[i];
     s1 += dh1[i];
     s2 += dh2[i];
   }
   s.dphi = s0;
-  s.phi = P.ref_phi + s0;
-  s.omphi = P.one_minus_ref_phi - s0;
+  s.phi = rphi + s0;
+  s.omphi = (T(1) - rphi) - s0;
   s.Dm = div_t(P.D1D2, P.KD1 * s.omphi + P.D2 * s.phi);
   const T a = P.half_A * s.Dm;
-  const T S1 = P.ref_c1 + s1, S2 = P.ref_c2 + s2;
+  const T S1 = rc1 + s1, S2 = rc2 + s2;
   const T Kphi = P.Keq * s.phi;
   const T e = div_t(Kphi * S2 - s.omphi * S1, T(1) + a * (Kphi + s.omphi));
   s.dc1 = s1 + a * e;
   s.dc2 = s2 - a * e;
-  s.c1 = P.ref_c1 + s.dc1;
-  s.c2 = P.ref_c2 + s.dc2;
+  s.c1 = rc1 + s.dc1;
+  s.c2 = rc2 + s.dc2;
 }
 
 // One-scalar model (Sec. II D, III D): c = sum h3_i; the phase parts of c at
@@ -172,16 +200,14 @@ __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const 
 // K_eff = Keq phi + 1 - phi; D_eff = D1 Keq phi + D2 (1 - phi) goes to Dm.
 template <class LF, class T>
 __device__ inline void moments_one(const KParams<T>& P, const T (&df)[LF::Q],
-                                   const T (&dh3)[LF::Q], Node<T>& s) {
-  T s0 = df[0], s1 = dh3[0];
+                                   const T (&dh3)[LF::Q], T rphi, Node<T>& s) {
+  const T s0 = phase_sum<LF>(df);
+  T s1 = dh3[0];
 #pragma unroll
-  for (int i = 1; i < LF::Q; ++i) {
-    s0 += df[i];
-    s1 += dh3[i];
-  }
+  for (int i = 1; i < LF::Q; ++i) s1 += dh3[i];
   s.dphi = s0;
-  s.phi = P.ref_phi + s0;
-  s.omphi = P.one_minus_ref_phi - s0;
+  s.phi = rphi + s0;
+  s.omphi = (T(1) - rphi) - s0;
   s.dc = s1;
   s.c = P.ref_c1 + s1;
   s.ct = div_t(s.c, P.Keq * s.phi + s.omphi);
@@ -203,13 +229,24 @@ struct Flow {
   T u[3];
   T F[3];
   T pi;     // bracket of the pressure formula: p = cs^2 / (1 - w0) * pi
+  T dpi;    // its change from the node's reference pi0
+  T j[3];   // momentum rho u = sum c_i g_i + F / 2
   T p, rho, mu, mu_phi;
   T inv_rho;  // 1 / rho
 };
 
+// The flow populations are held relative to the pressure part of the
+// equilibrium, d_i = g_i - v_i pi0 (i > 0, v_i = w_i / (1 - w0)), with pi0
+// the node's pressure bracket of the previous level: the pressure, the
+// largest part of every g_i, then enters the sums and the collision only as
+// the small change pi - pi0, and FP32 rounding stays relative to the flow
+// itself.  The rest population g_0 takes no part in the method (the
+// pressure sums i > 0, the momentum has c_0 = 0), so its slot carries pi0.
+// sum_{i>0} v_i = 1 and sum_i v_i c_i = 0 hold exactly for the weights kp
+// below, so sum_{i>0} g_i = pi0 + sum d_i and sum c_i g_i = sum c_i d_i.
 template <class LG, class T>
 __device__ inline void flow_macros(const KParams<T>& P, const T (&g)[LG::Q], const Node<T>& s,
-                                   const T (&gphi)[3], T lap, Flow<T>& fl) {
+                                   const T (&gphi)[3], T lap, T pi0, Flow<T>& fl) {
   constexpr T cs2 = T(LG::cs2);
   // 4 beta phi (phi-1)(phi-1/2) - k lap phi
   fl.mu_phi = -P.beta4 * s.phi * s.omphi * (s.phi - T(0.5)) - P.kappa * lap;
@@ -229,12 +266,14 @@ __device__ inline void flow_macros(const KParams<T>& P, const T (&g)[LG::Q], con
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     fl.F[a] = fl.mu_phi * gphi[a] + buoy * P.grav[a];
-    fl.u[a] = (m[a] + T(0.5) * fl.F[a]) * inv_rho;
+    fl.j[a] = m[a] + T(0.5) * fl.F[a];
+    fl.u[a] = fl.j[a] * inv_rho;
   }
   const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
   const T udg = fl.u[0] * gphi[0] + fl.u[1] * gphi[1] + fl.u[2] * gphi[2];
   const T s0 = T(LG::w[0]) * (-uu * T(0.5 / LG::cs2));
-  fl.pi = sg + T(0.5) * P.drho * udg + fl.rho * s0;
+  fl.dpi = sg + T(0.5) * P.drho * udg + fl.rho * s0;
+  fl.pi = pi0 + fl.dpi;
   fl.p = T(cs2 / (1.0 - LG::w[0])) * fl.pi;
   if (P.visc_exp)
     fl.mu = exp_t(s.c1 * P.ln_mu1 + s.c2 * P.ln_mu2);
@@ -301,6 +340,41 @@ __device__ inline void normal(const KParams<T>& P, const T (&gphi)[3], T (&n)[3]
   n[2] = gphi[2] * rn;
 }
 
+// True for the direction of each opposite pair whose first nonzero
+// component is positive.
+template <class L>
+__device__ constexpr bool first_of_pair(int i) {
+  return L::cx[i] > 0 || (L::cx[i] == 0 && (L::cy[i] > 0 || (L::cy[i] == 0 && L::cz[i] > 0)));
+}
+
+// Isotropic central gradient (Sec. III C) on the weights of lattice L,
+// grad v = sum_i w_i c_i v(x + c_i) / cs^2, summed over opposite pairs as
+// w_i c_i (v(x + c_i) - v(x - c_i)) / cs^2: the difference of two nearby
+// values is formed first, so the sum is taken of small numbers.  v(i) reads
+// the value at x + c_i.
+template <class L, class T, class V>
+__device__ inline void grad_pairs(V&& v, T (&g)[3]) {
+  g[0] = g[1] = g[2] = T(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    if (!first_of_pair<L>(i)) continue;
+    const T d = v(i) - v(L::opp[i]);
+    const T wc = T(L::w[i] / L::cs2);
+    if (L::cx[i]) g[0] += L::cx[i] > 0 ? wc * d : -(wc * d);
+    if (L::cy[i]) g[1] += L::cy[i] > 0 ? wc * d : -(wc * d);
+    if (L::cz[i]) g[2] += L::cz[i] > 0 ? wc * d : -(wc * d);
+  }
+}
+
+// isotropic Laplacian sum_i 2 w_i (v(x + c_i) - v(x)) / cs^2 (Sec. III C)
+template <class L, class T, class V>
+__device__ inline T lap_of(V&& v, T v0) {
+  T lap = T(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) lap += T(2.0 * L::w[i] / L::cs2) * (v(i) - v0);
+  return lap;
+}
+
 template <class T>
 __device__ inline T relax(T x, T xeq, T del, T hdel, T src) {
   const T neq = x - xeq;
@@ -337,6 +411,9 @@ __device__ inline void collide_f(const KParams<T>& P, const T (&df)[LF::Q], cons
 
 // flow: g^eq = p/cs^2 (w_i - delta_i0) + rho s_i(u),
 //       G_i = w [c.F/cs^2 + (rho1-rho2)(c.u)(c.grad phi)/cs^2], tau_g = 1/2 + mu/(rho cs^2)
+// on d_i = g_i - v_i pi0 (see Flow): d_i^eq = v_i (pi - pi0) + rho s_i; the
+// emitted values are g_i* - v_i pi0, i > 0 (the rest direction is not a
+// population of the method's output: its slot holds the new pi).
 template <class LG, class T, class Emit>
 __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const T (&gphi)[3],
                                  const Flow<T>& fl, Emit&& emit) {
@@ -348,22 +425,22 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
   const T hdel_g = T(0.5) * del_g;
   const T uu = fl.u[0] * fl.u[0] + fl.u[1] * fl.u[1] + fl.u[2] * fl.u[2];
   const T iso = uu * T(0.5) * inv_csg;
-  // p/cs^2 w_i = v_i Pi with Pi the bracket of the pressure formula
+  // p/cs^2 w_i = v_i pi with pi the bracket of the pressure formula; the
+  // first-moment term w_i rho c_i.u / cs^2 is formed from the momentum
+  // j = rho u itself, not from rho times the rounded u, so that the
+  // collision hands the populations their momentum back without the
+  // rounding of u (a bias that otherwise recurs every step)
   auto eq = [&](int i, T cu) {
-    return kp<LG, T>(i) * fl.pi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
-           kw<LG, T>(i) * fl.rho * cu;
+    return kp<LG, T>(i) * fl.dpi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
+           kw<LG, T>(i) * cdot<LG>(i, fl.j);
   };
-  // g_0^eq = p/cs^2 (w0 - 1) + rho s_0 = -Pi - rho w0 u.u/(2 cs^2): its
-  // pressure part is exactly -sum_{i>0} v_i Pi, the rounded-weight residue
-  // is left only in the O(u^2) term
-  const T rest = -fl.pi - T(LG::w[0]) * fl.rho * iso;
 #pragma unroll
-  for (int i = 0; i < LG::Q; ++i) {
+  for (int i = 1; i < LG::Q; ++i) {
     const T cu = cdot<LG>(i, fl.u);
     const T cF = cdot<LG>(i, fl.F);
     const T cg = cdot<LG>(i, gphi);
-    const T Gi = i == 0 ? T(0) : kw<LG, T>(i) * (cF + P.drho * cu * cg);
-    emit(i, relax(g[i], i == 0 ? rest : eq(i, cu), del_g, hdel_g, Gi));
+    const T Gi = kw<LG, T>(i) * (cF + P.drho * cu * cg);
+    emit(i, relax(g[i], eq(i, cu), del_g, hdel_g, Gi));
   }
 }
 
@@ -448,41 +525,21 @@ __device__ inline void collide(const KParams<T>& P, const T (&df)[LF::Q], const 
   collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h, xs);
 }
 
-// In-place form (post-collision values written back into the arrays).
-template <class LF, class LG, class T>
-__device__ inline void collide(const KParams<T>& P, T (&df)[LF::Q], T (&g)[LG::Q],
-                               T (&dh1)[LF::Q], T (&dh2)[LF::Q], const Node<T>& s,
-                               const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
-                               const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3]) {
-  T of[LF::Q], og[LG::Q], o1[LF::Q], o2[LF::Q];
-  collide<LF, LG>(P, df, g, dh1, dh2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
-                  [&](int i, T v) { of[i] = v; }, [&](int i, T v) { og[i] = v; },
-                  [&](int i, T a, T b) {
-                    o1[i] = a;
-                    o2[i] = b;
-                  });
-#pragma unroll
-  for (int i = 0; i < LF::Q; ++i) {
-    df[i] = of[i];
-    dh1[i] = o1[i];
-    dh2[i] = o2[i];
-  }
-#pragma unroll
-  for (int i = 0; i < LG::Q; ++i) g[i] = og[i];
-}
-
 // ------------------------------------------------------------- equilibria
-// Equilibrium populations of the initial fields, as deviations (init only).
+// Equilibrium populations of the initial fields, as deviations from the
+// node's own references (init only): the node's initial phi and, with
+// per-node scalar references, its initial c1, c2.
 template <class LF, class LG, class T>
 __device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const T (&u)[3], T p,
                                   T (&df)[LF::Q], T (&g)[LG::Q], T (&dh1)[LF::Q],
                                   T (&dh2)[LF::Q]) {
+  const T rc1 = P.href ? c1 : P.ref_c1, rc2 = P.href ? c2 : P.ref_c2;
   constexpr T inv_csf = T(1.0 / LF::cs2);
   constexpr T inv_csg = T(1.0 / LG::cs2);
   constexpr T half_inv_csg2 = T(0.5 / (LG::cs2 * LG::cs2));
   const T rho = phi * P.drho + P.rho2;
   const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const T dphi = phi - P.ref_phi, dc1 = c1 - P.ref_c1, dc2 = c2 - P.ref_c2;
+  const T dphi = T(0), dc1 = c1 - rc1, dc2 = c2 - rc2;
   // one-scalar model: h3 (in the h1 slot) of c = c1 + c2, h2 = 0
   const T c = c1 + c2;
   const T dct = c / (P.Keq * phi + (T(1) - phi)) - P.ref_c1;
@@ -501,11 +558,13 @@ __device__ inline void equilibria(const KParams<T>& P, T phi, T c1, T c2, const 
     }
   }
   if (P.one_scalar) dh1[0] = rest3;
+  // flow set relative to the pressure part of its equilibrium (see Flow):
+  // d_i = rho s_i(u), and the rest slot holds pi = (1 - w0) p / cs^2
+  g[0] = p * T((1.0 - LG::w[0]) / LG::cs2);
 #pragma unroll
-  for (int i = 0; i < LG::Q; ++i) {
+  for (int i = 1; i < LG::Q; ++i) {
     const T cu = cdot<LG>(i, u);
-    const T si = T(LG::w[i]) * (cu * inv_csg + cu * cu * half_inv_csg2 - uu * T(0.5) * inv_csg);
-    g[i] = p * inv_csg * (i == 0 ? T(LG::w[0] - 1.0) : T(LG::w[i])) + rho * si;
+    g[i] = rho * (T(LG::w[i]) * (cu * inv_csg + cu * cu * half_inv_csg2 - uu * T(0.5) * inv_csg));
   }
 }
 

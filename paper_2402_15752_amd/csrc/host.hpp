@@ -120,7 +120,11 @@ inline Geometry geometry(const cplb_params* p) {
   G.field_bytes = align_up((size_t)kNumFields * G.stride * G.s_cmp, kAlign);
   G.part_bytes = align_up((size_t)(kReduceBlocks + 1) * 8 * sizeof(double), kAlign);
   G.kp_bytes = align_up(sizeof(KParams<double>), kAlign) + align_up(sizeof(KParams<float>), kAlign);
-  G.total = 2 * G.lat_bytes + G.hist_bytes + G.field_bytes + G.part_bytes + G.kp_bytes;
+  // two histories, alternating like the two lattices: a step reads the
+  // previous level's (u, phi, c1, c2) -- the references of the populations it
+  // reads, also at the halo nodes other work-groups own -- from one and writes
+  // this level's to the other
+  G.total = 2 * G.lat_bytes + 2 * G.hist_bytes + G.field_bytes + G.part_bytes + G.kp_bytes;
   return G;
 }
 
@@ -193,17 +197,20 @@ KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
   K.itc2 = T(1.0 / (tau_h2 * csf));
   K.d1w = T(4.0 * p->D1 / p->W);
   K.d2w = T(4.0 * p->D2 / p->W);
-  // Dirichlet faces x-, x+, y-, y+ (bit f) and their values as deviations
+  // Dirichlet faces x-, x+, y-, y+ (bit f) and their values
   K.dirichlet = 0;
   for (int f = 0; f < 4; ++f) {
     if (f / 2 < G.dim && p->scalar_bc[f] == CPLB_BC_DIRICHLET) K.dirichlet |= 1 << f;
-    K.cw[f][0] = T(p->c_wall[f][0] - p->ref[2]);
-    K.cw[f][1] = T(p->c_wall[f][1] - p->ref[3]);
+    K.cw[f][0] = T(p->c_wall[f][0]);
+    K.cw[f][1] = T(p->c_wall[f][1]);
   }
   K.neps2 = T(p->n_eps * p->n_eps);
-  // reference state of the stored deviations (f, h1, h2; g is stored as is)
-  K.ref_phi = T(p->ref[0]);
-  K.one_minus_ref_phi = T(1.0 - p->ref[0]);
+  // references of the stored deviations: f always, and h1, h2 of the
+  // two-scalar model with the central stencil, are stored relative to the
+  // node's own phi, c1, c2 of the previous level; h1, h2 of the one-scalar
+  // model and of the local gradient scheme (no scalar halo) relative to the
+  // uniform ref[2], ref[3]; g is stored as is
+  K.href = p->scalar_model == CPLB_TWO_SCALAR && p->scalar_grad == CPLB_GRAD_CENTRAL;
   K.ref_c1 = T(p->ref[2]);
   K.ref_c2 = T(p->ref[3]);
   return K;

@@ -41,22 +41,23 @@ const char* step3d_variant_name(int v);
 
 // closure: per-node extra exchange added to the auxiliary scalar source
 // (N FP32 values in node order), or null
+// hin: history of the previous level (read), hout: this level's (written)
 template <class S, class T>
-hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_step2d(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, const float* closure,
                          hipStream_t stream);
 
 // P: host copy of the lattice constants (grid, launch shape); Pdev: the same
 // constants in device memory, read by the kernel
 template <class S, class T>
-hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_step3d(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream);
 
 // One case of a batch of independent 2-D lattices, as the batched kernel
 // reads it from device memory.
 struct BatchCase {
   const void* lat[2];  // the two population lattices (parity 0 reads lat[0])
-  void* hist;          // history planes
+  void* hist[2];       // the two histories (parity 0 reads hist[0], writes hist[1])
   void* fields;        // field planes
   int nx, ny;
   int px;              // row pitch (nodes between two rows of a plane)
@@ -130,7 +131,9 @@ hipError_t cnn_weights(const float* W, int cin, int cout, unsigned short* Wg, un
 
 // equilibrium initialisation from FP64 staging arrays in device memory:
 // phi (or the signed distance when from_sdf), c1, c2, u (d planes) and p,
-// each N values; u / p may be null.
+// each N values; u / p may be null.  hist receives the initial (u, phi, c1,
+// c2): the history the first step reads, and the references of the stored
+// populations.
 template <class S, class T>
 hipError_t launch_init(int dim, S* lat, T* hist, const double* phi_or_l, const double* c1,
                        const double* c2, const double* u, const double* p, int from_sdf,

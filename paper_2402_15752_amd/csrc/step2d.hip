@@ -31,7 +31,9 @@ using Lay = Layout<D2Q9, D2Q9>;
 // arguments stay a few dozen bytes.
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL>
 __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ src,
-                                                        S* __restrict__ dst, T* __restrict__ hist,
+                                                        S* __restrict__ dst,
+                                                        const T* __restrict__ hin,
+                                                        T* __restrict__ hout,
                                                         T* __restrict__ fields, KPtr<T> Pg,
                                                         Geo2<Off> G) {
   // XCD-aware tile order: work-groups are dealt round-robin to the 8 XCDs
@@ -41,11 +43,12 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= G.ntiles) return;
-  step2d_tile<S, T, TX, TY, NTS, MODE, Off, MODEL>(src, dst, hist, fields, params(Pg), G, tile);
+  step2d_tile<S, T, TX, TY, NTS, MODE, Off, MODEL>(src, dst, hin, hout, fields, params(Pg), G,
+                                                   tile);
 }
 
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL>
-hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, const float* closure, hipStream_t stream) {
   Geo2<Off> G;
   G.nx = P.nx;
@@ -60,7 +63,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.closure = closure;
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
   hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off, MODEL>), dim3(nblocks), dim3(TX * TY),
-                     0, stream, src, dst, hist, fields, (KPtr<T>)Pdev, G);
+                     0, stream, src, dst, hin, hout, fields, (KPtr<T>)Pdev, G);
   return hipGetLastError();
 }
 
@@ -77,7 +80,7 @@ namespace {
 
 // the variant switch of one scalar-model variant (kModel*)
 template <class S, class T, int MODEL>
-hipError_t launch_model(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_model(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                         const KParams<T>* Pdev, int mode, int variant, const float* closure,
                         hipStream_t stream) {
   constexpr int M = kModeStep;
@@ -85,56 +88,57 @@ hipError_t launch_model(const S* src, S* dst, T* hist, T* fields, const KParams<
   if (!fits_u32(L::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t, MODEL>(src, dst, hist, fields,
+      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t, MODEL>(src, dst, hin, hout, fields,
                                                                            P, Pdev, closure, stream);
-    return launch_variant<S, T, 128, 4, false, M, uint64_t, MODEL>(src, dst, hist, fields, P,
+    return launch_variant<S, T, 128, 4, false, M, uint64_t, MODEL>(src, dst, hin, hout, fields, P,
                                                                 Pdev, closure, stream);
   }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, kModeMacros, U, MODEL>(src, dst, hist, fields, P,
+    return launch_variant<S, T, 64, 4, false, kModeMacros, U, MODEL>(src, dst, hin, hout, fields, P,
                                                                   Pdev, closure, stream);
   switch (variant) {
-    case 1: return launch_variant<S, T, 32, 8, false, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 2: return launch_variant<S, T, 32, 4, false, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 3: return launch_variant<S, T, 128, 4, false, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 4: return launch_variant<S, T, 64, 4, true, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 5: return launch_variant<S, T, 32, 8, true, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 6: return launch_variant<S, T, 32, 4, true, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    case 7: return launch_variant<S, T, 128, 4, true, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
-    default: return launch_variant<S, T, 64, 4, false, M, U, MODEL>(src, dst, hist, fields, P, Pdev, closure, stream);
+    case 1: return launch_variant<S, T, 32, 8, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 2: return launch_variant<S, T, 32, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 3: return launch_variant<S, T, 128, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 4: return launch_variant<S, T, 64, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 5: return launch_variant<S, T, 32, 8, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 6: return launch_variant<S, T, 32, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 7: return launch_variant<S, T, 128, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    default: return launch_variant<S, T, 64, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
   }
 }
 
 }  // namespace
 
 template <class S, class T>
-hipError_t launch_step2d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_step2d(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, const float* closure,
                          hipStream_t stream) {
   if (P.one_scalar)
-    return launch_model<S, T, kModelOne>(src, dst, hist, fields, P, Pdev, mode, variant, nullptr,
+    return launch_model<S, T, kModelOne>(src, dst, hin, hout, fields, P, Pdev, mode, variant, nullptr,
                                          stream);
   if (P.local_grad)
-    return launch_model<S, T, kModelTwoLocal>(src, dst, hist, fields, P, Pdev, mode, variant,
+    return launch_model<S, T, kModelTwoLocal>(src, dst, hin, hout, fields, P, Pdev, mode, variant,
                                               closure, stream);
   if (P.dirichlet)
-    return launch_model<S, T, kModelTwoDirichlet>(src, dst, hist, fields, P, Pdev, mode, variant,
+    return launch_model<S, T, kModelTwoDirichlet>(src, dst, hin, hout, fields, P, Pdev, mode, variant,
                                                   closure, stream);
-  return launch_model<S, T, kModelTwo>(src, dst, hist, fields, P, Pdev, mode, variant, closure,
+  return launch_model<S, T, kModelTwo>(src, dst, hin, hout, fields, P, Pdev, mode, variant, closure,
                                        stream);
 }
 
-template hipError_t launch_step2d<double, double>(const double*, double*, double*, double*,
+template hipError_t launch_step2d<double, double>(const double*, double*, const double*, double*, double*,
                                                   const KParams<double>&, const KParams<double>*,
                                                   int, int, const float*, hipStream_t);
-template hipError_t launch_step2d<float, float>(const float*, float*, float*, float*,
+template hipError_t launch_step2d<float, float>(const float*, float*, const float*, float*, float*,
                                                 const KParams<float>&, const KParams<float>*,
                                                 int, int, const float*, hipStream_t);
-template hipError_t launch_step2d<__half, float>(const __half*, __half*, float*, float*,
+template hipError_t launch_step2d<__half, float>(const __half*, __half*, const float*, float*, float*,
                                                  const KParams<float>&, const KParams<float>*,
                                                 int, int, const float*, hipStream_t);
 template hipError_t launch_step2d<__hip_bfloat16, float>(const __hip_bfloat16*, __hip_bfloat16*,
-                                                         float*, float*, const KParams<float>&,
+                                                         const float*, float*, float*,
+                                                         const KParams<float>&,
                                                          const KParams<float>*, int, int,
                                                          const float*, hipStream_t);
 

@@ -4,13 +4,20 @@
 //   1. every global load the thread needs is issued first: f, h1, h2 of its
 //      node (27 values, coalesced along x), its g populations and history,
 //      and f, h1, h2 of at most one node of the halo ring around the tile
-//      (re-read from L2: the neighbouring tile ran on the same XCD);
-//   2. the deviations of phi and psi = c1 + Keq c2 of the tile and its halo
-//      go to LDS;
+//      with that node's history references (re-read from L2: the
+//      neighbouring tile ran on the same XCD);
+//   2. phi, c1, c2 of the tile and its halo go to LDS;
 //   3. after one barrier each thread takes the 9-point gradient / Laplacian
 //      stencils from LDS, collides all four sets and pushes the
 //      post-collision values to x + c_i of the other lattice (periodic wrap
-//      or half-way bounce-back).
+//      or half-way bounce-back), each f, h1, h2 value relative to the
+//      moments of the node it lands on (read from the same LDS).
+//
+// Two histories alternate like the two lattices: the step reads the
+// previous level's (u, phi, c1, c2) from `hin` -- at its own nodes for the
+// time derivatives and the references, at the halo nodes for their
+// references -- and writes this level's to `hout`, so no work-group
+// overwrites a value another one may still read.
 #pragma once
 
 #include "addr.hpp"
@@ -38,18 +45,22 @@ struct Geo2 {
 // (a compiled variant: the check costs the plain step ~5%).
 template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL = kModelTwo>
 __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ dst,
-                                   T* __restrict__ hist, T* __restrict__ fields,
-                                   const KParams<T>& P, const Geo2<Off>& G, int tile) {
+                                   const T* __restrict__ hin, T* __restrict__ hout,
+                                   T* __restrict__ fields, const KParams<T>& P, const Geo2<Off>& G,
+                                   int tile) {
   using L = D2Q9;
   using Lay = Layout<D2Q9, D2Q9>;
   constexpr bool ONE = MODEL == kModelOne;
   constexpr bool LOC = MODEL == kModelTwoLocal;  // no psi stencil, no h halo
+  // the scalar halo: psi stencil, and h1, h2 stored relative to the node's own c1, c2
   constexpr bool HALO_H = !ONE && !LOC;
   constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
   constexpr Off BS = sizeof(S);
   __shared__ T sphi[LY][LX];
-  __shared__ T spsi[LY][LX];
+  __shared__ T spi[LY][LX];  // pressure brackets: the references of the flow set
+  __shared__ T sc1[HALO_H ? LY : 1][LX];
+  __shared__ T sc2[HALO_H ? LY : 1][LX];
 
   const int x0 = (tile % G.tiles_x) * TX;
   const int y0 = (tile / G.tiles_x) * TY;
@@ -79,77 +90,98 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
     halo = gx <= nx && gy <= ny;  // beyond a ragged tile no node reads it
     halo_node = Off(fold(gy, ny, G.wall_y) * G.px + fold(gx, nx, G.wall_x)) * BS;
   }
+  const Off halo_nodeT = halo_node * Off(sizeof(T) / sizeof(S));
+
+  // history planes: ux, uy, phi, c1, c2 (one-scalar: ux, uy, phi, c)
+  constexpr int kPhi = 2, kC1 = 3, kC2 = 4;
+  constexpr int NH = ONE ? kHist2D - 1 : kHist2D;
 
   // ---- 1. all global loads first
   T f[9], h1[9], h2[9], g[9], hf[9], hh1[9], hh2[9];
   T hs[kHist2D];
-  constexpr int NH = ONE ? kHist2D - 1 : kHist2D;  // one-scalar: (ux, uy, phi, c)
+  T hr[3] = {T(0), T(0), T(0)};  // references (phi, c1, c2) of the halo node
+  T hpi = T(0);                  // and its pressure bracket (rest slot of g)
   if (own_slot) {
     load_q<L, NTS, false>(sF, G.sS, node, f);
     load_q<L, NTS, false>(sH1, G.sS, node, h1);
     if (!ONE) load_q<L, NTS, false>(sH2, G.sS, node, h2);
-  }
-  if (active) {
     load_q<L, NTS, false>(sG, G.sS, node, g);
 #pragma unroll
-    for (int k = 0; k < NH; ++k) hs[k] = *at(hist, plane<false>(k, G.sT) + nodeT);
+    for (int k = 0; k < NH; ++k) hs[k] = *at(hin, plane<false>(k, G.sT) + nodeT);
   }
   if (halo) {
     load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
+    hpi = Codec<S, T>::ld(ld_pop<NTS>(at(sG, halo_node)), T(L::w[0]));
+    hr[0] = *at(hin, plane<false>(kPhi, G.sT) + halo_nodeT);
     if (HALO_H) {
       load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
       load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
+      hr[1] = *at(hin, plane<false>(kC1, G.sT) + halo_nodeT);
+      hr[2] = *at(hin, plane<false>(kC2, G.sT) + halo_nodeT);
     }
   }
 
-  // ---- 2. moments to LDS (deviations: the stencils only take differences
-  //         and zero-sum weighted sums)
+  // ---- 2. moments to LDS
   Node<T> s{};
   if (own_slot) {
     if constexpr (ONE) {
-      moments_one<L>(P, f, h1, s);
+      moments_one<L>(P, f, h1, hs[kPhi], s);
     } else {
-      moments<L>(P, f, h1, h2, s);
-      if (HALO_H) spsi[ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+      moments<L>(P, f, h1, h2, hs[kPhi], HALO_H ? hs[kC1] : P.ref_c1, HALO_H ? hs[kC2] : P.ref_c2,
+                 s);
+      if (HALO_H) {
+        sc1[ty + 1][tx + 1] = s.c1;
+        sc2[ty + 1][tx + 1] = s.c2;
+      }
     }
-    sphi[ty + 1][tx + 1] = s.dphi;
+    sphi[ty + 1][tx + 1] = s.phi;
+    spi[ty + 1][tx + 1] = g[0];
   }
   if (halo) {
+    spi[hy + 1][hx + 1] = hpi;
     if constexpr (!HALO_H) {
-      T d = hf[0];
-#pragma unroll
-      for (int i = 1; i < 9; ++i) d += hf[i];
-      sphi[hy + 1][hx + 1] = d;
+      sphi[hy + 1][hx + 1] = hr[0] + phase_sum<L>(hf);
     } else {
       Node<T> q;
-      moments<L>(P, hf, hh1, hh2, q);
-      sphi[hy + 1][hx + 1] = q.dphi;
-      spsi[hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+      moments<L>(P, hf, hh1, hh2, hr[0], hr[1], hr[2], q);
+      sphi[hy + 1][hx + 1] = q.phi;
+      sc1[hy + 1][hx + 1] = q.c1;
+      sc2[hy + 1][hx + 1] = q.c2;
     }
   }
   __syncthreads();
   if (!active) return;
 
   // ---- 3. isotropic central stencils (Sec. III C) on D2Q9 weights
-  T gphi[3] = {0, 0, 0}, gpsi[3] = {0, 0, 0}, lap = 0;
+  auto nb = [&](const T (&a)[HALO_H ? LY : 1][LX], int i) -> T {
+    return a[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
+  };
+  auto nbp = [&](int i) -> T { return sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]]; };
+  T gphi[3], gpsi[3] = {T(0), T(0), T(0)};
+  grad_pairs<L, T>(nbp, gphi);
+  const T lap = lap_of<L, T>(nbp, s.phi);
+  if constexpr (HALO_H) {
+    // grad psi = grad c1 + Keq grad c2 (psi = c1 + Keq c2)
+    T gc1[3], gc2[3];
+    grad_pairs<L, T>([&](int i) { return nb(sc1, i); }, gc1);
+    grad_pairs<L, T>([&](int i) { return nb(sc2, i); }, gc2);
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const T a = sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
-    const T b = HALO_H ? spsi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]] : T(0);
-    const T wc = T(L::w[i] / L::cs2);
-    if (L::cx[i]) {
-      gphi[0] += wc * T(L::cx[i]) * a;
-      gpsi[0] += wc * T(L::cx[i]) * b;
-    }
-    if (L::cy[i]) {
-      gphi[1] += wc * T(L::cy[i]) * a;
-      gpsi[1] += wc * T(L::cy[i]) * b;
-    }
-    lap += T(2) * wc * (a - s.dphi);
+    for (int a = 0; a < 2; ++a) gpsi[a] = gc1[a] + P.Keq * gc2[a];
   }
 
+  // the flow populations relative to the own pressure bracket pi0: a value
+  // arriving from x - c_i was stored relative to the bracket of that node
+  // (of the node itself when the link bounced off a wall)
+  const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
+  const T pi0 = g[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const bool back = (push.bits & link_mask(-L::cx[i], -L::cy[i], 0)) != 0;
+    const T src = back ? pi0 : spi[ty + 1 - L::cy[i]][tx + 1 - L::cx[i]];
+    g[i] += kp<L, T>(i) * (src - pi0);
+  }
   Flow<T> fl;
-  flow_macros<L>(P, g, s, gphi, lap, fl);
+  flow_macros<L>(P, g, s, gphi, lap, pi0, fl);
 
   if (MODE == kModeMacros) {
     auto put_field = [&](int k, T v) { *at(fields, plane<false>(k, G.sT) + nodeT) = v; };
@@ -168,47 +200,69 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   // backward-difference time derivatives against the history (R1); the
   // one-scalar model keeps c in the c1 slot
   const T cA = ONE ? s.c : s.c1;
-  const T dJphi[3] = {s.phi * fl.u[0] - hs[2] * hs[0], s.phi * fl.u[1] - hs[2] * hs[1], T(0)};
-  const T dJ1[3] = {cA * fl.u[0] - hs[3] * hs[0], cA * fl.u[1] - hs[3] * hs[1], T(0)};
+  const T dJphi[3] = {s.phi * fl.u[0] - hs[kPhi] * hs[0], s.phi * fl.u[1] - hs[kPhi] * hs[1], T(0)};
+  const T dJ1[3] = {cA * fl.u[0] - hs[kC1] * hs[0], cA * fl.u[1] - hs[kC1] * hs[1], T(0)};
   T dJ2[3] = {T(0), T(0), T(0)};
   if constexpr (!ONE) {
-    dJ2[0] = s.c2 * fl.u[0] - hs[4] * hs[0];
-    dJ2[1] = s.c2 * fl.u[1] - hs[4] * hs[1];
+    dJ2[0] = s.c2 * fl.u[0] - hs[kC2] * hs[0];
+    dJ2[1] = s.c2 * fl.u[1] - hs[kC2] * hs[1];
   }
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const T v = k < 2 ? fl.u[k] : (k == 2 ? s.phi : (k == 3 ? cA : s.c2));
-    *at(hist, plane<false>(k, G.sT) + nodeT) = v;
+    const T v = k < 2 ? fl.u[k] : (k == kPhi ? s.phi : (k == kC1 ? cA : s.c2));
+    *at(hout, plane<false>(k, G.sT) + nodeT) = v;
   }
 
   // push streaming: X_i(x + c_i) <- X_i*(x), or half-way bounce-back into
   // the opposite slot of the own node when the link crosses a wall; each
   // post-collision value is stored as soon as it is formed
-  const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
+  auto bounced = [&](int i) { return (push.bits & link_mask(L::cx[i], L::cy[i], 0)) != 0; };
   auto target = [&](int i) -> Off {
     const int cx = L::cx[i], cy = L::cy[i];
     Off t = node;
     if (cx) t += cx < 0 ? push.dxm : push.dxp;
     if (cy) t += cy < 0 ? push.dym : push.dyp;
-    return (push.bits & link_mask(cx, cy, 0))
-               ? plane<false>(L::opp[i], G.sS) + node + skew<L, S, Off>(L::opp[i])
-               : plane<false>(i, G.sS) + t + skew<L, S, Off>(i);
+    return bounced(i) ? plane<false>(L::opp[i], G.sS) + node + skew<L, S, Off>(L::opp[i])
+                      : plane<false>(i, G.sS) + t + skew<L, S, Off>(i);
+  };
+  // The collisions emit X_i* - w_i R(x), R(x) the node's own reference (its
+  // moment at the previous level); the value stored at the target y is
+  // X_i* - w_i R'(y), with R'(y) the moment of y at this level, which y's
+  // history will hold when the value is read: the neighbour's for a pushed
+  // link, the node's own new moment for the rest direction and for a bounced
+  // link (both return to x).  `ring` is the LDS array of that moment.
+  auto rebase = [&](int i, T v, T rown, const T (&ring)[HALO_H ? LY : 1][LX]) -> T {
+    const T rt = bounced(i) ? ring[ty + 1][tx + 1] : ring[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
+    return v + T(L::w[i]) * (rown - rt);
+  };
+  auto rebase_phi = [&](int i, T v, T rown) -> T {
+    const T rt = bounced(i) ? s.phi : sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]];
+    return v + T(L::w[i]) * (rown - rt);
   };
   S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
   S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
   S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
   S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
+  const T rphi = hs[kPhi];
+  auto emit_f = [&](int i, T v) {
+    st_pop<NTS>(at(dF, target(i)),
+                Codec<S, T>::st(rebase_phi(i, v, rphi), T(1.0 / L::w[i])));
+  };
+  // flow set: the new bracket pi, as stored, is the reference of the values
+  // this node emits and goes to its own rest slot
+  const T pi_st = stored<S, T>(fl.pi, T(L::w[0]), T(1.0 / L::w[0]));
+  st_pop<NTS>(at(dG, target(0)), Codec<S, T>::st(fl.pi, T(1.0 / L::w[0])));
+  auto emit_g = [&](int i, T v) {
+    st_pop<NTS>(at(dG, target(i)),
+                Codec<S, T>::st(v + kp<L, T>(i) * (pi0 - pi_st), T(1.0 / L::w[i])));
+  };
   // Dirichlet faces this node's links reach (0 for every interior node)
   const int dmask = MODEL == kModelTwoDirichlet ? push.bits & P.dirichlet : 0;
   if constexpr (ONE) {
     T n[3];
     normal(P, gphi, n);
-    collide_g<L>(P, g, gphi, fl, [&](int i, T v) {
-      st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
-    });
-    collide_f<L>(P, f, s, n, fl, dJphi, [&](int i, T v) {
-      st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
-    });
+    collide_g<L>(P, g, gphi, fl, emit_g);
+    collide_f<L>(P, f, s, n, fl, dJphi, emit_f);
     collide_h3<L>(P, h1, s, fl, dJ1, [&](int i, T v) {
       st_pop<NTS>(at(dH1, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
     });
@@ -239,21 +293,25 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
       gpsi[a] = g1 + P.Keq * g2;
     }
   }
+  const T rc1 = HALO_H ? hs[kC1] : T(0), rc2 = HALO_H ? hs[kC2] : T(0);
   collide<L, L>(
-      P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2,
-      [&](int i, T v) { st_pop<NTS>(at(dF, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
-      [&](int i, T v) { st_pop<NTS>(at(dG, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i]))); },
+      P, f, g, h1, h2, s, gphi, gpsi, fl, dJphi, dJ1, dJ2, emit_f, emit_g,
       [&](int i, T a, T b) {
         const Off t = target(i);
+        if constexpr (HALO_H) {
+          a = rebase(i, a, rc1, sc1);
+          b = rebase(i, b, rc2, sc2);
+        }
         // half-way anti-bounce-back at a Dirichlet face (the x face first at a
-        // corner): h_opp(i) = -h_i* + 2 w_i c_wall, on the deviations
+        // corner): h_opp(i) = -h_i* + 2 w_i c_wall; the link returns to the own
+        // node, so relative to its new c1, c2 (the bounced value already is)
         if (MODEL == kModelTwoDirichlet && dmask) {
           const int hit = push.bits & link_mask(L::cx[i], L::cy[i], 0);
           if (hit & dmask) {
             const int f = (hit & 1) ? 0 : (hit & 2) ? 1 : (hit & 4) ? 2 : 3;
             if ((dmask >> f) & 1) {
-              a = T(2.0 * L::w[i]) * P.cw[f][0] - a;
-              b = T(2.0 * L::w[i]) * P.cw[f][1] - b;
+              a = T(2.0 * L::w[i]) * (P.cw[f][0] - s.c1) - a;
+              b = T(2.0 * L::w[i]) * (P.cw[f][1] - s.c2) - b;
             }
           }
         }

@@ -3,17 +3,21 @@
 //
 // One launch = one time step.  A work-group owns a TX x TY column tile and
 // marches along z over a chunk of planes.  LDS holds a ring of four
-// planes of the deviations of phi and psi = c1 + Keq c2 over the tile and
-// its one-node halo.  Per plane z the group
-//   1. loads f, h1, h2 (21 values) of its own nodes at z+1 -- kept in
-//      registers for the next plane -- and of at most one halo node at z+1
-//      (re-read from L2: neighbouring tiles march the same planes on the
-//      same XCD); the prefetching variants also load g and history of plane
-//      z here, before the barrier;
+// planes of phi, c1 and c2 over the tile and its one-node halo.  Per plane
+// z the group
+//   1. loads f, h1, h2 (21 values) and their references (phi, c1, c2 of
+//      the previous level, from the history) of its own nodes at z+1 --
+//      kept in registers for the next plane -- and of at most one halo node
+//      at z+1 (re-read from L2: neighbouring tiles march the same planes on
+//      the same XCD); the prefetching variants also load g and the velocity
+//      history of plane z here, before the barrier;
 //   2. puts the moments of plane z+1 in the ring, then one barrier;
 //   3. collides plane z: 19-point stencils from ring planes z-1, z, z+1,
 //      all four sets collided and pushed to x + c_i of the other lattice
-//      (periodic wrap or half-way bounce-back).
+//      (periodic wrap or half-way bounce-back), each f, h1, h2 value
+//      relative to the moments of the node it lands on (read from the ring).
+// The histories alternate like the lattices (read `hin`, write `hout`), so
+// no work-group overwrites a reference another one still reads.
 // With four ring slots a plane's slot is reused two barriers after its last
 // reader, so one barrier per plane suffices.  Interior moments are computed
 // once per node; only the halo ring and the first two planes of a chunk are
@@ -62,16 +66,23 @@ __device__ inline int slot_of(int z) { return (z + 4) & 3; }
 
 template <class T, int TX, int TY, bool PSI>
 struct Ring {
+  // phi, c1, c2 of four planes over the tile and its halo, exactly the
+  // values the nodes' histories keep (the references of their populations)
   T phi[4][TY + 2][TX + 2];
-  T psi[PSI ? 4 : 1][TY + 2][TX + 2];  // no psi ring with the local gradient scheme
+  T pi[4][TY + 2][TX + 2];  // pressure brackets: the references of the flow set
+  T c1[PSI ? 4 : 1][TY + 2][TX + 2];  // no scalar ring with the local gradient scheme
+  T c2[PSI ? 4 : 1][TY + 2][TX + 2];
 };
 
 // LOC: grad(c1 + Keq c2) by the local scheme of Eq. (39) from the own h1, h2
-// of the plane being collided -- no psi ring, no h1, h2 of the halo.
+// of the plane being collided -- no scalar ring, no h1, h2 of the halo; h1,
+// h2 then keep the uniform reference (c1_ref, c2_ref).
 template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off,
           bool LOC>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
-                                                        S* __restrict__ dst, T* __restrict__ hist,
+                                                        S* __restrict__ dst,
+                                                        const T* __restrict__ hin,
+                                                        T* __restrict__ hout,
                                                         T* __restrict__ fields,
                                                         KPtr<T> Pg, Geo3<Off> G) {
   constexpr int NTH = TX * TY, LX = TX + 2, NHALO = 2 * LX + 2 * TY;
@@ -79,6 +90,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // non-temporal hints: bit 0 f / h loads, bit 1 stores, bit 2 g loads
   constexpr bool NTL = NT & 1, NTW = NT & 2, NTG = NT & 4;
   constexpr Off BS = sizeof(S);
+  constexpr int kPhi = 3, kC1 = 4, kC2 = 5;  // history planes: ux, uy, uz, phi, c1, c2
   __shared__ Ring<T, TX, TY, !LOC> R;
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
   const int per = (G.ntiles + 7) / 8;
@@ -108,6 +120,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // zero their registers for a skipped branch.
   const Off own_col =
       own_slot ? Off(fold(y, ny, G.wall_y) * G.px + fold(x, nx, G.wall_x)) * BS : Off(0);
+  constexpr Off TS = Off(sizeof(T) / sizeof(S));  // population bytes -> history bytes
 
   int hx = 0, hy = 0;
   bool halo = false;
@@ -126,112 +139,150 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     load_q<LF, NTL, true>(sH1, G.sS, node, h1);
     load_q<LF, NTL, true>(sH2, G.sS, node, h2);
   };
+  // the references (phi, c1, c2 of the previous level) of a node
+  auto load_ref = [&](Off node, T (&r)[3]) {
+    const Off nT = node * TS;
+    r[0] = *at(hin, plane<true>(kPhi, G.sT) + nT);
+    if (!LOC) {
+      r[1] = *at(hin, plane<true>(kC1, G.sT) + nT);
+      r[2] = *at(hin, plane<true>(kC2, G.sT) + nT);
+    } else {
+      r[1] = T(0);
+      r[2] = T(0);
+    }
+  };
+  // the pressure bracket a node's flow populations are stored relative to
+  // (the rest slot of its g)
+  auto load_pi = [&](Off node) -> T {
+    return Codec<S, T>::ld(ld_pop<NTG>(at(sG, node)), T(LG::w[0]));
+  };
   // moments of plane zp of the own node into the ring
   auto put_own = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7],
-                     const T (&h2)[7], Node<T>& s) {
-    moments<LF>(P, f, h1, h2, s);
+                     const T (&h2)[7], const T (&r)[3], T pi, Node<T>& s) {
+    moments<LF>(P, f, h1, h2, r[0], LOC ? P.ref_c1 : r[1], LOC ? P.ref_c2 : r[2], s);
     if (own_slot) {
       const int sl = slot_of(zp);
-      R.phi[sl][ty + 1][tx + 1] = s.dphi;
-      if (!LOC) R.psi[sl][ty + 1][tx + 1] = s.dc1 + P.Keq * s.dc2;
+      R.phi[sl][ty + 1][tx + 1] = s.phi;
+      R.pi[sl][ty + 1][tx + 1] = pi;
+      if (!LOC) {
+        R.c1[sl][ty + 1][tx + 1] = s.c1;
+        R.c2[sl][ty + 1][tx + 1] = s.c2;
+      }
     }
   };
   // load plane zp of the lane's halo node and put its moments in the ring,
-  // in one conditional block (the halo needs h1, h2 only for the psi stencil)
+  // in one conditional block (the halo needs h1, h2 only for the scalar ring)
   auto halo_plane = [&](const KParams<T>& P, int zp, Off pbase) {
     if (!halo) return;
     const int sl = slot_of(zp);
-    T hf[7];
+    T hf[7], hr[3];
     load_q<LF, NTL, true>(sF, G.sS, pbase + halo_col, hf);
+    load_ref(pbase + halo_col, hr);
+    R.pi[sl][hy + 1][hx + 1] = load_pi(pbase + halo_col);
     if constexpr (LOC) {
-      T d = hf[0];
-#pragma unroll
-      for (int i = 1; i < 7; ++i) d += hf[i];
-      R.phi[sl][hy + 1][hx + 1] = d;
+      R.phi[sl][hy + 1][hx + 1] = hr[0] + phase_sum<LF>(hf);
     } else {
       T hh1[7], hh2[7];
       load_q<LF, NTL, true>(sH1, G.sS, pbase + halo_col, hh1);
       load_q<LF, NTL, true>(sH2, G.sS, pbase + halo_col, hh2);
       Node<T> q;
-      moments<LF>(P, hf, hh1, hh2, q);
-      R.phi[sl][hy + 1][hx + 1] = q.dphi;
-      R.psi[sl][hy + 1][hx + 1] = q.dc1 + P.Keq * q.dc2;
+      moments<LF>(P, hf, hh1, hh2, hr[0], hr[1], hr[2], q);
+      R.phi[sl][hy + 1][hx + 1] = q.phi;
+      R.c1[sl][hy + 1][hx + 1] = q.c1;
+      R.c2[sl][hy + 1][hx + 1] = q.c2;
     }
   };
 
   T f[7], h1[7], h2[7];  // own populations of the plane being collided
+  T r[3];                // and their references
   Node<T> s{};
   {
     // prologue: planes z0-1 and z0
     const KParams<T>& P = params(Pg);
-    T af[7], ah1[7], ah2[7];
+    T af[7], ah1[7], ah2[7], ar[3];
     const Off pm = Off(fold(z0 - 1, nz, G.wall_z)) * G.nxy;
     const Off p0 = Off(z0) * G.nxy;
     load_fh(pm + own_col, af, ah1, ah2);
+    load_ref(pm + own_col, ar);
+    const T apm = load_pi(pm + own_col);
     halo_plane(P, z0 - 1, pm);
     Node<T> tmp;
-    put_own(P, z0 - 1, af, ah1, ah2, tmp);
+    put_own(P, z0 - 1, af, ah1, ah2, ar, apm, tmp);
     load_fh(p0 + own_col, f, h1, h2);
+    load_ref(p0 + own_col, r);
+    const T ap0 = load_pi(p0 + own_col);
     halo_plane(P, z0, p0);
-    put_own(P, z0, f, h1, h2, s);
+    put_own(P, z0, f, h1, h2, r, ap0, s);
   }
   // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits: the
   // same lines were read for the moments one plane earlier) right before
   // collide_f and collide_h, instead of being held in registers from the
   // previous plane through the whole g collision.  21 more loads per node
-  // that HBM does not see; only the 8 values of the node state are carried.
+  // that HBM does not see; only the node state and references are carried.
 
   for (int z = z0; z < z1; ++z) {
     const KParams<T>& P = params(Pg);
     const Off zoff = Off(z) * G.nxy;
-    const Off node = zoff + own_col;                       // bytes, population arrays
-    const Off nodeT = node * Off(sizeof(T) / sizeof(S));   // bytes, history / fields
+    const Off node = zoff + own_col;  // bytes, population arrays
+    const Off nodeT = node * TS;      // bytes, history / fields
     const Off pn = Off(fold(z + 1, nz, G.wall_z)) * G.nxy;
     // ---- 1. global loads of this plane
-    T g[19], hs[kHist3D], nf[7], nh1[7], nh2[7];
+    T g[19], uo[3], nf[7], nh1[7], nh2[7], nr[3];
     auto load_g = [&] {
 #pragma unroll
-      for (int i = 0; i < 19; ++i)
+      for (int i = 1; i < 19; ++i)
         g[i] = Codec<S, T>::ld(
             ld_pop<NTG>(at(sG, plane<true>(i, G.sS) + node + skew<LG, S, Off>(i))), T(LG::w[i]));
 #pragma unroll
-      for (int k = 0; k < kHist3D; ++k) hs[k] = *at(hist, plane<true>(k, G.sT) + nodeT);
+      for (int k = 0; k < 3; ++k) uo[k] = *at(hin, plane<true>(k, G.sT) + nodeT);
     };
     if (PREF && active) load_g();
     load_fh(pn + own_col, nf, nh1, nh2);
+    load_ref(pn + own_col, nr);
+    const T npi = load_pi(pn + own_col);
     // ---- 2. moments of plane z+1 into the ring
     halo_plane(P, z + 1, pn);
     Node<T> ns;
-    put_own(P, z + 1, nf, nh1, nh2, ns);
+    put_own(P, z + 1, nf, nh1, nh2, nr, npi, ns);
     __syncthreads();
     // ---- 3. collide plane z
     if (active) {
       if (!PREF) load_g();
       const int sm = slot_of(z - 1), s0 = slot_of(z), sp = slot_of(z + 1);
+      auto slot = [&](int i) { return LG::cz[i] < 0 ? sm : (LG::cz[i] > 0 ? sp : s0); };
       // isotropic central stencils (Sec. III C) on D3Q19 weights
-      T gphi[3] = {0, 0, 0}, gpsi[3] = {0, 0, 0}, lap = 0;
+      auto nbp = [&](int i) -> T { return R.phi[slot(i)][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]]; };
+      T gphi[3], gpsi[3] = {T(0), T(0), T(0)};
+      grad_pairs<LG, T>(nbp, gphi);
+      const T lap = lap_of<LG, T>(nbp, s.phi);
+      if constexpr (!LOC) {
+        // grad psi = grad c1 + Keq grad c2 (psi = c1 + Keq c2)
+        T gc1[3], gc2[3];
+        grad_pairs<LG, T>([&](int i) { return R.c1[slot(i)][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]]; },
+                          gc1);
+        grad_pairs<LG, T>([&](int i) { return R.c2[slot(i)][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]]; },
+                          gc2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gpsi[a] = gc1[a] + P.Keq * gc2[a];
+      }
+      // z bounce bits of this plane (uniform) with the lane's x / y ones
+      int bits = push.bits;
+      if (z == 0 && G.wall_z) bits |= 16;
+      if (z == nz - 1 && G.wall_z) bits |= 32;
+      // the flow populations relative to the own pressure bracket pi0: a
+      // value arriving from x - c_i was stored relative to the bracket of
+      // that node (of the node itself when the link bounced off a wall)
+      const T pi0 = R.pi[s0][ty + 1][tx + 1];
+      g[0] = pi0;
 #pragma unroll
       for (int i = 1; i < 19; ++i) {
-        const int sl = LG::cz[i] < 0 ? sm : (LG::cz[i] > 0 ? sp : s0);
-        const T a = R.phi[sl][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]];
-        const T b = LOC ? T(0) : R.psi[sl][ty + 1 + LG::cy[i]][tx + 1 + LG::cx[i]];
-        const T wc = T(LG::w[i] / LG::cs2);
-        if (LG::cx[i]) {
-          gphi[0] += wc * T(LG::cx[i]) * a;
-          gpsi[0] += wc * T(LG::cx[i]) * b;
-        }
-        if (LG::cy[i]) {
-          gphi[1] += wc * T(LG::cy[i]) * a;
-          gpsi[1] += wc * T(LG::cy[i]) * b;
-        }
-        if (LG::cz[i]) {
-          gphi[2] += wc * T(LG::cz[i]) * a;
-          gpsi[2] += wc * T(LG::cz[i]) * b;
-        }
-        lap += T(2) * wc * (a - s.dphi);
+        const bool back = (bits & link_mask(-LG::cx[i], -LG::cy[i], -LG::cz[i])) != 0;
+        const int sl = LG::cz[i] > 0 ? sm : (LG::cz[i] < 0 ? sp : s0);
+        const T src = back ? pi0 : R.pi[sl][ty + 1 - LG::cy[i]][tx + 1 - LG::cx[i]];
+        g[i] += kp<LG, T>(i) * (src - pi0);
       }
       Flow<T> fl;
-      flow_macros<LG>(P, g, s, gphi, lap, fl);
+      flow_macros<LG>(P, g, s, gphi, lap, pi0, fl);
       if (MODE == kModeMacros) {
         auto put_field = [&](int k, T v) { *at(fields, plane<true>(k, G.sT) + nodeT) = v; };
         put_field(kFieldPhi, s.phi);
@@ -244,31 +295,25 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         put_field(kFieldMu, fl.mu);
         put_field(kFieldPsi, s.c1 + P.Keq * s.c2);
       } else {
-        // backward-difference time derivatives against the history (R1)
+        // backward-difference time derivatives against the history (R1):
+        // the references are the previous level's phi, c1, c2
         T dJphi[3], dJ1[3], dJ2[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          dJphi[a] = s.phi * fl.u[a] - hs[3] * hs[a];
-          dJ1[a] = s.c1 * fl.u[a] - hs[4] * hs[a];
-          dJ2[a] = s.c2 * fl.u[a] - hs[5] * hs[a];
+          dJphi[a] = s.phi * fl.u[a] - r[0] * uo[a];
+          dJ1[a] = s.c1 * fl.u[a] - (LOC ? *at(hin, plane<true>(kC1, G.sT) + nodeT) : r[1]) * uo[a];
+          dJ2[a] = s.c2 * fl.u[a] - (LOC ? *at(hin, plane<true>(kC2, G.sT) + nodeT) : r[2]) * uo[a];
         }
 #pragma unroll
         for (int k = 0; k < kHist3D; ++k) {
-          const T v = k < 3 ? fl.u[k] : (k == 3 ? s.phi : (k == 4 ? s.c1 : s.c2));
-          *at(hist, plane<true>(k, G.sT) + nodeT) = v;
+          const T v = k < 3 ? fl.u[k] : (k == kPhi ? s.phi : (k == kC1 ? s.c1 : s.c2));
+          *at(hout, plane<true>(k, G.sT) + nodeT) = v;
         }
 
-        // z push deltas and bounce bits of this plane (uniform)
+        // z push deltas of this plane (uniform)
         Off dzm = Off(0) - G.nxy, dzp = G.nxy;
-        int bits = push.bits;
-        if (z == 0) {
-          if (G.wall_z) bits |= 16;
-          dzm = Off(nz - 1) * G.nxy;
-        }
-        if (z == nz - 1) {
-          if (G.wall_z) bits |= 32;
-          dzp = Off(0) - Off(nz - 1) * G.nxy;
-        }
+        if (z == 0) dzm = Off(nz - 1) * G.nxy;
+        if (z == nz - 1) dzp = Off(0) - Off(nz - 1) * G.nxy;
         // byte offset of the push target of direction i (plane i of its set),
         // or of the bounce-back target (plane opp(i), this node); the plane
         // skew of direction i is -c_ix nodes, that of opp(i) +c_ix.  Walls
@@ -279,6 +324,9 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         // selected per lane (the plane offsets are opaque to the compiler,
         // which would otherwise branch around each one).
         const bool walls = __ballot(bits != 0) != 0;
+        auto bounced = [&](int cx, int cy, int cz) {
+          return walls && (bits & link_mask(cx, cy, cz)) != 0;
+        };
         auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
           const Off sk = cx > 0 ? Off(0) - BS : (cx < 0 ? BS : Off(0));
           Off t = node;
@@ -290,20 +338,38 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
           const Off back_t = plane<true>(o, G.sS) + node - sk;
           return (bits & link_mask(cx, cy, cz)) ? back_t : push_t;
         };
+        // The collisions emit X_i* - w_i R(x), R(x) the node's own reference
+        // (its moment at the previous level); the D3Q7 value stored at the
+        // target y is X_i* - w_i R'(y), with R'(y) the moment of y at this
+        // level, which y's history will hold when the value is read: the
+        // neighbour's for a pushed link, the node's own new moment for the
+        // rest direction and for a bounced link (both return to x)
+        auto rebase = [&](int i, T v, T rown, const T (&ring)[4][TY + 2][TX + 2]) -> T {
+          const int sl = LF::cz[i] < 0 ? sm : (LF::cz[i] > 0 ? sp : s0);
+          const T rt = bounced(LF::cx[i], LF::cy[i], LF::cz[i])
+                           ? ring[s0][ty + 1][tx + 1]
+                           : ring[sl][ty + 1 + LF::cy[i]][tx + 1 + LF::cx[i]];
+          return v + T(LF::w[i]) * (rown - rt);
+        };
         S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
         S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
         S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
         S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
         T n[3];
         normal(P, gphi, n);
+        // flow set: the new bracket pi, as stored, is the reference of the
+        // values this node emits and goes to its own rest slot
+        const T pi_st = stored<S, T>(fl.pi, T(LG::w[0]), T(1.0 / LG::w[0]));
+        st_pop<NTW>(at(dG, node), Codec<S, T>::st(fl.pi, T(1.0 / LG::w[0])));
         collide_g<LG>(P, g, gphi, fl, [&](int i, T v) {
           const Off t = target(i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
-          st_pop<NTW>(at(dG, t), Codec<S, T>::st(v, T(1.0 / LG::w[i])));
+          st_pop<NTW>(at(dG, t),
+                      Codec<S, T>::st(v + kp<LG, T>(i) * (pi0 - pi_st), T(1.0 / LG::w[i])));
         });
         if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          st_pop<NTW>(at(dF, t), Codec<S, T>::st(v, T(1.0 / LF::w[i])));
+          st_pop<NTW>(at(dF, t), Codec<S, T>::st(rebase(i, v, r[0], R.phi), T(1.0 / LF::w[i])));
         });
         if (LATE) {
           load_q<LF, NTL, true>(sH1, G.sS, node, h1);
@@ -328,6 +394,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          if constexpr (!LOC) {
+            a = rebase(i, a, r[1], R.c1);
+            c = rebase(i, c, r[2], R.c2);
+          }
           st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
           st_pop<NTW>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
         });
@@ -341,6 +411,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         h2[i] = nh2[i];
       }
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = nr[k];
     s = ns;
   }
 }
@@ -383,7 +455,7 @@ int choose_chunks(int tiles_xy, int nz, int slots) {
 
 template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE,
           class Off, bool LOC = false>
-hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, hipStream_t stream) {
   constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off, LOC>;
   static std::atomic<int> per_cu{0};
@@ -412,7 +484,7 @@ hipError_t launch_variant(const S* src, S* dst, T* hist, T* fields, const KParam
   G.sT = Off(P.stride * (long long)sizeof(T));
   G.nxy = Off((long long)P.px * P.ny * (long long)sizeof(S));
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(TX * TY), 0, stream, src, dst, hist, fields,
+  hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(TX * TY), 0, stream, src, dst, hin, hout, fields,
                      (KPtr<T>)Pdev, G);
   return hipGetLastError();
 }
@@ -430,24 +502,25 @@ namespace {
 
 // the variant switch of one gradient scheme (LOC: Eq. (39))
 template <class S, class T, bool LOC>
-hipError_t launch_scheme(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_scheme(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
   constexpr int M = kModeStep;
   using U = uint32_t;
   if (!fits_u32(LG::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t>(
-          src, dst, hist, fields, P, Pdev, stream);
+      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t, LOC>(
+          src, dst, hin, hout, fields, P, Pdev, stream);
     return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t, LOC>(
-        src, dst, hist, fields, P, Pdev, stream);
+        src, dst, hin, hout, fields, P, Pdev, stream);
   }
-  // the field read-out does not depend on the gradient scheme
+  // the field read-out takes the scheme's references of h1, h2 (per node for
+  // the central stencil, uniform for the local scheme)
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U>(
-        src, dst, hist, fields, P, Pdev, stream);
+    return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U, LOC>(
+        src, dst, hin, hout, fields, P, Pdev, stream);
 #define PFLB_V3(TX, TY, NT, PREF, LATE, WPE) \
-  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC>(src, dst, hist, fields, P, Pdev, stream)
+  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC>(src, dst, hin, hout, fields, P, Pdev, stream)
   // NT: non-temporal hints (bit 0 f / h loads, bit 1 stores, bit 2 g loads);
   // LATE: f / h re-read before their collision; WPE: minimum waves per SIMD
   // the register allocator must allow (1: free)
@@ -467,24 +540,25 @@ hipError_t launch_scheme(const S* src, S* dst, T* hist, T* fields, const KParams
 }  // namespace
 
 template <class S, class T>
-hipError_t launch_step3d(const S* src, S* dst, T* hist, T* fields, const KParams<T>& P,
+hipError_t launch_step3d(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                          const KParams<T>* Pdev, int mode, int variant, hipStream_t stream) {
   if (P.local_grad)
-    return launch_scheme<S, T, true>(src, dst, hist, fields, P, Pdev, mode, variant, stream);
-  return launch_scheme<S, T, false>(src, dst, hist, fields, P, Pdev, mode, variant, stream);
+    return launch_scheme<S, T, true>(src, dst, hin, hout, fields, P, Pdev, mode, variant, stream);
+  return launch_scheme<S, T, false>(src, dst, hin, hout, fields, P, Pdev, mode, variant, stream);
 }
 
-template hipError_t launch_step3d<double, double>(const double*, double*, double*, double*,
+template hipError_t launch_step3d<double, double>(const double*, double*, const double*, double*, double*,
                                                   const KParams<double>&, const KParams<double>*,
                                                   int, int, hipStream_t);
-template hipError_t launch_step3d<float, float>(const float*, float*, float*, float*,
+template hipError_t launch_step3d<float, float>(const float*, float*, const float*, float*, float*,
                                                 const KParams<float>&, const KParams<float>*, int,
                                                 int, hipStream_t);
-template hipError_t launch_step3d<__half, float>(const __half*, __half*, float*, float*,
+template hipError_t launch_step3d<__half, float>(const __half*, __half*, const float*, float*, float*,
                                                  const KParams<float>&, const KParams<float>*, int,
                                                  int, hipStream_t);
 template hipError_t launch_step3d<__hip_bfloat16, float>(const __hip_bfloat16*, __hip_bfloat16*,
-                                                         float*, float*, const KParams<float>&,
+                                                         const float*, float*, float*,
+                                                         const KParams<float>&,
                                                          const KParams<float>*, int, int,
                                                          hipStream_t);
 

@@ -104,18 +104,17 @@ def test_hbm_size_2d_random_fields(cplb, grad):
         a = g.field(k).cpu().numpy()
         assert np.all(np.isfinite(a)), k
         errs[k] = rel_err(a, o.field(k))
-    # mu = exp(c1 ln mu1 + c2 ln mu2) (Eq. (4.3)) is not held to the field
-    # bound: with Keq = 0.2 the exchange anti-correlates the c1 and c2
-    # errors, which the exponent amplifies about five-fold.  Its evaluation
-    # is checked node by node instead, against FP64 exp of the GPU's own c1,
-    # c2: the FP32 exponential (v_exp_f32 of x log2 e) is good to a few 1e-7.
+    # mu = exp(c1 ln mu1 + c2 ln mu2) (Eq. (4.3)) is held to the field bound
+    # against the oracle (1.4e-7 central, 6.2e-7 local, measured) and, node
+    # by node, against FP64 exp of the GPU's own c1, c2: the FP32 exponential
+    # (v_exp_f32 of x log2 e) is good to a few 1e-7.
     c1, c2, mu = (g.field(k).cpu().numpy().astype(np.float64) for k in ("c1", "c2", "mu"))
     mu_exact = np.exp(c1 * np.log(p["mu1"]) + c2 * np.log(p["mu2"]))
     errs["mu_eval_max"] = float(np.max(np.abs(mu / mu_exact - 1.0)))
     errs["mu_vs_oracle"] = rel_err(mu, o.field("mu"))
     say(f"  t=5: variant {g.variant_names()[g.variant]}: "
         + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    bounds = dict({k: 1e-5 for k in FP32_2D + ("psi",)}, mu_eval_max=1e-6, mu_vs_oracle=1e-4)
+    bounds = dict({k: 1e-5 for k in FP32_2D + ("psi",)}, mu_eval_max=1e-6, mu_vs_oracle=1e-5)
     bad = {k: v for k, v in errs.items() if not v <= bounds[k]}
     assert not bad, bad
 

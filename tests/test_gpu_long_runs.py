@@ -3,18 +3,18 @@ bubble for 20,000 steps and the 3-D rising droplet for 5,000, checked for
 stability (no non-finite value), mass conservation and motion.
 
 The scheme conserves sum phi and sum (c1 + c2) exactly (pin P2 of the
-oracle); in finite precision each stored population is rounded, and in a
-near-steady state the same rounding recurs every step, so the drift grows
-linearly rather than as a random walk.  Measured (MI355X):
+oracle); in finite precision each stored population is rounded.  f, h1 and
+h2 are stored relative to the moments of the node they are stored at, so
+a rounding is relative to the change of that node's moment over one step,
+not to the moment itself.  Measured (MI355X):
 
-  bubble 256 x 1024, FP32, 20,000 steps:  phi 4.2e-7, c1 + c2 1.3e-5
-  droplet 256^3, FP32, 5,000 steps:       phi 9.1e-7, c1 + c2 1.7e-5
-  droplet 256^3, FP16 storage, 5,000:     phi 1.75e-6, c1 + c2 7.0e-3
+  bubble 256 x 1024, FP32, 20,000 steps:  phi 2.1e-9,  c1 + c2 1.3e-7
+  droplet 256^3, FP32, 5,000 steps:       phi 1.5e-11, c1 + c2 3.5e-9
+  droplet 256^3, FP16 storage, 5,000:     phi 1.8e-8,  c1 + c2 2.4e-4
 
-The phase-mass target, 1e-6, holds for FP32 storage and is asserted; with
-FP16 storage it does not (1.75e-6), nor is the scalar mass held better than
-1e-2 -- recorded as such.  The other bounds are regression guards at about
-twice the measured drift."""
+The phase-mass target, 1e-6, is asserted for every run; the scalar-mass
+bounds (no stated target) are regression guards at about twice the
+measured drift."""
 import numpy as np
 import pytest
 
@@ -61,12 +61,12 @@ def test_rising_bubble_20000_steps(cplb):
         f"bubble {y0:.1f} -> {y1:.1f}  max|u| {r['max_u']:.2e}")
     assert r["nonfinite"] == 0 and r["step"] == 20000
     assert drift(r, r0, "sum_phi") <= 1e-6
-    assert drift(r, r0, "sum_c") <= 3e-5
+    assert drift(r, r0, "sum_c") <= 3e-7
     assert y1 - y0 > 50.0  # the bubble rises (85 nodes measured)
 
 
-@pytest.mark.parametrize("precision,phi_bound,c_bound", [("f32", 1e-6, 4e-5),
-                                                         ("f32_s16f", 4e-6, 1.5e-2)])
+@pytest.mark.parametrize("precision,phi_bound,c_bound", [("f32", 1e-6, 1e-8),
+                                                         ("f32_s16f", 1e-6, 5e-4)])
 def test_rising_droplet_5000_steps(cplb, precision, phi_bound, c_bound):
     w = W.rising_droplet_3d(256, precision)
     say(f"rising droplet 256^3 {precision}, 5000 steps")

@@ -51,17 +51,32 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / scale)
 
 
+def max_err(a, b):
+    """Largest nodal error over the field's scale (its largest magnitude or
+    its largest deviation from the mean, whichever is larger)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = max(np.abs(b).max(), np.abs(b - b.mean()).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)
+
+
 def compare(g, o, names, tol, label=""):
-    errs = {}
+    """Relative L2 error of each field within tol and, so that an error held
+    to a few nodes (a wall row, the interface) cannot hide under the norm,
+    its max-abs error within 30 tol (10 tol for the 16-bit bounds, 100 tol
+    for the FP64 ones)."""
+    errs, maxs = {}, {}
     for k in names:
         a = g.field(k).cpu().numpy()
         b = o.field(k)
         assert a.shape == b.shape
         assert np.all(np.isfinite(a)), (label, k)
         errs[k] = rel_err(a, b)
-    say(f"  {label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= tol}
-    assert not bad, (label, bad, tol)
+        maxs[k] = max_err(a, b)
+    mtol = (10.0 if tol >= 1e-3 else 30.0 if tol >= 1e-7 else 100.0) * tol
+    say(f"  {label}: " + " ".join(f"{k}={v:.2e}/{maxs[k]:.2e}" for k, v in errs.items()))
+    bad = {k: (v, maxs[k]) for k, v in errs.items() if not (v <= tol and maxs[k] <= mtol)}
+    assert not bad, (label, bad, tol, mtol)
     return errs
 
 
@@ -197,16 +212,12 @@ def test_droplet3d_fp32_reduced(cplb):
 
 def test_droplet3d_fp32_1000_steps(cplb):
     """The FP32 target is 1e-5 after 1000 steps: the 3-D droplet on a 64^3
-    copy for that long (the oracle takes ~10 s on 16 cores).  phi, c1, c2 and
-    p meet it; the velocity does not: its FP32 rounding accumulates to
-    1.15e-5 of its norm by step 1000 (1.03e-5 with correctly rounded
-    division and exp; 3.4e-6 at step 200), so u is held to 2e-5 here and the
-    miss is recorded as such."""
+    copy for that long (the oracle takes ~10 s on 16 cores).  Measured on
+    MI355X: u 9.6e-6, p 7.6e-6, c2 3.9e-6, c1 1.1e-6, phi 1.5e-7."""
     w = W.rising_droplet_3d(n=64)
     say("rising droplet 64^3 fp32 1000 steps")
     g, o = pair_workload(cplb, w, 1000)
-    compare(g, o, ("phi", "c1", "c2", "p"), 1e-5, "t=1000")
-    compare(g, o, ("ux", "uy", "uz"), 2e-5, "t=1000 velocity")
+    compare(g, o, ("phi", "c1", "c2", "ux", "uy", "uz", "p"), 1e-5, "t=1000")
 
 
 def test_droplet3d_fp32_full_size(cplb):
@@ -220,7 +231,10 @@ def test_droplet3d_fp32_full_size(cplb):
 
 # ------------------------------------------------------- 16-bit storage
 
-TOL16 = {"f32_s16f": 2e-3, "f32_s16b": 2e-2}
+TOL16 = 2e-3
+# with BF16 storage p and u miss the target (see the 128^3 1000-step parity);
+# both 16-bit formats hold phi, c1 and c2 to it
+FIELDS16 = {"f32_s16f": ("phi", "c1", "c2", "ux", "uy", "uz", "p"), "f32_s16b": ("phi", "c1", "c2")}
 
 
 @pytest.mark.parametrize("precision", ["f32_s16f", "f32_s16b"])
@@ -228,7 +242,7 @@ def test_droplet3d_16bit_storage(cplb, precision):
     w = W.rising_droplet_3d(n=64)
     say(f"rising droplet 64^3 {precision} 200 steps")
     g, o = pair_workload(cplb, w, 200, precision=precision)
-    compare(g, o, ("phi", "c1", "c2"), TOL16[precision], f"{precision} t=200")
+    compare(g, o, FIELDS16[precision], TOL16, f"{precision} t=200")
 
 
 @pytest.mark.parametrize("precision", ["f32_s16f", "f32_s16b"])
@@ -236,7 +250,7 @@ def test_bubble2d_16bit_storage(cplb, precision):
     w = W.rising_bubble_2d(nx=64, ny=256)
     say(f"rising bubble 64x256 {precision} 1000 steps")
     g, o = pair_workload(cplb, w, 1000, precision=precision)
-    compare(g, o, ("phi", "c1", "c2"), TOL16[precision], f"{precision} t=1000")
+    compare(g, o, ("phi", "c1", "c2"), TOL16, f"{precision} t=1000")
 
 
 # ------------------------------------------------ invariants and contract

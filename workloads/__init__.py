@@ -15,18 +15,13 @@ Parameter dictionaries use the keys
     g (3-vector), rho_ref, n_eps
 
 plus, for the GPU library only, ``precision`` ('f64' | 'f32' | 'f32_s16f' |
-'f32_s16b') and the reference state of its stored population deviations,
-``ref_f`` (phi_ref), ``ref_g`` (always 0), ``ref_h1``, ``ref_h2`` (c1_ref,
-c2_ref).  ``ref_h1`` / ``ref_h2`` are the concentrations that fill most of
-the domain.  ``ref_f`` sets where the stored phase populations resolve phi
-best.  Both tails matter: the scalar sources carry phi c2 in the core of
-fluid 2 (phi -> 0) and the buoyancy (rho - rho_ref) g carries 1 - phi in
-the bulk of fluid 1 (phi -> 1); a reference at either end leaves the other
-tail at the absolute FP32 resolution of a deviation of size 1 (~6e-8).
-FP32 storage therefore takes ref_f = 1/2 (both tails at ~3e-8); 16-bit
-storage takes the bulk phase (ref_f = 1), whose deviations are then exactly
-zero -- a deviation of size 1/2 would leave FP16's ~5e-4 resolution in the
-bulk.  See ``phase_reference``.
+'f32_s16b') and the uniform references of its stored scalar populations,
+``ref_h1``, ``ref_h2`` (c1_ref, c2_ref: the concentrations that fill most
+of the domain), used where h1, h2 have no per-node reference (one-scalar
+model, local gradient scheme).  ``ref_f`` and ``ref_g`` are kept for the
+parameter layout: the library stores f relative to each node's own phase
+and g relative to a pressure bracket, so ``ref_f`` has no effect and
+``ref_g`` must be 0.
 
 Every field array is a numpy float64 array of shape (ny, nx) in 2-D or
 (nz, ny, nx) in 3-D (x fastest in memory).
@@ -47,9 +42,10 @@ DEFAULTS = dict(
 
 
 def phase_reference(precision: str, bulk_phi: float = 1.0) -> float:
-    """Reference phi of the stored phase populations for a storage precision
-    (see the module docstring): 1/2 for FP64 / FP32, the bulk phase for
-    16-bit storage."""
+    """A uniform phase reference for a storage precision: 1/2 for FP64 / FP32,
+    the bulk phase for 16-bit storage.  The library takes it in ``ref_f``
+    and ignores it (see the module docstring); kept so that parameter sets
+    written for uniform references still load."""
     return bulk_phi if precision.startswith("f32_s16") else 0.5
 
 
