@@ -172,17 +172,26 @@ def test_p3_flat_equilibrium(D1, D2, K):
             assert abs(psi.mean() - plateau) < 1e-3
 
 
-def test_p3_flat_equilibrium_default_regularisation():
-    # with the default normal regularisation (1e-3) the far tails of phi relax
-    # by slow bulk diffusion; the plateau is already within 1e-3 of the closed
-    # form after the same run
+@pytest.mark.parametrize("n_eps", [1e-3, 1e-4, 1e-5])
+def test_p3_flat_equilibrium_regularised_tail(n_eps):
+    # With the regularised normal n = grad phi / sqrt(|grad phi|^2 + n_eps^2)
+    # the sharpening flux fades where |grad phi| falls below n_eps: the far
+    # tails of the tanh profile stop at phi ~ n_eps / 3 instead of relaxing
+    # to round-off, and the flat equilibrium's plateau carries an error of
+    # the same size.  Both scale linearly with n_eps (measured 0.27 n_eps and
+    # 0.31 n_eps at 1e-3, 1e-4 and 1e-5), which pins the regularisation's
+    # only effect: the profile's tails.
     K = 1 / 3
-    o = _flat_case(1.0, 1.0, K, n_eps=1e-3)
+    o = _flat_case(1.0, 1.0, K, n_eps=n_eps)
     phi, c1, c2 = o.field("phi")[0], o.field("c1")[0], o.field("c2")[0]
     N = phi.size
     c2t = (c1 + c2).sum() / (K * phi.sum() + N - phi.sum())
-    assert np.abs(c1 - K * c2t * phi).max() <= 1e-3 * K * c2t
-    assert np.ptp(c1 + K * c2) <= 1e-3 * (c1 + K * c2).mean()
+    plateau = np.abs(c1 - K * c2t * phi).max() / (K * c2t)
+    flat = np.ptp(c1 + K * c2) / (c1 + K * c2).mean()
+    tail = min(phi.min(), 1.0 - phi.max())
+    assert 0.1 * n_eps <= plateau <= 0.5 * n_eps, plateau
+    assert flat <= 0.5 * n_eps, flat
+    assert 0.1 * n_eps <= tail <= 0.5 * n_eps, tail
 
 
 # --------------------------------------------------------------------------
@@ -523,9 +532,15 @@ def test_nonfinite_is_reported():
 # phi overshoots 1 on a flat profile, amplifies it to ~1e-5 within 100 steps).
 # This is what makes element-wise parity of long runs meaningful.
 # --------------------------------------------------------------------------
-def test_trajectory_is_well_conditioned():
+@pytest.mark.parametrize("n_eps", [1e-3, 1e-5])
+def test_trajectory_is_well_conditioned(n_eps):
+    # A 1-ulp perturbation of the initial drop stays at round-off over 500
+    # steps of the 64^2 static drop for every normal regularisation down to
+    # n_eps = 1e-5 (measured: 7e-15 at 1e-3 ... 1e-5); at 5e-6 it grows to
+    # 3e-11 and at 1e-6 to 4e-5, where the normal at the drop centre is set
+    # by round-off.
     w = W.static_drop_64()
-    p = w["params"]
+    p = dict(w["params"], n_eps=n_eps)
     phi0 = 0.5 + 0.5 * np.tanh(2 * w["sdf"] / p["W"])
     rng = np.random.default_rng(0)
     a = make(p, phi0, phi0.copy(), np.zeros_like(phi0))
@@ -536,6 +551,35 @@ def test_trajectory_is_well_conditioned():
     for k in ("phi", "c1", "c2", "p"):
         fa, fb = a.field(k), b.field(k)
         assert np.linalg.norm(fa - fb) <= 1e-13 * np.linalg.norm(fa), k
+
+
+def _mirror_asymmetry_3d(n_eps, steps):
+    p = W.params(nx=20, ny=20, nz=20, lattice="d3q19_d3q7", sigma=0.01, rho1=2.0, rho2=1.0,
+                 D1=0.05, D2=0.01, Keq=2.0, A=0.2, n_eps=n_eps)
+    o = ref.Oracle(p)
+    o.init_sdf(W.sdf_sphere(p, (10.0, 10.0, 10.0), 5.0), c1=(0.0, 1.0), c2=(0.2, -0.2))
+    o.step(steps)
+    phi = o.field("phi")
+    o.close()
+    ix = (-np.arange(20)) % 20
+    return float(np.abs(phi - phi[:, :, ix]).max())
+
+
+@pytest.mark.parametrize("n_eps,bound", [(1e-3, 1e-13), (1e-4, None)])
+def test_regularisation_floor_3d(n_eps, bound):
+    # Where the tails of periodic images meet (a 20^3 box, drop radius 5),
+    # |grad phi| falls to ~1e-5 and the normal turns over within the nodes
+    # where |grad phi| < n_eps.  With n_eps = 1e-3 the turn is smooth and the
+    # round-off asymmetry of the mirror-symmetric drop stays at 1e-15 over
+    # 300 steps; with 1e-4 the sharpening flux turns abruptly and amplifies it
+    # to ~3e-3 (measured: 3e-4 -> 1.4e-9, 1e-4 -> 3.0e-3, 1e-5 -> 4.1e-3).
+    # This is why the default stays at 1e-3 although the 2-D drop is well
+    # conditioned down to 1e-5.
+    a = _mirror_asymmetry_3d(n_eps, 300)
+    if bound is not None:
+        assert a <= bound, a
+    else:
+        assert a >= 1e-6, a
 
 
 # --------------------------------------------------------------------------
