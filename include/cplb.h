@@ -223,11 +223,17 @@ size_t cplb_state_bytes(const cplb_t* h);
 int cplb_save_state(cplb_t* h, void* host_dst, size_t bytes);
 int cplb_load_state(cplb_t* h, const void* host_src, size_t bytes);
 
-/* Learned closure on a D2Q9 lattice: dev_s (device, N FP32 values in node
- * order, owned by the caller and kept alive while set) is an extra exchange
- * per step carried like the auxiliary source ~H_k (Sec. III C): h1 loses
- * w_i s, h2 gains it, so c1 + c2 is conserved exactly.  NULL switches it
- * off.  CPLB_EINVAL on a 3-D lattice or with the one-scalar model. */
+/* Learned closure on a D2Q9 lattice: dev_s (device, 2 N FP32 values: the
+ * plane of x1 in node order, then that of x2; owned by the caller and kept
+ * alive while set) holds per-node corrections of c1 and c2 per step: each
+ * step lowers the recovered c_k of the node by x_k.  They are carried like
+ * the auxiliary source ~H_k (Sec. III C), h_k losing w_i s_k with (s1, s2)
+ * = J^-1 (x1, x2), J the Jacobian of the implicit recovery of c1, c2 at the
+ * node (exact where phi and D_m do not change over the step).  x1 = -x2 is
+ * a pure exchange (c1 + c2 conserved node by node); in general the total
+ * scalar drops by sum (x1 + x2) per step (the network's inference makes it
+ * zero per case).  NULL switches it off.  CPLB_EINVAL on a 3-D lattice or
+ * with the one-scalar model. */
 int cplb_set_closure(cplb_t* h, const float* dev_s);
 
 /* Step-kernel variants (tile shape, non-temporal population traffic).
@@ -299,9 +305,9 @@ int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]);
 int64_t cplb_batch_num_nodes(const cplb_batch_t* b);
 
 /* Learned closure for every case (as cplb_set_closure): dev_s (device, FP32)
- * holds the cases' per-node values one after the other in case order,
- * cplb_batch_num_nodes values; NULL switches it off.  The buffer stays the
- * caller's; its contents may change between steps.  Synchronises. */
+ * holds, case after case, each case's s1 plane then its s2 plane (2 x
+ * cplb_batch_num_nodes values in all); NULL switches it off.  The buffer
+ * stays the caller's; its contents may change between steps.  Synchronises. */
 int cplb_batch_set_closure(cplb_batch_t* b, const float* dev_s);
 
 /* Fields fields[0..nf) (CPLB_FIELD_*) of every case at the current level
@@ -335,10 +341,11 @@ const char* cplb_batch_last_error(const cplb_batch_t* b);
 void cplb_batch_destroy(cplb_batch_t* b);
 
 /* ------------------------------------------------------------------------
- * Closure network: the small CNN that predicts the per-node correction s of
- * the interfacial scalar exchange on a coarse grid from its fields.  Fixed
- * architecture: four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 channels,
- * leaky-ReLU (slope 0.1) after the first three, output = channel 0 of the
+ * Closure network: the small CNN that predicts the per-node corrections
+ * (s1, s2) of c1 and c2 per step on a coarse grid from its fields (applied
+ * through cplb_set_closure / cplb_batch_set_closure).  Fixed architecture:
+ * four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 channels, leaky-ReLU
+ * (slope 0.1) after the first three, outputs = channels 0 and 1 of the
  * last; padding periodic along x, zero outside each sample along y.  BF16
  * MFMA with FP32 accumulation for every convolution, FP32 master
  * parameters, FP64 loss accumulation.  The parameter vector stacks per
@@ -366,13 +373,17 @@ int cplb_cnn_set_input_scale(cplb_cnn_t* c, const float scale[16]);
 
 /* Forward pass of nsamples samples: dev_planes (device) holds
  * [nsamples][cin][H][W] FP32, cin <= 16 (missing planes are zero); dev_out
- * (device, may be NULL) receives [nsamples][H][W] FP32.  Asynchronous. */
+ * (device, may be NULL) receives [nsamples][2][H][W] FP32: the two output
+ * channels times their output scales, then balanced per sample (half the
+ * sample's mean of s1 + s2 taken from both planes, so that the corrections
+ * add nothing to the sample's total scalar).  Asynchronous. */
 int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin, float* dev_out);
 
 /* Inference: the forward pass without the FP32 pre-activations the
  * backward pass needs (activations in BF16 only, the output scaled and
- * written by the last convolution).  dev_out (device) receives
- * [nsamples][H][W] FP32, bitwise equal to cplb_cnn_forward's output.  A
+ * written by the last convolution, then balanced).  dev_out (device)
+ * receives [nsamples][2][H][W] FP32, bitwise equal to cplb_cnn_forward's
+ * output.  A
  * following cplb_cnn_backward needs a cplb_cnn_forward first.  No host
  * synchronisation and no allocation: capturable in a HIP graph.
  * Asynchronous. */
@@ -382,10 +393,11 @@ int cplb_cnn_infer(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin
  * orders it after work already queued on the previous stream. */
 int cplb_cnn_set_stream(cplb_cnn_t* c, void* hip_stream);
 
-/* Loss mean((out - target)^2) of the last forward against dev_target
- * ([nsamples][H][W] FP32, device), accumulated in FP64, and the gradient of
- * every parameter (FP32).  *loss (may be NULL) receives the loss; with it
- * the call synchronises. */
+/* Loss mean((z - target)^2) of the last forward's two output channels z
+ * (before output scale and balance) against dev_target ([nsamples][2][H][W]
+ * FP32, device), the mean over both channels and every pixel, accumulated
+ * in FP64, and the gradient of every parameter (FP32).  *loss (may be NULL)
+ * receives the loss; with it the call synchronises. */
 int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss);
 int cplb_cnn_get_grads(cplb_cnn_t* c, float* host_grad);
 
@@ -393,9 +405,9 @@ int cplb_cnn_get_grads(cplb_cnn_t* c, float* host_grad);
  * weight copies are refreshed.  Asynchronous. */
 int cplb_cnn_adam(cplb_cnn_t* c, float lr, float beta1, float beta2, float eps);
 
-/* The forward output is multiplied by `scale` (default 1): the network is
- * trained on targets divided by it. */
-int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale);
+/* Output channel k (the correction of c_k) is multiplied by scale_k
+ * (default 1): the network is trained on targets divided by them. */
+int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale1, float scale2);
 
 /* Block average of nsamples fine planes (H f x W f each, device FP32) onto
  * coarse planes (H x W, device FP32): the restriction of fine-grid fields

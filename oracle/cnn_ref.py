@@ -1,18 +1,21 @@
 """FP64 CPU oracle of the closure network (test infrastructure only).
 
-The closure network maps coarse-grid fields to a per-node correction of the
-interfacial scalar exchange.  Its architecture is fixed:
+The closure network maps coarse-grid fields to per-node corrections
+(s1, s2) of the two scalars.  Its architecture is fixed:
 
     x (C0 = 16 input planes; unused planes are zero)
     z1 = conv3x3(x;  W1, b1)   16 -> 32   a1 = lrelu(z1)
     z2 = conv3x3(a1; W2, b2)   32 -> 32   a2 = lrelu(z2)
     z3 = conv3x3(a2; W3, b3)   32 -> 32   a3 = lrelu(z3)
-    z4 = conv3x3(a3; W4, b4)   32 -> 16   output = z4[channel 0]
+    z4 = conv3x3(a3; W4, b4)   32 -> 16   outputs = z4[channels 0, 1]
 
 with lrelu(z) = z for z > 0 and 0.1 z otherwise, 3x3 cross-correlation
 y[co, r, c] = b[co] + sum_{ci, dy, dx} W[co, ci, dy + 1, dx + 1] x[ci, r + dy, c + dx],
 periodic in x (columns) and zero outside the sample in y (rows), and the
-loss L = mean over nodes of (output - target)^2.
+loss L = mean over both outputs and every node of (output - target)^2.
+What is applied to a coarse run (``output``) is the outputs times their
+scales, balanced per sample: half the sample's mean of s1 + s2 is taken from
+both, so that the corrections add nothing to the sample's total scalar.
 
 The parameter vector stacks, layer by layer, W[co][ci][ky][kx] then b[co].
 
@@ -132,7 +135,7 @@ def _identity(a):
 
 
 def forward(theta, x, storage="f64"):
-    """Output [B, H, W], the pre-activations [z1..z4] and the layer inputs.
+    """Outputs [B, 2, H, W], the pre-activations [z1..z4] and the layer inputs.
 
     storage="bf16" rounds what a mixed-precision network stores: the input
     and every layer's activations and weights to BF16, the pre-activations
@@ -147,7 +150,20 @@ def forward(theta, x, storage="f64"):
         z = f32(conv(a, rnd(W), b))
         zs.append(z)
         a = rnd(lrelu(z) if n < len(layers) - 1 else z)
-    return zs[-1][:, 0], zs, ins
+    return zs[-1][:, :2], zs, ins
+
+
+def balance(out):
+    """out [B, 2, H, W] minus half of each sample's mean of out[:, 0] + out[:, 1]."""
+    out = np.asarray(out, dtype=np.float64)
+    m = (out[:, 0] + out[:, 1]).mean(axis=(1, 2)) / 2.0
+    return out - m[:, None, None, None]
+
+
+def output(theta, x, scale=(1.0, 1.0), storage="f64"):
+    """The corrections applied to a coarse run: scaled outputs, balanced."""
+    out = forward(theta, x, storage)[0]
+    return balance(out * np.asarray(scale, dtype=np.float64)[None, :, None, None])
 
 
 def loss_and_grad(theta, x, target, storage="f64"):
@@ -158,10 +174,10 @@ def loss_and_grad(theta, x, target, storage="f64"):
     layers = unpack(np.asarray(theta, dtype=np.float64))
     out, zs, ins = forward(theta, x, storage)
     r = out - target
-    P = r.size
-    loss = float(np.sum(r * r) / P)
+    P = r[:, 0].size  # pixels; the mean runs over both outputs of each
+    loss = float(np.sum(r * r) / (2 * P))
     g = np.zeros_like(zs[-1])
-    g[:, 0] = rnd(2.0 * r / P)
+    g[:, :2] = rnd(r / P)
     grads = [None] * len(layers)
     for n in range(len(layers) - 1, -1, -1):
         W, _ = layers[n]

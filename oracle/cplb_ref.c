@@ -140,7 +140,8 @@ struct cplb_ref {
   double *u_old, *phi_old, *c1_old, *c2_old;
   int64_t step;
   int macros_valid;
-  /* caller's per-node extra exchange (learned-closure extension), or NULL */
+  /* caller's per-node corrections of c1 and c2 (learned-closure extension:
+     two planes of N values, s1 then s2), or NULL */
   const double* xs;
   char err[256];
 };
@@ -630,9 +631,21 @@ static void collide(cplb_ref_t* h) {
     /* two-scalar sets h1, h2 with sources H_k and auxiliary sources ~H_k */
     const double M1 = P->A * Dm * (P->Keq * c2 * phi - c1 * (1.0 - phi));
     const double M2 = P->A * Dm * (c1 * (1.0 - phi) - P->Keq * c2 * phi);
-    /* D_m grad phi . grad(c1 + Keq c2), plus the closure's extra exchange:
-       h1 loses w_i s and h2 gains it, as with ~H */
-    const double aux = Dm * dot3(gphi, gpsi) + (h->xs ? h->xs[n] : 0.0);
+    /* D_m grad phi . grad(c1 + Keq c2).  The closure's corrections x1, x2
+       of c1, c2 are carried like ~H: h_k loses w_i s_k with (s1, s2) the
+       solution of J (s1, s2) = (x1, x2), J the Jacobian of the implicit
+       recovery c_k(S1, S2) above, so that the recovered c_k drops by x_k */
+    const double aux = Dm * dot3(gphi, gpsi);
+    double s1 = 0.0, s2 = 0.0;
+    if (h->xs) {
+      const double x1 = h->xs[n], x2 = h->xs[N + n];
+      const double a = 0.5 * P->A * Dm, den = 1.0 + a * (P->Keq * phi + 1.0 - phi);
+      const double J11 = 1.0 - a * (1.0 - phi) / den, J12 = a * P->Keq * phi / den;
+      const double J21 = a * (1.0 - phi) / den, J22 = 1.0 - a * P->Keq * phi / den;
+      const double det = J11 * J22 - J12 * J21;
+      s1 = (J22 * x1 - J12 * x2) / det;
+      s2 = (J11 * x2 - J21 * x1) / det;
+    }
     for (int i = 0; i < LF->q; i++) {
       const int* c = LF->c[i];
       const double w = LF->w[i];
@@ -640,8 +653,8 @@ static void collide(cplb_ref_t* h) {
       double heq2 = h_eq(LF, i, c2, u);
       double H1 = w * (cdot(c, dc1u) / LF->cs2 + cdot(c, nv) * 4.0 * (1.0 - phi) * c1 / P->W + M1);
       double H2 = w * (cdot(c, dc2u) / LF->cs2 - cdot(c, nv) * 4.0 * phi * c2 / P->W + M2);
-      double Ht1 = -w * aux;
-      double Ht2 = w * aux;
+      double Ht1 = -w * aux - w * s1;
+      double Ht2 = w * aux - w * s2;
       double a1 = h->h1[i * N + n], a2 = h->h2[i * N + n];
       h->h1s[i * N + n] = a1 - (a1 - heq1) / tau_h1 + (1.0 - 1.0 / (2.0 * tau_h1)) * H1 + Ht1;
       h->h2s[i * N + n] = a2 - (a2 - heq2) / tau_h2 + (1.0 - 1.0 / (2.0 * tau_h2)) * H2 + Ht2;

@@ -99,9 +99,12 @@ int cplb_ref_init_sdf(cplb_ref_t* h, const double* l, double c1_a, double c1_b,
 
 int cplb_ref_step(cplb_ref_t* h, int64_t nsteps);
 
-/* Extra exchange per step (N values in node order, caller-owned, NULL for
- * none), carried like the auxiliary source ~H_k: h1 loses w_i s, h2 gains
- * it.  Used to check the learned closure's coupling into the step. */
+/* Per-node corrections x1, x2 of c1 and c2 per step (2 N values in node
+ * order, the plane of x1 then that of x2, caller-owned, NULL for none),
+ * carried like the auxiliary source ~H_k: h_k loses w_i s_k, where (s1, s2)
+ * solves J s = x with J the Jacobian of the node's implicit recovery of
+ * (c1, c2) from (S1, S2), so that the recovered c_k drops by x_k.  Used to
+ * check the learned closure's coupling into the step. */
 int cplb_ref_set_closure(cplb_ref_t* h, const double* s);
 
 /* Macroscopic field at the current time level (moments of the current

@@ -151,13 +151,16 @@ class Oracle:
                                                _dptr(arrs[2]), up, pp))
 
     def set_closure(self, s):
-        """Per-node extra exchange per step (None switches it off); the array
-        is kept alive by the oracle object."""
+        """Per-node corrections (s1, s2) of c1 and c2 per step, shaped
+        (2,) + the lattice shape (None switches them off); the array is kept
+        alive by the oracle object."""
         if s is None:
             self._closure = None
             self._check(lib().cplb_ref_set_closure(self._h, None))
             return
         self._closure = np.ascontiguousarray(s, dtype=np.float64).reshape(-1).copy()
+        if self._closure.size != 2 * self.N:
+            raise ValueError(f"closure needs 2 planes of {self.N} values, got {self._closure.size}")
         self._check(lib().cplb_ref_set_closure(self._h, _dptr(self._closure)))
 
     def step(self, n=1):

@@ -154,7 +154,7 @@ def library():
         L.cplb_batch_num_nodes.restype = ctypes.c_int64
         L.cplb_batch_set_closure.argtypes = [vp, vp]
         L.cplb_batch_gather_fields.argtypes = [vp, ctypes.POINTER(i32), i32, i32, vp]
-        L.cplb_cnn_set_output_scale.argtypes = [vp, ctypes.c_float]
+        L.cplb_cnn_set_output_scale.argtypes = [vp, ctypes.c_float, ctypes.c_float]
         L.cplb_batch_init_planes.argtypes = [vp, vp, i32, i32, i32, i32]
         L.cplb_cnn_restrict.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         _lib = L
@@ -396,16 +396,18 @@ class Lattice:
         cplb_set_variant(self._h, v)
 
     def set_closure(self, s):
-        """Per-node extra exchange (a float32 device tensor of the lattice's
-        shape) applied by every following step, or None.  The tensor is kept
-        alive while set; the library stream waits for the caller's stream."""
+        """Per-node corrections (s1, s2) of c1 and c2 per step (a float32
+        device tensor of 2 N values: the s1 plane then the s2 plane, e.g.
+        shaped (2,) + the lattice shape) applied by every following step, or
+        None.  The tensor is kept alive while set; the library stream waits
+        for the caller's stream."""
         if s is None:
             cplb_set_closure(self._h, None)
             self._closure = None
             return
         t = s
         assert t.dtype == self.torch.float32 and t.is_cuda and t.is_contiguous()
-        assert t.numel() == self.N
+        assert t.numel() == 2 * self.N
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         cplb_set_closure(self._h, t.data_ptr())
         self._closure = t
@@ -622,14 +624,15 @@ class Batch:
         return cplb_batch_num_nodes(self._b)
 
     def set_closure(self, s):
-        """Per-node extra exchange of every case (float32 device tensor of
-        num_nodes values, cases one after the other), or None; kept alive
+        """Per-node corrections of every case (float32 device tensor of
+        2 num_nodes values: case after case, its s1 plane then its s2 plane;
+        with cases of equal size, shaped [n, 2, ny, nx]), or None; kept alive
         while set."""
         if s is None:
             cplb_batch_set_closure(self._b, None)
             self._closure = None
             return
-        assert s.dtype == self.torch.float32 and s.is_contiguous() and s.numel() == self.num_nodes
+        assert s.dtype == self.torch.float32 and s.is_contiguous() and s.numel() == 2 * self.num_nodes
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         cplb_batch_set_closure(self._b, s.data_ptr())
         self._closure = s
@@ -799,12 +802,14 @@ class ClosureNet:
         cplb_cnn_set_input_scale(self._c, sc)
 
     def forward(self, planes, out=None):
-        """planes: [B, cin, H, W] float32 device tensor -> [B, H, W]."""
+        """planes: [B, cin, H, W] float32 device tensor -> [B, 2, H, W], the
+        corrections (s1, s2) of c1 and c2, scaled and balanced per sample."""
         torch = self.torch
         assert planes.dtype == torch.float32 and planes.is_contiguous()
         B, cin = int(planes.shape[0]), int(planes.shape[1])
         if out is None:
-            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+            out = torch.empty((B, 2, self.H, self.W), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == B * 2 * self.H * self.W
         self._order()
         cplb_cnn_forward(self._c, B, planes.data_ptr(), cin, out.data_ptr())
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
@@ -812,13 +817,13 @@ class ClosureNet:
 
     def infer(self, planes, out=None):
         """Inference (no training buffers): planes [B, cin, H, W] float32
-        device tensor -> [B, H, W], equal to forward()."""
+        device tensor -> [B, 2, H, W], equal to forward()."""
         torch = self.torch
         assert planes.dtype == torch.float32 and planes.is_contiguous()
         B, cin = int(planes.shape[0]), int(planes.shape[1])
         if out is None:
-            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
-        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == B * self.H * self.W
+            out = torch.empty((B, 2, self.H, self.W), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == B * 2 * self.H * self.W
         self._order()
         _ccheck(self._c, library().cplb_cnn_infer(self._c, B, ctypes.c_void_p(planes.data_ptr()),
                                                   cin, ctypes.c_void_p(out.data_ptr())))
@@ -833,8 +838,9 @@ class ClosureNet:
         self.stream = stream
 
     def backward(self, target) -> float:
-        """Loss of the last forward against target [B, H, W] (FP64), and
-        every gradient."""
+        """Loss of the last forward's two output channels (before output
+        scale and balance) against target [B, 2, H, W] (FP64), and every
+        gradient."""
         assert target.dtype == self.torch.float32 and target.is_contiguous()
         self._order()
         return cplb_cnn_backward(self._c, target.data_ptr())
@@ -842,8 +848,10 @@ class ClosureNet:
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         cplb_cnn_adam(self._c, lr, beta1, beta2, eps)
 
-    def set_output_scale(self, scale):
-        _ccheck(self._c, library().cplb_cnn_set_output_scale(self._c, float(scale)))
+    def set_output_scale(self, scale1, scale2=None):
+        """Scales of the two outputs (the second defaults to the first)."""
+        scale2 = scale1 if scale2 is None else scale2
+        _ccheck(self._c, library().cplb_cnn_set_output_scale(self._c, float(scale1), float(scale2)))
 
 
 def restrict(fine, factor, out=None, stream=None):

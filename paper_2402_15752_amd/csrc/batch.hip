@@ -541,7 +541,9 @@ int cplb_batch_reduce(cplb_batch_t* b, int icase, double out[8]) {
 
 int cplb_batch_set_closure(cplb_batch_t* b, const float* dev_s) {
   if (!b) return CPLB_EINVAL;
-  for (int c = 0; c < b->n; ++c) b->cases[c].closure = dev_s ? dev_s + b->cases[c].out_off : nullptr;
+  // case c: its s1 plane then its s2 plane, from twice its node offset on
+  for (int c = 0; c < b->n; ++c)
+    b->cases[c].closure = dev_s ? dev_s + 2 * b->cases[c].out_off : nullptr;
   int rc = hip_check(b, hipMemcpyAsync(b->d_cases, b->cases.data(), b->n * sizeof(BatchCase),
                                        hipMemcpyHostToDevice, b->stream), "closure table upload");
   if (!rc) rc = hip_check(b, hipStreamSynchronize(b->stream), "closure table synchronise");

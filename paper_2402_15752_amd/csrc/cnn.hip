@@ -2,8 +2,8 @@
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulate) for every convolution.
 //
 // Network (fixed): four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 with
-// leaky-ReLU (slope 0.1) after the first three; the output is channel 0 of
-// the last layer.  Padding: periodic along x, zero outside the sample along
+// leaky-ReLU (slope 0.1) after the first three; the outputs are channels 0
+// and 1 of the last layer (the corrections of c1 and c2).  Padding: periodic along x, zero outside the sample along
 // y (samples are stacked along y).
 //
 // Layouts.  Activations are NHWC, pixel p = (sample * H + y) * W + x.  The
@@ -31,6 +31,7 @@ typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 constexpr float kSlope = 0.1f;
+constexpr int kOut = 2;  // output channels: the corrections of c1 and c2
 
 // FP32 -> BF16 with round to nearest, ties to even (finite inputs)
 __device__ inline unsigned short to_bf16(float f) {
@@ -42,6 +43,16 @@ __device__ inline float from_bf16(unsigned short h) { return __uint_as_float((un
 
 __device__ inline float4v mfma(short4v a, short4v b, float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// gfx950's double-rate shape: A[m][k] lane l holds A[l % 16][8 g + j],
+// B[k][n] lane l holds B[8 g + j][l % 16] (g = l / 16, j = 0..7); D as above
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ inline float4v mfma32(bf16x8 a, bf16x8 b, float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline bf16x8 lds8(const unsigned short* p) {
+  return __builtin_bit_cast(bf16x8, *(const uint4*)p);
 }
 
 enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2, kInfAct = 3, kInfOut = 4 };
@@ -117,13 +128,15 @@ __device__ inline void stage_matrix(Src src_row, unsigned short* dst, Valid vali
 
 // Each block stages its input rows (with a one-pixel halo, periodic in x)
 // and the layer's BF16 weights in LDS once, then every wave runs its row x
-// all COUT channels with both MFMA operands read from LDS.  Pixel and weight
-// rows are padded by 8 bytes so that the 16 lanes of a 64-bit LDS read hit
-// distinct banks.  The accumulation order (tap, channel group, MFMA) is that
-// of a direct loop over the taps.
+// all COUT channels with both MFMA operands read from LDS, 32 values of the
+// K = 9 CIN reduction (k = tap CIN + ci) per 16x16x32 MFMA: one tap of 32
+// channels, or two taps of 16 channels (K padded with zero weights to a
+// multiple of 32).  Pixel and weight rows are padded by 16 bytes so that the
+// 16 lanes of a 128-bit LDS read hit distinct banks.
 // kFwdAct / kFwdLinear: Z = conv(X) + b (FP32), A = act(Z) (BF16).
 // kInfAct: A = lrelu(conv(X) + b) only (inference: no FP32 copy).
-// kInfOut: out[p] = scale * (conv(X) + b)[channel 0], written to Z.
+// kInfOut: out[sample][c][q] = scale_c * (conv(X) + b)[channel c] for the
+// kOut output channels, written to Z ([sample][kOut][H W] planes).
 // kBwd: X is dZ of the layer above, W its flipped transpose; the result is
 // dA of the layer below, written as dZ = dA * lrelu'(Zprev) in BF16.
 template <int CIN, int COUT, int MODE>
@@ -133,10 +146,11 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
                                                    float* __restrict__ Z,
                                                    unsigned short* __restrict__ A,
                                                    const float* __restrict__ Zprev, int H, int W,
-                                                   int rows, float scale) {
+                                                   int rows, float scale0, float scale1) {
   constexpr int NT = COUT / 16, K = 9 * CIN, G = kConvCols / 16;
-  constexpr int PS = CIN + 4;            // LDS pixel stride (BF16 values)
-  constexpr int KS = K + 4;              // LDS weight-row stride
+  constexpr int NK = (K + 31) / 32;      // K steps of 32
+  constexpr int PS = CIN + 8;            // LDS pixel stride (BF16 values)
+  constexpr int KS = 32 * NK + 8;        // LDS weight-row stride
   constexpr int LC = kConvCols + 2, LR = kConvRowsF + 2;
   static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels in multiples of 16");
   __shared__ __align__(16) unsigned short sx[LR * LC * PS];
@@ -152,6 +166,11 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
   stage_rows<CIN, PS, kConvRowsF, 64 * kConvRowsF>(X, sx, R0, x0, W, rows);
   stage_matrix<COUT, K, KS, 64 * kConvRowsF>([&](int co) { return Wg + (long long)co * K; }, sw,
                             [](int) { return true; });
+  if constexpr (32 * NK > K) {
+    // zero weights of the padded K range
+    for (int e = threadIdx.x; e < COUT * (32 * NK - K); e += 64 * kConvRowsF)
+      sw[(e / (32 * NK - K)) * KS + K + e % (32 * NK - K)] = 0;
+  }
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -165,24 +184,24 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
+  for (int ks = 0; ks < NK; ++ks) {
+    // this lane's 8 values of the K step: tap and first channel
+    const int k = 32 * ks + 8 * g;
+    const int tap = k / CIN, ci = k % CIN;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    if (y + dy < 0 || y + dy >= H) continue;  // zero padding in y (uniform per wave)
-    const unsigned short* xrow = sx + (wave + 1 + dy) * LC * PS;
+    // zero padding in y, and the zero-weight K padding past the ninth tap
+    const bool live = tap < 9 && y + dy >= 0 && y + dy < H;
+    const unsigned short* xrow = sx + (wave + 1 + (tap < 9 ? dy : 0)) * LC * PS;
+    bf16x8 b[NT];
 #pragma unroll
-    for (int cg = 0; cg < CIN / 16; ++cg) {
-      const int k = tap * CIN + cg * 16 + 4 * g;
-      short4v b[NT];
+    for (int t = 0; t < NT; ++t) b[t] = lds8(sw + (t * 16 + m) * KS + k);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = __builtin_bit_cast(short4v, *(const u64*)(sw + (t * 16 + m) * KS + k));
+    for (int q = 0; q < G; ++q) {
+      const int col = q * 16 + m + (tap < 9 ? dx : 0) + 1;  // LDS column of this lane's A row
+      bf16x8 a = lds8(xrow + col * PS + ci);
+      if (!live) a = bf16x8{};
 #pragma unroll
-      for (int q = 0; q < G; ++q) {
-        const int col = q * 16 + m + dx + 1;  // LDS column of this lane's A row
-        const short4v a =
-            __builtin_bit_cast(short4v, *(const u64*)(xrow + col * PS + cg * 16 + 4 * g));
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[q][t] = mfma(a, b[t], acc[q][t]);
-      }
+      for (int t = 0; t < NT; ++t) acc[q][t] = mfma32(a, b[t], acc[q][t]);
     }
   }
   // D[pixel 4 g + j][channel l % 16]
@@ -192,7 +211,7 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + m;
-      if (MODE == kInfOut && co != 0) continue;
+      if (MODE == kInfOut && co >= kOut) continue;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int xp = xq + 4 * g + j;
@@ -204,7 +223,8 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
           v *= zp > 0.f ? 1.f : kSlope;
           A[p * COUT + co] = to_bf16(v);
         } else if (MODE == kInfOut) {
-          Z[p] = scale * (v + bias[0]);
+          const long long q = (long long)(R % H) * W + xp, hw = (long long)H * W;
+          Z[((long long)(R / H) * kOut + co) * hw + q] = (co == 0 ? scale0 : scale1) * (v + bias[co]);
         } else {
           v += bias[co];
           if (MODE != kInfAct) Z[p * COUT + co] = v;
@@ -365,11 +385,35 @@ __global__ void pack_kernel(const float* __restrict__ planes, int cin, const flo
   X0[i] = c < cin ? to_bf16(scale[c] * planes[(s * cin + c) * hw + q]) : (unsigned short)0;
 }
 
-// out[p] = scale * Z4[p][0]
-__global__ void output_kernel(const float* __restrict__ Z4, long long P, float scale,
-                              float* __restrict__ out) {
+// out[sample][c][q] = scale_c * Z4[p][c], p = sample * hw + q, c < kOut
+__global__ void output_kernel(const float* __restrict__ Z4, long long P, long long hw,
+                              float scale0, float scale1, float* __restrict__ out) {
   const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (p < P) out[p] = scale * Z4[p * 16];
+  if (p >= P) return;
+  const long long smp = p / hw, q = p % hw;
+  out[(smp * kOut + 0) * hw + q] = scale0 * Z4[p * 16 + 0];
+  out[(smp * kOut + 1) * hw + q] = scale1 * Z4[p * 16 + 1];
+}
+
+// Per sample (one work-group each): subtract half the sample's mean of
+// out[c=0] + out[c=1] from both planes, so that the corrections of c1 and c2
+// add nothing to the sample's total scalar.  FP64 sum in a fixed order.
+__global__ __launch_bounds__(256) void balance_kernel(float* __restrict__ out, long long hw) {
+  __shared__ double red[256];
+  float* o = out + (long long)blockIdx.x * kOut * hw;
+  double s = 0.0;
+  for (long long q = threadIdx.x; q < hw; q += 256) s += (double)o[q] + (double)o[hw + q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const float m = (float)(red[0] / (2.0 * (double)hw));
+  for (long long q = threadIdx.x; q < hw; q += 256) {
+    o[q] -= m;
+    o[hw + q] -= m;
+  }
 }
 
 __global__ void restrict_kernel(const float* __restrict__ fine, int nsamples, int H, int W, int f,
@@ -388,19 +432,25 @@ __global__ void restrict_kernel(const float* __restrict__ fine, int nsamples, in
   coarse[i] = acc / (float)(f * f);
 }
 
-// loss partials (FP64) and dZ4 = d(mean (z - t)^2) / dz4 in BF16 (channel 0)
+// loss partials (FP64) and dZ4 = d(mean (z - t)^2) / dz4 in BF16, the mean
+// over the kOut output channels of every pixel; target [sample][c][hw]
 __global__ void loss_kernel(const float* __restrict__ Z4, const float* __restrict__ target,
-                            long long P, unsigned short* __restrict__ dZ4,
+                            long long P, long long hw, unsigned short* __restrict__ dZ4,
                             double* __restrict__ partial) {
   __shared__ double red[256];
   double s = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
+  const float inv = 1.0f / (float)P;  // 2 / (kOut P)
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += stride) {
-    const float r = Z4[p * 16] - target[p];
-    s += (double)r * (double)r;
-    dZ4[p * 16] = to_bf16(2.0f * r / (float)P);
+    const long long smp = p / hw, q = p % hw;
 #pragma unroll
-    for (int c = 1; c < 16; ++c) dZ4[p * 16 + c] = 0;
+    for (int c = 0; c < kOut; ++c) {
+      const float r = Z4[p * 16 + c] - target[(smp * kOut + c) * hw + q];
+      s += (double)r * (double)r;
+      dZ4[p * 16 + c] = to_bf16(r * inv);
+    }
+#pragma unroll
+    for (int c = kOut; c < 16; ++c) dZ4[p * 16 + c] = 0;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -411,7 +461,7 @@ __global__ void loss_kernel(const float* __restrict__ Z4, const float* __restric
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void sum_partials(const double* __restrict__ partial, int n, long long P,
+__global__ void sum_partials(const double* __restrict__ partial, int n, long long count,
                              double* __restrict__ out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -422,7 +472,7 @@ __global__ void sum_partials(const double* __restrict__ partial, int n, long lon
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0] / (double)P;
+  if (threadIdx.x == 0) out[0] = red[0] / (double)count;
 }
 
 // Adam on the FP32 master parameters (bias-corrected step size c1 / (sqrt(v^) + eps))
@@ -457,12 +507,13 @@ __global__ void weights_kernel(const float* __restrict__ W, int cin, int cout,
 
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
-                    int W, int rows, float scale, hipStream_t s) {
+                    int W, int rows, float scale0, float scale1, hipStream_t s) {
   const long long blocks =
       (long long)((W + kConvCols - 1) / kConvCols) * ((rows + kConvRowsF - 1) / kConvRowsF);
   const dim3 grid((unsigned)blocks), blk(64 * kConvRowsF);
 #define PFLB_CONV(CI, CO, MO) \
-  hipLaunchKernelGGL((conv_kernel<CI, CO, MO>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, scale)
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MO>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, \
+                     scale0, scale1)
   // forward: layer l maps C_in(l) -> C_out(l); backward (the adjoint of
   // layer l) maps C_out(l) -> C_in(l)
   switch (mode) {
@@ -525,9 +576,15 @@ hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long 
   return hipGetLastError();
 }
 
-hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(output_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, Z4, P,
-                     scale, out);
+hipError_t cnn_output(const float* Z4, long long P, long long hw, float scale0, float scale1,
+                      float* out, hipStream_t s) {
+  hipLaunchKernelGGL(output_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, Z4, P, hw,
+                     scale0, scale1, out);
+  return hipGetLastError();
+}
+
+hipError_t cnn_balance(float* out, int nsamples, long long hw, hipStream_t s) {
+  hipLaunchKernelGGL(balance_kernel, dim3(nsamples), dim3(256), 0, s, out, hw);
   return hipGetLastError();
 }
 
@@ -539,12 +596,12 @@ hipError_t cnn_restrict(const float* fine, int nsamples, int H, int W, int f, fl
   return hipGetLastError();
 }
 
-hipError_t cnn_loss(const float* Z4, const float* target, long long P, unsigned short* dZ4,
-                    double* partial, int nparts, double* loss, hipStream_t s) {
-  hipLaunchKernelGGL(loss_kernel, dim3(nparts), dim3(256), 0, s, Z4, target, P, dZ4, partial);
+hipError_t cnn_loss(const float* Z4, const float* target, long long P, long long hw,
+                    unsigned short* dZ4, double* partial, int nparts, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(loss_kernel, dim3(nparts), dim3(256), 0, s, Z4, target, P, hw, dZ4, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, partial, nparts, P, loss);
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, partial, nparts, kOut * P, loss);
   return hipGetLastError();
 }
 

@@ -97,7 +97,7 @@ struct cplb_cnn {
   CnnLayout L;
   long long used_P;  // pixels of the last forward
   int adam_t;
-  float out_scale;
+  float out_scale[2];  // output scale of the c1 and c2 corrections
   char err[512];
   template <class X>
   X* at(size_t off) const {
@@ -166,7 +166,7 @@ int cplb_cnn_create(int nsamples, int H, int W, void* dev_workspace, size_t byte
   c->L = cnn_layout(c->P, W);
   c->used_P = 0;
   c->adam_t = 0;
-  c->out_scale = 1.f;
+  c->out_scale[0] = c->out_scale[1] = 1.f;
   c->err[0] = 0;
   const float one[16] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
   rc = hip_check(c, hipMemcpyAsync(c->at<float>(c->L.scale), one, sizeof(one),
@@ -253,14 +253,16 @@ int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int c
     const float* bias = c->at<float>(c->L.theta) + w_offset(l) + kCout[l] * kCin[l] * 9;
     rc = hip_check(c, cnn_conv(l, kConvForward, x, c->at<unsigned short>(c->L.wg[l]), bias,
                                c->at<float>(c->L.z[l]), c->at<unsigned short>(c->L.a[l]), nullptr,
-                               c->H, c->W, rows, 1.f, c->stream), "forward convolution");
+                               c->H, c->W, rows, 1.f, 1.f, c->stream), "forward convolution");
     if (rc) return rc;
     x = c->at<unsigned short>(c->L.a[l]);
   }
   c->used_P = P;
-  if (dev_out)
-    rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, c->out_scale, dev_out,
-                                 c->stream), "output copy");
+  if (dev_out) {
+    rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, hw, c->out_scale[0],
+                                 c->out_scale[1], dev_out, c->stream), "output copy");
+    if (!rc) rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->stream), "output balance");
+  }
   return rc;
 }
 
@@ -283,10 +285,12 @@ int cplb_cnn_infer(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin
     const bool last = l == kLayers - 1;
     rc = hip_check(c, cnn_conv(l, last ? kConvInferOut : kConvInfer, x,
                                c->at<unsigned short>(c->L.wg[l]), bias, last ? dev_out : nullptr,
-                               a, nullptr, c->H, c->W, rows, c->out_scale, c->stream),
+                               a, nullptr, c->H, c->W, rows, c->out_scale[0], c->out_scale[1],
+                               c->stream),
                    "inference convolution");
     x = a;
   }
+  if (!rc) rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->stream), "output balance");
   c->used_P = 0;  // the training buffers of the last forward are gone
   return rc;
 }
@@ -305,7 +309,7 @@ int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
   const int rows = (int)(P / c->W);
   double* dloss = c->at<double>(c->L.loss);
   int rc = hip_check(c, cnn_loss(c->at<float>(c->L.z[kLayers - 1]), dev_target, P,
-                                 c->at<unsigned short>(c->L.dz[kLayers - 1]),
+                                 (long long)c->H * c->W, c->at<unsigned short>(c->L.dz[kLayers - 1]),
                                  c->at<double>(c->L.lpart), kLossParts, dloss, c->stream),
                      "loss");
   if (rc) return rc;
@@ -321,7 +325,7 @@ int cplb_cnn_backward(cplb_cnn_t* c, const float* dev_target, double* loss) {
     rc = hip_check(c, cnn_conv(l, kConvAdjoint, c->at<unsigned short>(c->L.dz[l]),
                                c->at<unsigned short>(c->L.wf[l]), nullptr, nullptr,
                                c->at<unsigned short>(c->L.dz[l - 1]), c->at<float>(c->L.z[l - 1]),
-                               c->H, c->W, rows, 1.f, c->stream), "input gradient");
+                               c->H, c->W, rows, 1.f, 1.f, c->stream), "input gradient");
   }
   if (rc) return rc;
   if (loss) {
@@ -346,9 +350,10 @@ int cplb_cnn_adam(cplb_cnn_t* c, float lr, float beta1, float beta2, float eps) 
   return rc;
 }
 
-int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale) {
-  if (!c || !std::isfinite(scale)) return CPLB_EINVAL;
-  c->out_scale = scale;
+int cplb_cnn_set_output_scale(cplb_cnn_t* c, float scale1, float scale2) {
+  if (!c || !std::isfinite(scale1) || !std::isfinite(scale2)) return CPLB_EINVAL;
+  c->out_scale[0] = scale1;
+  c->out_scale[1] = scale2;
   return CPLB_OK;
 }
 

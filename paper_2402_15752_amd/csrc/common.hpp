@@ -95,6 +95,22 @@ struct Codec<__hip_bfloat16, float> {
   __device__ static __hip_bfloat16 st(float x, float inv_w) { return __float2bfloat16(x * inv_w); }
 };
 
+// x + w d stored: for FP64 and FP32 storage exactly that sum; 16-bit storage
+// keeps (x + w d) / w and forms it as x / w + d, one fused operation
+template <class S, class T>
+__device__ inline S store_shifted(T x, T d, T w, T inv_w) {
+  return Codec<S, T>::st(x + w * d, inv_w);
+}
+template <>
+__device__ inline __half store_shifted<__half, float>(float x, float d, float, float inv_w) {
+  return __float2half_rn(__builtin_fmaf(x, inv_w, d));
+}
+template <>
+__device__ inline __hip_bfloat16 store_shifted<__hip_bfloat16, float>(float x, float d, float,
+                                                                      float inv_w) {
+  return __float2bfloat16(__builtin_fmaf(x, inv_w, d));
+}
+
 // the value a population of weight w stored as x reads back as (x itself
 // for FP64 and FP32 storage)
 template <class S, class T>
@@ -448,16 +464,25 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
 //   H_1 = w [c.d_t(c1 u)/cs^2 + c.n 4 (1-phi) c1/W + A D_m (Keq c2 phi - c1 (1-phi))],
 //   H_2 = w [c.d_t(c2 u)/cs^2 - c.n 4 phi c2/W + A D_m (c1 (1-phi) - Keq c2 phi)],
 //   ~H_1 = -w D_m grad phi . grad psi = -~H_2
-// `xs` is an extra exchange per step carried the same way as ~H (h1 loses
-// w_i xs, h2 gains it, so c1 + c2 is untouched): the learned closure's
-// correction on a coarse grid, 0 otherwise.
+// `xs1`, `xs2` are per-node corrections of c1 and c2 per step: the learned
+// closure's on a coarse grid, 0 otherwise.  They are carried the same way as
+// ~H (h_k loses w_i s_k), with (s1, s2) = J^-1 (xs1, xs2) and J the Jacobian
+// of the implicit recovery (c1, c2) = R(S1, S2) (Sec. III C, see moments):
+//   s1 = (1 + a (1 - phi)) xs1 - a Keq phi xs2,
+//   s2 = -a (1 - phi) xs1 + (1 + a Keq phi) xs2,   a = A D_m / 2,
+// so that the recovered c_k is lowered by xs_k (exactly where phi and D_m do
+// not change over the step), not by the part of it that the exchange in the
+// recovery leaves (s1 + s2 = xs1 + xs2).
 template <class LF, class T, class Emit>
 __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], const T (&dh2)[LF::Q],
                                  const Node<T>& s, const T (&n)[3], const T (&gphi)[3],
                                  const T (&gpsi)[3], const Flow<T>& fl, const T (&dJ1)[3],
-                                 const T (&dJ2)[3], Emit&& emit, T xs = T(0)) {
+                                 const T (&dJ2)[3], Emit&& emit, T xs1 = T(0), T xs2 = T(0)) {
   const T M1 = P.A * s.Dm * (P.Keq * s.c2 * s.phi - s.c1 * s.omphi);
-  const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]) + xs;
+  const T aux = s.Dm * (gphi[0] * gpsi[0] + gphi[1] * gpsi[1] + gphi[2] * gpsi[2]);
+  const T ra = P.half_A * s.Dm, ra1 = ra * s.omphi, ra2 = ra * (P.Keq * s.phi);
+  const T cs1 = xs1 + (ra1 * xs1 - ra2 * xs2), cs2 = xs2 + (ra2 * xs2 - ra1 * xs1);
+  const T aux1 = aux + cs1, aux2 = aux - cs2;
   const T fl1 = P.four_over_W * s.omphi * s.c1;
   const T fl2 = P.four_over_W * s.phi * s.c2;
   auto cu_of = [&](int i) {
@@ -482,8 +507,8 @@ __device__ inline void collide_h(const KParams<T>& P, const T (&dh1)[LF::Q], con
     const T k = kw<LF, T>(i);
     const T H1 = k * cj1 + w * (cn * fl1 + M1);
     const T H2 = k * cj2 - w * (cn * fl2 + M1);
-    emit(i, relax(dh1[i], e1, P.del_h1, P.hdel_h1, H1) - w * aux,
-         relax(dh2[i], e2, P.del_h2, P.hdel_h2, H2) + w * aux);
+    emit(i, relax(dh1[i], e1, P.del_h1, P.hdel_h1, H1) - w * aux1,
+         relax(dh2[i], e2, P.del_h2, P.hdel_h2, H2) + w * aux2);
   }
 }
 
@@ -517,12 +542,13 @@ __device__ inline void collide(const KParams<T>& P, const T (&df)[LF::Q], const 
                                const T (&dh1)[LF::Q], const T (&dh2)[LF::Q], const Node<T>& s,
                                const T (&gphi)[3], const T (&gpsi)[3], const Flow<T>& fl,
                                const T (&dJphi)[3], const T (&dJ1)[3], const T (&dJ2)[3],
-                               EF&& emit_f, EG&& emit_g, EH&& emit_h, T xs = T(0)) {
+                               EF&& emit_f, EG&& emit_g, EH&& emit_h, T xs1 = T(0),
+                               T xs2 = T(0)) {
   T n[3];
   normal(P, gphi, n);
   collide_g<LG>(P, g, gphi, fl, emit_g);
   collide_f<LF>(P, df, s, n, fl, dJphi, emit_f);
-  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h, xs);
+  collide_h<LF>(P, dh1, dh2, s, n, gphi, gpsi, fl, dJ1, dJ2, emit_h, xs1, xs2);
 }
 
 // ------------------------------------------------------------- equilibria

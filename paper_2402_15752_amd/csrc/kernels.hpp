@@ -39,8 +39,8 @@ constexpr int kVariants3D = 8;
 const char* step2d_variant_name(int v);
 const char* step3d_variant_name(int v);
 
-// closure: per-node extra exchange added to the auxiliary scalar source
-// (N FP32 values in node order), or null
+// closure: per-node corrections of c1 and c2 carried like the auxiliary
+// scalar source (2 N FP32 values: the plane of s1, then that of s2), or null
 // hin: history of the previous level (read), hout: this level's (written)
 template <class S, class T>
 hipError_t launch_step2d(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
@@ -64,7 +64,7 @@ struct BatchCase {
   int wall_x, wall_y;  // 1: half-way bounce-back walls on both faces
   unsigned int sS;     // bytes between two population planes
   unsigned int sT;     // bytes between two history / field planes
-  const float* closure;  // per-node extra exchange of this case, or null
+  const float* closure;  // per-node corrections (s1 plane, s2 plane) of this case, or null
   long long out_off;     // first value of this case in a gathered field buffer
 };
 
@@ -104,11 +104,12 @@ hipError_t launch_batch_gather(const BatchCase* cases, int ncases, long long max
 // H rows stacked.  Modes: training forward (Z in FP32 and A = act(Z) in
 // BF16; the last layer linear), the adjoint of layer l (dZ of layer l in, dZ
 // of layer l - 1 out), inference (A only; the last layer writes
-// scale * channel 0 to Z, which is then the [P] output).
+// scale0 * channel 0 and scale1 * channel 1 to Z, which is then the
+// [sample][2][H W] output).
 enum { kConvForward = 0, kConvAdjoint = 2, kConvInfer = 3, kConvInferOut = 4 };
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
-                    int W, int rows, float scale, hipStream_t s);
+                    int W, int rows, float scale0, float scale1, hipStream_t s);
 // weight and bias gradients of layer l over `rows` rows of width W; partial
 // and bpart hold cnn_wgrad_parts(W, rows) partial sums of COUT x 9 CIN and
 // COUT floats
@@ -118,12 +119,17 @@ hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* d
                      hipStream_t s);
 hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
                     unsigned short* X0, hipStream_t s);
-hipError_t cnn_output(const float* Z4, long long P, float scale, float* out, hipStream_t s);
+// out [sample][2][hw] = scale_c * channel c of Z4, c = 0, 1
+hipError_t cnn_output(const float* Z4, long long P, long long hw, float scale0, float scale1,
+                      float* out, hipStream_t s);
+// per sample: subtract half the mean of out[c=0] + out[c=1] from both planes
+hipError_t cnn_balance(float* out, int nsamples, long long hw, hipStream_t s);
 // block average: coarse[s][y][x] = mean of fine[s][f y + j][f x + i], 0 <= i, j < f
 hipError_t cnn_restrict(const float* fine, int nsamples, int H, int W, int f, float* coarse,
                         hipStream_t s);
-hipError_t cnn_loss(const float* Z4, const float* target, long long P, unsigned short* dZ4,
-                    double* partial, int nparts, double* loss, hipStream_t s);
+// mean over the two output channels of (Z4 - target)^2, target [sample][2][hw]
+hipError_t cnn_loss(const float* Z4, const float* target, long long P, long long hw,
+                    unsigned short* dZ4, double* partial, int nparts, double* loss, hipStream_t s);
 hipError_t cnn_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float b1,
                     float b2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t cnn_weights(const float* W, int cin, int cout, unsigned short* Wg, unsigned short* Wf,

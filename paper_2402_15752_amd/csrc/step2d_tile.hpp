@@ -33,7 +33,8 @@ struct Geo2 {
   int tiles_x, ntiles;
   Off sS;  // bytes between two population planes
   Off sT;  // bytes between two history / field planes
-  const float* closure;  // per-node extra exchange (learned closure) or null
+  const float* closure;  // per-node corrections of c1, c2 (learned closure: the
+                         // plane of s1, then that of s2) or null
 };
 
 // One TX x TY tile of the fused 2-D step (moments, stencils, macros,
@@ -318,7 +319,8 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
         st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
         st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
       },
-      G.closure ? T(G.closure[y * nx + x]) : T(0));
+      G.closure ? T(G.closure[y * nx + x]) : T(0),
+      G.closure ? T(G.closure[(long long)nx * ny + y * nx + x]) : T(0));
 }
 
 }  // namespace pflb

@@ -11,7 +11,7 @@ from oracle import cnn_ref as C
 def small_case(seed, B=2, H=5, W=6):
     rng = np.random.default_rng(seed)
     x = rng.normal(size=(B, 16, H, W))
-    t = rng.normal(size=(B, H, W)) * 0.1
+    t = rng.normal(size=(B, 2, H, W)) * 0.1
     theta = C.init_params(seed) * 3.0  # larger last layer: every layer matters
     theta += rng.normal(size=theta.size) * 0.01  # non-zero biases
     return x, t, theta
@@ -39,13 +39,13 @@ def test_gradient_matches_finite_differences():
     x, t, theta = small_case(2)
     loss, grad = C.loss_and_grad(theta, x, t)
     rng = np.random.default_rng(3)
-    # every layer's weights and biases, including the output layer's channel 0
+    # every layer's weights and biases, including the output layer's channels 0 and 1
     idx = list(rng.choice(theta.size, size=60, replace=False))
     k = 0
     for ci, co in C.LAYERS:
-        idx += [k, k + co * ci * 9]  # first weight, first bias of each layer
+        idx += [k, k + co * ci * 9, k + co * ci * 9 + 1]  # first weight, first biases of each layer
         k += co * ci * 9 + co
-    h = 1e-6
+    h = 1e-5  # the loss is ~90 here: smaller steps drown in its round-off (eps L / h)
     for i in idx:
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h
@@ -78,10 +78,9 @@ def test_param_vector_layout():
 
 def test_oracle_closure_term_closed_form():
     """Uniform fields at partition equilibrium (no exchange, no gradients)
-    and a uniform closure s: one step moves S1 = c1 - s, S2 = c2 + s, and the
-    exact recovery c1' = S1 + a e', c2' = S2 - a e' with
-    e' = (Keq phi S2 - (1 - phi) S1) / (1 + a (Keq phi + 1 - phi)),
-    a = A D_m / 2, D_m = D1 D2 / (Keq D1 (1 - phi) + D2 phi) (Sec. III C)."""
+    and a uniform closure (x, -x), a pure exchange: one step lowers c1 by x
+    and raises c2 by x exactly -- the closure's source is the inverse of the
+    implicit recovery's response (Sec. III C) applied to the correction."""
     import workloads as W
     from oracle import ref
     p = W.params(nx=6, ny=5, D1=0.07, D2=0.02, Keq=0.6, A=0.4)
@@ -91,21 +90,27 @@ def test_oracle_closure_term_closed_form():
     shp = W.shape_of(p)
     o = ref.Oracle(p)
     o.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
-    s = 1.7e-3
-    o.set_closure(np.full(shp, s))
+    x = 1.7e-3
+    o.set_closure(np.stack([np.full(shp, x), np.full(shp, -x)]))
     o.step(1)
-    Dm = p["D1"] * p["D2"] / (K * p["D1"] * (1 - phi) + p["D2"] * phi)
-    a = 0.5 * p["A"] * Dm
-    S1, S2 = c1 - s, c2 + s
-    e = (K * phi * S2 - (1 - phi) * S1) / (1 + a * (K * phi + 1 - phi))
-    np.testing.assert_allclose(o.field("c1"), S1 + a * e, rtol=0, atol=1e-15)
-    np.testing.assert_allclose(o.field("c2"), S2 - a * e, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o.field("c1"), c1 - x, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o.field("c2"), c2 + x, rtol=0, atol=1e-15)
     np.testing.assert_allclose(o.field("phi"), phi, rtol=0, atol=1e-15)
     # without the closure the state stays put
     o2 = ref.Oracle(p)
     o2.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
     o2.step(1)
     np.testing.assert_allclose(o2.field("c1"), c1, rtol=0, atol=1e-15)
+    # the source it carries: S_k = c_k - s_k with the exact recovery
+    # c1' = S1 + a e', c2' = S2 - a e', e' = (Keq phi S2 - (1 - phi) S1) /
+    # (1 + a (Keq phi + 1 - phi)), a = A D_m / 2, inverted by hand
+    Dm = p["D1"] * p["D2"] / (K * p["D1"] * (1 - phi) + p["D2"] * phi)
+    a = 0.5 * p["A"] * Dm
+    s1 = (1 + a * (1 - phi)) * x + a * K * phi * x
+    s2 = -a * (1 - phi) * x - (1 + a * K * phi) * x
+    S1, S2 = c1 - s1, c2 - s2
+    e = (K * phi * S2 - (1 - phi) * S1) / (1 + a * (K * phi + 1 - phi))
+    assert abs(S1 + a * e - (c1 - x)) <= 1e-15 and abs(S2 - a * e - (c2 + x)) <= 1e-15
 
 
 def test_bf16_rounding_is_round_to_nearest_even():
@@ -136,3 +141,40 @@ def test_bf16_storage_model_is_close_to_fp64():
     o64 = C.forward(th, xx)[0]
     o16 = C.forward(th, xx, storage="bf16")[0]
     assert np.max(np.abs(o16 - o64)) <= 1e-2 * np.max(np.abs(o64))
+
+
+def test_balance_removes_the_total_per_sample():
+    """The applied corrections add nothing to each sample's total scalar and
+    keep the exchange part s1 - s2 of the outputs unchanged."""
+    x, t, theta = small_case(8, B=3)
+    raw = C.forward(theta, x)[0]
+    out = C.output(theta, x, scale=(2.0, 0.5))
+    np.testing.assert_allclose((out[:, 0] + out[:, 1]).sum(axis=(1, 2)), 0.0, atol=1e-12)
+    np.testing.assert_allclose(out[:, 0] - out[:, 1], 2.0 * raw[:, 0] - 0.5 * raw[:, 1],
+                               rtol=1e-12, atol=1e-14)
+    # a pure exchange (s2 = -s1) passes through unchanged
+    ex = np.stack([raw[:, 0], -raw[:, 0]], axis=1)
+    np.testing.assert_allclose(C.balance(ex), ex, rtol=0, atol=1e-15)
+
+
+def test_oracle_closure_corrections_per_scalar():
+    """Uniform fields at partition equilibrium and uniform corrections
+    (x1, x2) of either sign: one step lowers c1 by x1 and c2 by x2, so the
+    total by x1 + x2 per node."""
+    import workloads as W
+    from oracle import ref
+    p = W.params(nx=6, ny=5, D1=0.07, D2=0.02, Keq=0.6, A=0.4)
+    phi, K = 0.3, p["Keq"]
+    c2 = 0.5
+    c1 = K * phi * c2 / (1.0 - phi)
+    shp = W.shape_of(p)
+    o = ref.Oracle(p)
+    o.init_fields(np.full(shp, phi), np.full(shp, c1), np.full(shp, c2))
+    x1, x2 = 1.1e-3, 2.3e-3
+    o.set_closure(np.stack([np.full(shp, x1), np.full(shp, x2)]))
+    o.step(1)
+    np.testing.assert_allclose(o.field("c1"), c1 - x1, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o.field("c2"), c2 - x2, rtol=0, atol=1e-15)
+    r = o.reduce()
+    n = np.prod(shp)
+    assert abs(r["sum_c"] - n * (c1 + c2 - x1 - x2)) <= 1e-13 * n

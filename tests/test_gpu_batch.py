@@ -177,17 +177,18 @@ def test_full_sweep_sampled_cases(cplb):
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_batch_closure_equals_single_lattice_closure(cplb, precision):
-    """A per-node closure exchange over the whole batch (cases one after the
-    other) acts on each case exactly as the same slice does on the case run
-    alone: bitwise equal fields, and c1 + c2 still conserved."""
+    """Per-node closure corrections over the whole batch (case after case,
+    its s1 plane then its s2 plane) act on each case exactly as the same
+    slice does on the case run alone: bitwise equal fields, and c1 + c2
+    moved by exactly what the corrections take (8 sum (s1 + s2))."""
     import torch
     cases = mixed_cases(precision, seed=9)
     say(f"batch closure vs single-lattice closure, {precision}, 8 steps")
     b = make_batch(cplb, cases)
     n = b.num_nodes
     assert n == sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
-    s = torch.tensor(np.random.default_rng(2).normal(size=n) * 2e-3, dtype=torch.float32,
-                     device="cuda").contiguous()
+    s_host = (np.random.default_rng(2).normal(size=2 * n) * 2e-3).astype(np.float32)
+    s = torch.tensor(s_host, device="cuda").contiguous()
     b.set_closure(s)
     c0 = [b.reduce(k)["sum_c"] for k in range(len(cases))]
     b.step(8)
@@ -196,13 +197,14 @@ def test_batch_closure_equals_single_lattice_closure(cplb, precision):
         nx, ny = c["params"]["nx"], c["params"]["ny"]
         g = cplb.Lattice(c["params"])
         g.init_sdf(c["sdf"], c1=c["init"]["c1"], c2=c["init"]["c2"])
-        g.set_closure(s[off:off + nx * ny].view(ny, nx).contiguous())
+        g.set_closure(s[2 * off:2 * (off + nx * ny)].view(2, ny, nx).contiguous())
         g.step(8)
         for f in ("phi", "c1", "c2", "ux", "uy", "p"):
             a, r = b.field(k, f).cpu().numpy(), g.field(f).cpu().numpy()
             assert np.array_equal(a, r), (k, f, float(np.abs(a - r).max()))
         tol = 1e-12 if precision == "f64" else 1e-6
-        assert abs(b.reduce(k)["sum_c"] - c0[k]) <= tol * abs(c0[k]), k
+        taken = 8.0 * float(s_host[2 * off:2 * (off + nx * ny)].astype(np.float64).sum())
+        assert abs(b.reduce(k)["sum_c"] - (c0[k] - taken)) <= tol * abs(c0[k]), k
         off += nx * ny
         g.close()
     # switching the closure off restores the plain step

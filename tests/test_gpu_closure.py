@@ -68,12 +68,17 @@ def setup_net(cplb, B, H, Wd, seed, cin=5):
 def test_forward_matches_oracle(cplb, B, H, Wd):
     say(f"cnn forward B={B} H={H} W={Wd}")
     net, theta, x, tp = setup_net(cplb, B, H, Wd, seed=B * 100 + H)
+    net.set_output_scale(1.5, 0.75)
     out = net.forward(tp).cpu().numpy()
-    ref_out = C.forward(theta, x)[0]
-    ref16 = C.forward(theta, x, storage="bf16")[0]
+    assert out.shape == (B, 2, H, Wd)
+    ref_out = C.output(theta, x, scale=(1.5, 0.75))
+    ref16 = C.output(theta, x, scale=(1.5, 0.75), storage="bf16")
     e, e16 = rel(out, ref_out), rel(out, ref16)
     say(f"  rel L2 vs fp64 {e:.2e}, vs bf16 storage model {e16:.2e}")
     assert np.all(np.isfinite(out)) and e <= 3e-2 and e16 <= 1e-2, (e, e16)
+    # balanced: the corrections add nothing to a sample's total
+    tot = (out[:, 0].astype(np.float64) + out[:, 1]).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) <= 1e-5 * np.abs(out).sum(axis=(1, 2, 3))), tot
     net.close()
 
 
@@ -83,7 +88,7 @@ def test_gradients_match_oracle(cplb, B, H, Wd):
     say(f"cnn gradients B={B} H={H} W={Wd}")
     net, theta, x, tp = setup_net(cplb, B, H, Wd, seed=7 + H)
     rng = np.random.default_rng(11)
-    target = rng.normal(size=(B, H, Wd)) * 0.5
+    target = rng.normal(size=(B, 2, H, Wd)) * 0.5
     net.forward(tp)
     loss = net.backward(torch.tensor(target, dtype=torch.float32, device="cuda").contiguous())
     g = net.grads()
@@ -131,15 +136,16 @@ def test_training_fits_a_teacher(cplb):
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_closure_hook_matches_oracle(cplb, precision, tol):
-    """Random fields, walls, and a random per-node closure exchange: the
-    GPU step with the closure equals the oracle step with the same closure."""
+    """Random fields, walls, and random per-node corrections of c1 and c2:
+    the GPU step with the closure equals the oracle step with the same
+    closure."""
     import torch
     p = W.params(nx=67, ny=37, periodic=(1, 0, 1), precision=precision, sigma=2e-3, rho1=3.0,
                  rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07, D2=0.02, Keq=0.6,
                  A=0.4, g=(0.0, -2e-5, 0.0), rho_ref=1.5,
                  ref_f=W.phase_reference(precision))
     f = W.random_fields(p, seed=21)
-    s = (np.random.default_rng(4).normal(size=W.shape_of(p)) * 1e-3).astype(np.float32)
+    s = (np.random.default_rng(4).normal(size=(2,) + W.shape_of(p)) * 1e-3).astype(np.float32)
     g = cplb.Lattice(p)
     g.init_fields(f["phi"], f["c1"], f["c2"], u=f["u"], p=f["p"])
     ts = torch.tensor(s, device="cuda").contiguous()
@@ -160,8 +166,10 @@ def test_closure_hook_matches_oracle(cplb, precision, tol):
     g2.step(3)
     d = g.field("c1").cpu().numpy() - g2.field("c1").cpu().numpy()
     assert np.abs(d).max() > 1e-4
+    # each step the corrections take sum (s1 + s2) from the total scalar
     r, r2 = g.reduce(), g2.reduce()
-    assert abs(r["sum_c"] - r2["sum_c"]) <= 1e-5 * abs(r2["sum_c"])
+    want = -3.0 * float(s.astype(np.float64).sum())
+    assert abs((r["sum_c"] - r2["sum_c"]) - want) <= 1e-5 * abs(r2["sum_c"]), (r["sum_c"] - r2["sum_c"], want)
 
 
 @pytest.mark.parametrize("n,H,Wd,F", [(3, 8, 12, 4), (2, 5, 7, 2), (1, 16, 64, 4)])
@@ -180,7 +188,7 @@ def test_infer_equals_forward_bitwise(cplb):
     another stream too."""
     import torch
     net, theta, x, tp = setup_net(cplb, 3, 16, 48, seed=5)
-    net.set_output_scale(2.5)
+    net.set_output_scale(2.5, 0.7)
     a = net.forward(tp).cpu().numpy()
     b = net.infer(tp).cpu().numpy()
     assert np.array_equal(a, b)
