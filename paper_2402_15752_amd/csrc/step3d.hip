@@ -38,6 +38,7 @@
 // z loop, which overflows the scalar file and spills into vector lanes.
 #include <atomic>
 #include <cmath>
+#include <type_traits>
 
 #include "addr.hpp"
 #include "kernels.hpp"
@@ -269,6 +270,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       int bits = push.bits;
       if (z == 0 && G.wall_z) bits |= 16;
       if (z == nz - 1 && G.wall_z) bits |= 32;
+      // Walls is uniform over the wave: true only where a lane of it has a
+      // wall link (the first and last planes of a walled z axis, the columns
+      // of walled x / y faces); elsewhere no link needs the wall selects.
+      const bool walls = __ballot(bits != 0) != 0;
       // the flow populations relative to the own pressure bracket pi0: a
       // value arriving from x - c_i was stored relative to the bracket of
       // that node (of the node itself when the link bounced off a wall)
@@ -316,14 +321,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         if (z == nz - 1) dzp = Off(0) - Off(nz - 1) * G.nxy;
         // byte offset of the push target of direction i (plane i of its set),
         // or of the bounce-back target (plane opp(i), this node); the plane
-        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix.  Walls
-        // is uniform over the wave: true only where a lane of it has a wall
-        // link (the first and last planes of a walled z axis, the columns
-        // of walled x / y faces); elsewhere every store takes its push
-        // target without a select.  With walls both offsets are formed and
-        // selected per lane (the plane offsets are opaque to the compiler,
-        // which would otherwise branch around each one).
-        const bool walls = __ballot(bits != 0) != 0;
+        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix.  Without
+        // walls in the wave every store takes its push target without a
+        // select.  With walls both offsets are formed and selected per lane
+        // (the plane offsets are opaque to the compiler, which would
+        // otherwise branch around each one).
         auto bounced = [&](int cx, int cy, int cz) {
           return walls && (bits & link_mask(cx, cy, cz)) != 0;
         };
@@ -344,12 +346,12 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         // level, which y's history will hold when the value is read: the
         // neighbour's for a pushed link, the node's own new moment for the
         // rest direction and for a bounced link (both return to x)
-        auto rebase = [&](int i, T v, T rown, const T (&ring)[4][TY + 2][TX + 2]) -> T {
+        auto rebase = [&](int i, T v, T rown, const T (&ring)[4][TY + 2][TX + 2]) -> S {
           const int sl = LF::cz[i] < 0 ? sm : (LF::cz[i] > 0 ? sp : s0);
           const T rt = bounced(LF::cx[i], LF::cy[i], LF::cz[i])
                            ? ring[s0][ty + 1][tx + 1]
                            : ring[sl][ty + 1 + LF::cy[i]][tx + 1 + LF::cx[i]];
-          return v + T(LF::w[i]) * (rown - rt);
+          return store_shifted<S, T>(v, rown - rt, T(LF::w[i]), T(1.0 / LF::w[i]));
         };
         S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
         S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          st_pop<NTW>(at(dF, t), Codec<S, T>::st(rebase(i, v, r[0], R.phi), T(1.0 / LF::w[i])));
+          st_pop<NTW>(at(dF, t), rebase(i, v, r[0], R.phi));
         });
         if (LATE) {
           load_q<LF, NTL, true>(sH1, G.sS, node, h1);
@@ -395,11 +397,12 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
           if constexpr (!LOC) {
-            a = rebase(i, a, r[1], R.c1);
-            c = rebase(i, c, r[2], R.c2);
+            st_pop<NTW>(at(dH1, t), rebase(i, a, r[1], R.c1));
+            st_pop<NTW>(at(dH2, t), rebase(i, c, r[2], R.c2));
+          } else {
+            st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
+            st_pop<NTW>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
           }
-          st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
-          st_pop<NTW>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
         });
       }
     }
