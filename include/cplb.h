@@ -144,6 +144,12 @@ typedef struct cplb_params {
                             CPLB_BC_NOFLUX or CPLB_BC_DIRICHLET (h1, h2)          */
   double c_wall[6][2];   /* (c1, c2) imposed at each Dirichlet face              */
   int32_t scalar_grad;   /* grad(c1 + Keq c2) of ~H: CPLB_GRAD_CENTRAL | CPLB_GRAD_LOCAL */
+  int32_t phase_grad;    /* grad phi: CPLB_GRAD_CENTRAL (the isotropic stencil) or
+                            CPLB_GRAD_LOCAL (the local scheme after Eq. (39), Sec.
+                            III C: from the first moment of the node's own f, with
+                            the previous step's velocity standing in for this
+                            step's, which needs grad phi); the Laplacian is central
+                            either way */
 } cplb_params;
 
 typedef struct cplb cplb_t; /* opaque handle */

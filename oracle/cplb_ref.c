@@ -207,6 +207,10 @@ static int check_params(const cplb_ref_params* p, char* err) {
     strcpy(err, "unknown scalar gradient scheme");
     return -1;
   }
+  if (p->phase_grad != CPLB_REF_GRAD_CENTRAL && p->phase_grad != CPLB_REF_GRAD_LOCAL) {
+    strcpy(err, "unknown phase gradient scheme");
+    return -1;
+  }
   if (p->scalar_model != CPLB_REF_TWO_SCALAR && p->scalar_model != CPLB_REF_ONE_SCALAR) {
     strcpy(err, "unknown scalar model");
     return -1;
@@ -486,6 +490,32 @@ static void pass2(cplb_ref_t* h) {
         gpsi[a] += L->w[i] * L->c[i][a] * h->psi[m] / L->cs2;
       }
       lap += 2.0 * L->w[i] * (h->phi[m] - phi) / L->cs2;
+    }
+    if (P->phase_grad == CPLB_REF_GRAD_LOCAL) {
+      /* local scheme after Eq. (39): with C = sum c_i f_i - phi u +
+         d_t(phi u) / 2, D = -tau_f cs^2 and B = 4 M phi (1 - phi) / W,
+         |grad phi| = (-|C| - B) / D and grad phi = C / (D + B / |grad phi|).
+         u and d_t(phi u) need grad phi (through the force), so the previous
+         level's u stands in for u, and d_t(phi u) is the backward difference
+         (phi - phi_old) u_old.  The direction C / |C| is undefined where C
+         vanishes -- at an equilibrium start C is round-off everywhere -- so
+         it is regularised like the normal: |C| in the denominator becomes
+         sqrt(|C|^2 + (tau_f cs^2 n_eps)^2), the scale of C at a gradient of
+         n_eps. */
+      const lattice_t* LF = &h->LF;
+      const double tau_f = 0.5 + P->M / LF->cs2;
+      const double D = -tau_f * LF->cs2, B = 4.0 * P->M * phi * (1.0 - phi) / P->W;
+      double C[3] = {0, 0, 0};
+      for (int i = 0; i < LF->q; i++)
+        for (int a = 0; a < 3; a++) C[a] += LF->c[i][a] * h->f[i * N + n];
+      for (int a = 0; a < 3; a++) {
+        const double uo = h->u_old[a * N + n];
+        C[a] += -phi * uo + 0.5 * (phi - h->phi_old[n]) * uo;
+      }
+      /* D + B / |grad phi| = D |C| / (|C| + B): the quotient is taken in
+         that form, which does not cancel where |C| << B */
+      const double cn = sqrt(dot3(C, C)), ec = tau_f * LF->cs2 * P->n_eps;
+      for (int a = 0; a < 3; a++) gphi[a] = C[a] * (cn + B) / (D * sqrt(cn * cn + ec * ec));
     }
     /* unit normal n = grad phi / |grad phi|, regularised at n_eps */
     double norm = sqrt(dot3(gphi, gphi) + P->n_eps * P->n_eps);

@@ -79,6 +79,8 @@ typedef struct cplb_ref_params {
   double c_wall[6][2];      /* (c1, c2) imposed at each Dirichlet face          */
   int32_t scalar_grad;      /* grad(c1 + Keq c2) of ~H: CPLB_REF_GRAD_CENTRAL or
                                CPLB_REF_GRAD_LOCAL (two-scalar model)           */
+  int32_t phase_grad;       /* grad phi: CPLB_REF_GRAD_CENTRAL or CPLB_REF_GRAD_LOCAL
+                               (the local scheme after Eq. (39), Sec. III C)    */
 } cplb_ref_params;
 
 typedef struct cplb_ref cplb_ref_t;

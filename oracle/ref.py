@@ -35,7 +35,7 @@ class RefParams(ctypes.Structure):
         ("A", ctypes.c_double), ("g", ctypes.c_double * 3), ("rho_ref", ctypes.c_double),
         ("n_eps", ctypes.c_double), ("scalar_model", ctypes.c_int32),
         ("scalar_bc", ctypes.c_int32 * 6), ("c_wall", ctypes.c_double * 12),
-        ("scalar_grad", ctypes.c_int32),
+        ("scalar_grad", ctypes.c_int32), ("phase_grad", ctypes.c_int32),
     ]
 
 
@@ -88,6 +88,7 @@ def make_params(p: dict) -> RefParams:
         setattr(r, k, float(p[k]))
     r.scalar_model = SCALAR_MODELS[p.get("scalar_model", "two")]
     r.scalar_grad = SCALAR_GRAD[p.get("scalar_grad", "central")]
+    r.phase_grad = SCALAR_GRAD[p.get("phase_grad", "central")]
     for f in range(6):
         r.scalar_bc[f] = SCALAR_BC[p.get("scalar_bc", ("noflux",) * 6)[f]]
         cw = p.get("c_wall", ((0.0, 0.0),) * 6)[f]

@@ -60,6 +60,10 @@ struct KParams {
   int local_grad;     // 1: grad c_k from the moments of h_k (Eq. (39))
   T itc1, itc2;       // 1 / (tau_hk cs^2)
   T d1w, d2w;         // 4 D_k / W
+  int local_phase;    // 1: grad phi by the local scheme after Eq. (39)
+  T itf;              // 1 / (tau_f cs^2)
+  T ec2;              // (tau_f cs^2 n_eps)^2
+  T mw;               // 4 M / W
 };
 
 // ------------------------------------------------------------ storage codec
@@ -208,6 +212,37 @@ __device__ inline void moments(const KParams<T>& P, const T (&df)[LF::Q], const 
   s.dc2 = s2 - a * e;
   s.c1 = rc1 + s.dc1;
   s.c2 = rc2 + s.dc2;
+}
+
+// grad phi by the local scheme after Eq. (39) (Sec. III C): with
+// C = sum c_i f_i - phi u + d_t(phi u) / 2, D = -tau_f cs^2 and
+// B = 4 M phi (1 - phi) / W, |grad phi| = (-|C| - B) / D and
+// grad phi = C / (D + B / |grad phi|) = -(|C| + B) C / (tau_f cs^2 |C|),
+// the last form free of the cancellation in D + B / |grad phi| where
+// |C| << B.  Its direction C / |C| is undefined where C vanishes (at an
+// equilibrium start C is round-off everywhere), so |C| in the denominator is
+// regularised as sqrt(|C|^2 + ec^2), ec = tau_f cs^2 n_eps, the scale of C
+// at a gradient of n_eps.  u is the previous level's, uo (this level's needs
+// grad phi through the force), d_t(phi u) = (phi - phi_old) uo.  The stored
+// deviations df carry the first moment of f (their references have none).
+template <class LF, class T>
+__device__ inline void local_grad_phi(const KParams<T>& P, const T (&df)[LF::Q], T phi,
+                                      const T (&uo)[3], T phi_old, T (&gphi)[3]) {
+  const T k = T(0.5) * (phi - phi_old) - phi;
+  T C[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) C[a] = k * uo[a];
+#pragma unroll
+  for (int i = 1; i < LF::Q; ++i) {
+    if (LF::cx[i]) C[0] += LF::cx[i] > 0 ? df[i] : -df[i];
+    if (LF::cy[i]) C[1] += LF::cy[i] > 0 ? df[i] : -df[i];
+    if (LF::cz[i]) C[2] += LF::cz[i] > 0 ? df[i] : -df[i];
+  }
+  const T cn2 = C[0] * C[0] + C[1] * C[1] + C[2] * C[2];
+  const T B = P.mw * phi * (T(1) - phi);
+  const T fac = -(sqrt(cn2) + B) * P.itf * rsqrt_t(cn2 + P.ec2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gphi[a] = fac * C[a];
 }
 
 // One-scalar model (Sec. II D, III D): c = sum h3_i; the phase parts of c at

@@ -50,6 +50,8 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
   }
   if (p->scalar_grad != CPLB_GRAD_CENTRAL && p->scalar_grad != CPLB_GRAD_LOCAL)
     return fail("unknown scalar gradient scheme");
+  if (p->phase_grad != CPLB_GRAD_CENTRAL && p->phase_grad != CPLB_GRAD_LOCAL)
+    return fail("unknown phase gradient scheme");
   if (p->scalar_grad == CPLB_GRAD_LOCAL) {
     if (p->scalar_model != CPLB_TWO_SCALAR) return fail("the local gradient scheme takes the two-scalar model");
     for (int f = 0; f < 6; ++f)
@@ -82,7 +84,8 @@ inline int validate(const cplb_params* p, char* err, size_t errn) {
 inline bool same_params(const cplb_params& a, const cplb_params& b) {
   bool eq = a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lattice == b.lattice &&
             a.precision == b.precision && a.visc_law == b.visc_law &&
-            a.scalar_model == b.scalar_model && a.scalar_grad == b.scalar_grad;
+            a.scalar_model == b.scalar_model && a.scalar_grad == b.scalar_grad &&
+            a.phase_grad == b.phase_grad;
   for (int k = 0; k < 3; ++k) eq = eq && a.periodic[k] == b.periodic[k] && a.g[k] == b.g[k];
   eq = eq && a.rho1 == b.rho1 && a.rho2 == b.rho2 && a.mu1 == b.mu1 && a.mu2 == b.mu2 &&
        a.sigma == b.sigma && a.W == b.W && a.M == b.M && a.D1 == b.D1 && a.D2 == b.D2 &&
@@ -197,6 +200,11 @@ KParams<T> make_kparams(const cplb_params* p, const Geometry& G) {
   K.itc2 = T(1.0 / (tau_h2 * csf));
   K.d1w = T(4.0 * p->D1 / p->W);
   K.d2w = T(4.0 * p->D2 / p->W);
+  // local scheme for grad phi (after Eq. (39)): 1 / (tau_f cs^2) and 4 M / W
+  K.local_phase = p->phase_grad == CPLB_GRAD_LOCAL;
+  K.itf = T(1.0 / (tau_f * csf));
+  K.ec2 = T((tau_f * csf * p->n_eps) * (tau_f * csf * p->n_eps));
+  K.mw = T(4.0 * p->M / p->W);
   // Dirichlet faces x-, x+, y-, y+ (bit f) and their values
   K.dirichlet = 0;
   for (int f = 0; f < 4; ++f) {

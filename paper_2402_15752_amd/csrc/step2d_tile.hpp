@@ -160,6 +160,10 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   auto nbp = [&](int i) -> T { return sphi[ty + 1 + L::cy[i]][tx + 1 + L::cx[i]]; };
   T gphi[3], gpsi[3] = {T(0), T(0), T(0)};
   grad_pairs<L, T>(nbp, gphi);
+  if (P.local_phase) {
+    const T uo[3] = {hs[0], hs[1], T(0)};
+    local_grad_phi<L>(P, f, s.phi, uo, hs[kPhi], gphi);
+  }
   const T lap = lap_of<L, T>(nbp, s.phi);
   if constexpr (HALO_H) {
     // grad psi = grad c1 + Keq grad c2 (psi = c1 + Keq c2)

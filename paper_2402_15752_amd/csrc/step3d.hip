@@ -256,6 +256,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       T gphi[3], gpsi[3] = {T(0), T(0), T(0)};
       grad_pairs<LG, T>(nbp, gphi);
       const T lap = lap_of<LG, T>(nbp, s.phi);
+      if (P.local_phase) {
+        if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
+        local_grad_phi<LF>(P, f, s.phi, uo, r[0], gphi);
+      }
       if constexpr (!LOC) {
         // grad psi = grad c1 + Keq grad c2 (psi = c1 + Keq c2)
         T gc1[3], gc2[3];

@@ -38,6 +38,7 @@ DEFAULTS = dict(
     D1=0.1, D2=0.1, Keq=1.0, A=0.1, g=(0.0, 0.0, 0.0), rho_ref=0.0, n_eps=1e-3,
     precision="f64", ref_f=0.0, ref_g=0.0, ref_h1=0.0, ref_h2=0.0, scalar_model="two",
     scalar_bc=("noflux",) * 6, c_wall=((0.0, 0.0),) * 6, scalar_grad="central",
+    phase_grad="central",
 )
 
 
