@@ -421,10 +421,11 @@ def generate_chunked(cases, steps, chunk, log=None, net=None, every=1, skip=5):
 
 
 def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batch=32, seed=1,
-               kind="static", every=1, gen_steps=None, n_held=8, chunk=64, skip=5, log=None):
-    """Draw cases, train the closure in two rounds (on plain coarse runs,
-    then on runs with the closure itself), and evaluate it on held-out cases
-    against the fine grid.  Data generation runs `gen_steps` coarse steps
+               kind="static", every=1, gen_steps=None, n_held=8, chunk=64, skip=5, rounds=2,
+               log=None):
+    """Draw cases, train the closure in one or two rounds (on plain coarse
+    runs, then on runs with the closure itself), and evaluate it on held-out
+    cases against the fine grid.  Data generation runs `gen_steps` coarse steps
     (default `steps`), `chunk` cases at a time, with targets averaged over
     spans of `every` steps; `n_held` further cases give the held-out loss
     during training.  Returns a summary: median scalar errors (c1, c2
@@ -443,10 +444,14 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
     t_gen = time.perf_counter() - t0
     net, scale, l1, h1 = train(X, Y, iters=iters[0], batch=batch, seed=seed, log=log,
                                capacity=max(n_test, batch, min(chunk, n_train)), held=(Xh, Yh))
-    X2, Y2 = generate_chunked(train_cases, gen_steps, chunk, net=net, every=every, skip=skip)
-    net, _, l2, h2 = train(torch.cat([X, X2]), torch.cat([Y, Y2]), iters=iters[1], batch=batch,
-                           seed=seed + 1, log=log, net=net, scale=scale, held=(Xh, Yh))
-    del X, Y, X2, Y2, Xh, Yh
+    l2, h2 = l1, []
+    if rounds > 1:
+        X2, Y2 = generate_chunked(train_cases, gen_steps, chunk, net=net, every=every, skip=skip)
+        X, Y = torch.cat([X, X2]), torch.cat([Y, Y2])
+        del X2, Y2
+        net, _, l2, h2 = train(X, Y, iters=iters[1], batch=batch, seed=seed + 1, log=log, net=net,
+                               scale=scale, held=(Xh, Yh))
+    del X, Y, Xh, Yh
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ev = evaluate(test_cases, steps=steps, net=net, log=log)
@@ -457,7 +462,8 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
     return dict(
         kind=kind, train_cases=n_train, test_cases=n_test, held_cases=n_held,
         coarse_grid=[nx, ny], fine_grid=[F * nx, F * ny], coarse_steps=steps,
-        fine_steps=F * F * steps, data_steps=gen_steps, data_every=every,
+        fine_steps=F * F * steps, data_steps=gen_steps, data_every=every, data_skip=skip,
+        rounds=rounds,
         err_plain_coarse=ep, err_closure=ec, closure_better_cases=int(wins),
         t_fine_ms=ev["t_fine"] * 1e3, t_coarse_ms=ev["t_coarse"] * 1e3,
         t_closure_ms=ev["t_closure"] * 1e3,

@@ -66,8 +66,11 @@ enum { kFwdAct = 0, kFwdLinear = 1, kBwd = 2, kInfAct = 3, kInfOut = 4 };
 constexpr int kConvRows = 4;
 constexpr int kConvCols = 32;
 constexpr int kConvRowsF = 8;
-// pixel tiles per work-group of the weight gradient (one partial each)
+// work-groups (one partial each) of the weight gradient: at most
+// kWgradParts, each taking at least kWgradTiles pixel tiles, so that the
+// partials its reduction reads stay small at any batch size
 constexpr int kWgradTiles = 2;
+constexpr int kWgradParts = 1024;
 
 // LDS staging of the convolution tiles.  Each thread issues all of its
 // global loads before its LDS stores (fixed trip counts, unrolled), so a
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
   }
 }
 
-// Weight and bias gradients, per work-group of kWgradTiles pixel tiles
+// Weight and bias gradients, per work-group of the pixel tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...
 // (kConvRows x kConvCols pixels each, the convolution's tiles):
 //   partial[g][co][k] = sum_p dZ[p][co] * X(p shifted by tap(k))[ci(k)],
 //   bpart[g][co]      = sum_p dZ[p][co],
@@ -274,9 +278,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const unsigned short* __rest
   float bacc = 0.f;
   const int bco = threadIdx.x % COUT, bgrp = threadIdx.x / COUT;
 
-  for (int q = 0; q < kWgradTiles; ++q) {
-    const int tile = blockIdx.x * kWgradTiles + q;
-    if (tile >= ntiles) break;  // uniform over the group
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % tiles_x) * kConvCols;
     const int R0 = (tile / tiles_x) * kConvRows;
     // input rows R0-1 .. R0+kConvRows, columns x0-1 .. x0+kConvCols, and dZ
@@ -374,15 +376,20 @@ __global__ __launch_bounds__(64 * kRedWaves) void wgrad_reduce(const float* __re
   }
 }
 
-// FP32 planes [sample][c][y][x] (c < cin) -> X0[p][16] in BF16, scaled
+// FP32 planes [sample][c][y][x] (c < cin) -> X0[p][16] in BF16, scaled: one
+// pixel per thread (coalesced plane reads, two 16-byte stores)
 __global__ void pack_kernel(const float* __restrict__ planes, int cin, const float* __restrict__ scale,
                             long long hw, long long P, unsigned short* __restrict__ X0) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= P * 16) return;
-  const long long p = i / 16;
-  const int c = (int)(i % 16);
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (p >= P) return;
   const long long s = p / hw, q = p % hw;
-  X0[i] = c < cin ? to_bf16(scale[c] * planes[(s * cin + c) * hw + q]) : (unsigned short)0;
+  unsigned short v[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    v[c] = c < cin ? to_bf16(scale[c] * planes[(s * cin + c) * hw + q]) : (unsigned short)0;
+  uint4* dst = (uint4*)(X0 + p * 16);
+  dst[0] = __builtin_bit_cast(uint4, *(const unsigned short(*)[8])v);
+  dst[1] = __builtin_bit_cast(uint4, *(const unsigned short(*)[8])(v + 8));
 }
 
 // out[sample][c][q] = scale_c * Z4[p][c], p = sample * hw + q, c < kOut
@@ -395,22 +402,38 @@ __global__ void output_kernel(const float* __restrict__ Z4, long long P, long lo
   out[(smp * kOut + 1) * hw + q] = scale1 * Z4[p * 16 + 1];
 }
 
-// Per sample (one work-group each): subtract half the sample's mean of
-// out[c=0] + out[c=1] from both planes, so that the corrections of c1 and c2
-// add nothing to the sample's total scalar.  FP64 sum in a fixed order.
-__global__ __launch_bounds__(256) void balance_kernel(float* __restrict__ out, long long hw) {
+// Balance per sample: subtract half the sample's mean of out[c=0] +
+// out[c=1] from both planes, so that the corrections of c1 and c2 add
+// nothing to the sample's total scalar.  Two passes over kBalanceParts
+// chunks of every sample (grid chunks x samples): FP64 chunk sums, then each
+// chunk adds its sample's kBalanceParts sums in a fixed order (the same mean
+// for every chunk) and subtracts.
+constexpr int kBalanceParts = 64;
+
+__global__ __launch_bounds__(256) void balance_sums(const float* __restrict__ out, long long hw,
+                                                    double* __restrict__ part) {
   __shared__ double red[256];
-  float* o = out + (long long)blockIdx.x * kOut * hw;
+  const float* o = out + (long long)blockIdx.y * kOut * hw;
+  const long long q0 = hw * blockIdx.x / kBalanceParts, q1 = hw * (blockIdx.x + 1) / kBalanceParts;
   double s = 0.0;
-  for (long long q = threadIdx.x; q < hw; q += 256) s += (double)o[q] + (double)o[hw + q];
+  for (long long q = q0 + threadIdx.x; q < q1; q += 256) s += (double)o[q] + (double)o[hw + q];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const float m = (float)(red[0] / (2.0 * (double)hw));
-  for (long long q = threadIdx.x; q < hw; q += 256) {
+  if (threadIdx.x == 0) part[blockIdx.y * kBalanceParts + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void balance_apply(float* __restrict__ out, long long hw,
+                                                     const double* __restrict__ part) {
+  float* o = out + (long long)blockIdx.y * kOut * hw;
+  double s = 0.0;
+  for (int k = 0; k < kBalanceParts; ++k) s += part[blockIdx.y * kBalanceParts + k];
+  const float m = (float)(s / (2.0 * (double)hw));
+  const long long q0 = hw * blockIdx.x / kBalanceParts, q1 = hw * (blockIdx.x + 1) / kBalanceParts;
+  for (long long q = q0 + threadIdx.x; q < q1; q += 256) {
     o[q] -= m;
     o[hw + q] -= m;
   }
@@ -547,7 +570,8 @@ hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned
 int cnn_wgrad_parts(int W, long long rows) {
   const long long tiles =
       (long long)((W + kConvCols - 1) / kConvCols) * ((rows + kConvRows - 1) / kConvRows);
-  return (int)((tiles + kWgradTiles - 1) / kWgradTiles);
+  const long long parts = (tiles + kWgradTiles - 1) / kWgradTiles;
+  return (int)(parts < kWgradParts ? parts : kWgradParts);
 }
 
 hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* dZ, float* partial,
@@ -571,7 +595,7 @@ hipError_t cnn_wgrad(int layer, const unsigned short* X, const unsigned short* d
 
 hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long hw, long long P,
                     unsigned short* X0, hipStream_t s) {
-  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((P * 16 + 255) / 256)), dim3(256), 0, s, planes,
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, planes,
                      cin, scale, hw, P, X0);
   return hipGetLastError();
 }
@@ -583,8 +607,13 @@ hipError_t cnn_output(const float* Z4, long long P, long long hw, float scale0, 
   return hipGetLastError();
 }
 
-hipError_t cnn_balance(float* out, int nsamples, long long hw, hipStream_t s) {
-  hipLaunchKernelGGL(balance_kernel, dim3(nsamples), dim3(256), 0, s, out, hw);
+int cnn_balance_parts(int nsamples) { return nsamples * kBalanceParts; }
+
+hipError_t cnn_balance(float* out, int nsamples, long long hw, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(balance_sums, dim3(kBalanceParts, nsamples), dim3(256), 0, s, out, hw, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(balance_apply, dim3(kBalanceParts, nsamples), dim3(256), 0, s, out, hw, part);
   return hipGetLastError();
 }
 

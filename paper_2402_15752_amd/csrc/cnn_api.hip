@@ -35,10 +35,10 @@ int w_offset(int l) {  // start of W of layer l in the parameter vector
 
 struct CnnLayout {
   size_t theta, m, v, grad, wg[kLayers], wf[kLayers], scale, x0, z[kLayers], a[kLayers],
-      dz[kLayers], wpart, bpart, lpart, loss, total;
+      dz[kLayers], wpart, bpart, lpart, loss, bal, total;
 };
 
-CnnLayout cnn_layout(long long P, int W) {
+CnnLayout cnn_layout(long long P, int W, int nsamples) {
   CnnLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -67,6 +67,7 @@ CnnLayout cnn_layout(long long P, int W) {
   L.bpart = take((size_t)nparts * 32 * 4);
   L.lpart = take(kLossParts * 8);
   L.loss = take(8);
+  L.bal = take((size_t)cnn_balance_parts(nsamples) * 8);
   L.total = off;
   return L;
 }
@@ -142,7 +143,7 @@ int cplb_cnn_num_params(void) { return num_params(); }
 int cplb_cnn_workspace_bytes(int nsamples, int H, int W, size_t* bytes) {
   if (!bytes || nsamples < 1 || H < 1 || W < 1) return CPLB_EINVAL;
   if ((double)nsamples * H * W > 2.0e8) return CPLB_EINVAL;
-  *bytes = cnn_layout((long long)nsamples * H * W, W).total;
+  *bytes = cnn_layout((long long)nsamples * H * W, W, nsamples).total;
   return CPLB_OK;
 }
 
@@ -163,7 +164,7 @@ int cplb_cnn_create(int nsamples, int H, int W, void* dev_workspace, size_t byte
   c->P = (long long)nsamples * H * W;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)dev_workspace;
-  c->L = cnn_layout(c->P, W);
+  c->L = cnn_layout(c->P, W, nsamples);
   c->used_P = 0;
   c->adam_t = 0;
   c->out_scale[0] = c->out_scale[1] = 1.f;
@@ -261,7 +262,9 @@ int cplb_cnn_forward(cplb_cnn_t* c, int nsamples, const float* dev_planes, int c
   if (dev_out) {
     rc = hip_check(c, cnn_output(c->at<float>(c->L.z[kLayers - 1]), P, hw, c->out_scale[0],
                                  c->out_scale[1], dev_out, c->stream), "output copy");
-    if (!rc) rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->stream), "output balance");
+    if (!rc)
+      rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->at<double>(c->L.bal), c->stream),
+                     "output balance");
   }
   return rc;
 }
@@ -290,7 +293,9 @@ int cplb_cnn_infer(cplb_cnn_t* c, int nsamples, const float* dev_planes, int cin
                    "inference convolution");
     x = a;
   }
-  if (!rc) rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->stream), "output balance");
+  if (!rc)
+    rc = hip_check(c, cnn_balance(dev_out, nsamples, hw, c->at<double>(c->L.bal), c->stream),
+                   "output balance");
   c->used_P = 0;  // the training buffers of the last forward are gone
   return rc;
 }

@@ -122,8 +122,10 @@ hipError_t cnn_pack(const float* planes, int cin, const float* scale, long long 
 // out [sample][2][hw] = scale_c * channel c of Z4, c = 0, 1
 hipError_t cnn_output(const float* Z4, long long P, long long hw, float scale0, float scale1,
                       float* out, hipStream_t s);
-// per sample: subtract half the mean of out[c=0] + out[c=1] from both planes
-hipError_t cnn_balance(float* out, int nsamples, long long hw, hipStream_t s);
+// per sample: subtract half the mean of out[c=0] + out[c=1] from both planes;
+// part holds cnn_balance_parts(nsamples) doubles
+int cnn_balance_parts(int nsamples);
+hipError_t cnn_balance(float* out, int nsamples, long long hw, double* part, hipStream_t s);
 // block average: coarse[s][y][x] = mean of fine[s][f y + j][f x + i], 0 <= i, j < f
 hipError_t cnn_restrict(const float* fine, int nsamples, int H, int W, int f, float* coarse,
                         hipStream_t s);

@@ -113,5 +113,5 @@ def test_one_scalar_refuses_a_closure(cplb):
     p = W.params(nx=16, ny=8, precision="f32", scalar_model="one")
     g = cplb.Lattice(p)
     with pytest.raises(cplb.CplbError) as e:
-        g.set_closure(torch.zeros((8, 16), dtype=torch.float32, device="cuda"))
+        g.set_closure(torch.zeros((2, 8, 16), dtype=torch.float32, device="cuda"))
     assert e.value.code == cplb.CPLB_EINVAL
