@@ -108,11 +108,12 @@ int default_variant(const cplb_params* p) {
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
     return p->scalar_grad == CPLB_GRAD_LOCAL && lattice_bytes > 256e6 ? 7 : 3;
   }
-  // 3-D: 64x4 with non-temporal stores; FP32 and FP64 carry f, h1, h2 in
-  // registers from the previous plane, 16-bit storage (bound by instruction
-  // issue more than by registers) re-reads them from the caches before their
-  // collision (0.96 against 1.00 ms per 256^3 step)
-  return p->precision == CPLB_F32_S16F || p->precision == CPLB_F32_S16B ? 1 : 4;
+  // 3-D, every precision and gradient scheme: 64x4 with f, h1, h2 carried in
+  // registers from the previous plane, non-temporal stores.  (With 16-bit
+  // storage the variant that re-reads f, h1, h2 before their collision is
+  // 4% faster, but 41% of those re-reads miss L2: 1.41 x the algorithmic
+  // read bytes against 1.03 x.)
+  return 4;
 }
 
 hipError_t run_kernel(cplb_t* h, int mode) {
