@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44600947, "write": 43035964,
-                                  "src": "ddfe7f2148e823ea"},
-    "rising_droplet_256c_f32": {"read": 3272538956, "write": 3120015696,
-                               "src": "ddfe7f2148e823ea"},
-    "rising_droplet_256c_f32_s16f": {"read": 1791466362, "write": 1776066251,
-                                    "src": "ddfe7f2148e823ea"},
-    "rising_bubble_2048x4096_f32": {"read": 1484596930, "write": 1376889419,
-                                   "src": "ddfe7f2148e823ea"},
-    "rising_bubble_one_256x1024_f32": {"read": 32773100, "write": 32527935,
-                                      "src": "ddfe7f2148e823ea"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1766492580, "write": 1379170344,
-                                         "src": "ddfe7f2148e823ea"},
-    "rising_droplet_local_256c_f32": {"read": 3319307608, "write": 3120038704,
-                                     "src": "ddfe7f2148e823ea"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1790263236, "write": 1774675856,
-                                          "src": "ddfe7f2148e823ea"},
+    "rising_bubble_256x1024_f32": {"read": 44272426, "write": 43020688,
+                                  "src": "c86daa52e20d4e10"},
+    "rising_droplet_256c_f32": {"read": 3162481621, "write": 3117583621,
+                               "src": "c86daa52e20d4e10"},
+    "rising_droplet_256c_f32_s16f": {"read": 1786464341, "write": 1773712506,
+                                    "src": "c86daa52e20d4e10"},
+    "rising_bubble_2048x4096_f32": {"read": 1465819968, "write": 1376908218,
+                                   "src": "c86daa52e20d4e10"},
+    "rising_bubble_one_256x1024_f32": {"read": 32824021, "write": 32532762,
+                                      "src": "c86daa52e20d4e10"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1736460288, "write": 1379446458,
+                                         "src": "c86daa52e20d4e10"},
+    "rising_droplet_local_256c_f32": {"read": 3171405440, "write": 3120242832,
+                                     "src": "c86daa52e20d4e10"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773599872, "write": 1771606730,
+                                          "src": "c86daa52e20d4e10"},
 }
 
 
