@@ -4,7 +4,8 @@
 // reached from a 64-bit set base held in scalar registers plus an Off-typed
 // byte offset plane * stride + node.  With Off = uint32_t (each set below
 // 4 GiB) a load or store takes the scalar-base + 32-bit-vector-offset form
-// and an address costs one VGPR; Off = uint64_t serves larger sets.
+// and an address costs one VGPR; Off = uint64_t serves larger sets.  The 3-D
+// step reaches allocations below 4 GiB as buffers instead (View below).
 #pragma once
 
 #include <type_traits>
@@ -69,6 +70,66 @@ __device__ inline P* at(P* base, Off off) {
   using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
   return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
 }
+
+// A population, history or field buffer as a kernel reaches it.  An access
+// names a per-lane byte offset (`lane`: the node and its x / y push step)
+// and a uniform one (`uni`: set, plane, skew, z plane and z push step).
+// BUF (the whole buffer below 4 GiB): a buffer resource over the
+// allocation; the address unit adds the two offsets (vector register +
+// scalar register), so an access costs no vector instruction.  Otherwise a
+// 64-bit base plus one Off-typed offset, lane + uni, formed per access.
+template <bool BUF, class P, class Off>
+struct View;
+
+template <class P, class Off>
+struct View<false, P, Off> {
+  P* base;
+  __device__ View(P* b, Off) : base(b) {}
+  template <bool NT>
+  __device__ typename std::remove_const<P>::type ld(Off lane, Off uni) const {
+    return ld_pop<NT>(at(base, uni + lane));
+  }
+  template <bool NT>
+  __device__ void st(Off lane, Off uni, P v) const {
+    st_pop<NT>(at(base, uni + lane), v);
+  }
+};
+
+template <class P, class Off>
+struct View<true, P, Off> {
+  static_assert(std::is_same<Off, uint32_t>::value, "buffer offsets are 32-bit");
+  using V = typename std::remove_const<P>::type;
+  // cache policy of the non-temporal accesses (the bit the compiler sets for
+  // a non-temporal global load or store)
+  static constexpr int kNT = 2;
+  __amdgpu_buffer_rsrc_t r;
+  // bytes: size of the allocation (the range every access stays in); the
+  // fourth word is the raw-buffer format of this GPU family
+  __device__ View(P* b, Off bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<V*>(b), (short)0, (int)bytes, 0x00020000)) {}
+  template <bool NT>
+  __device__ V ld(Off lane, Off uni) const {
+    constexpr int aux = NT ? kNT : 0;
+    if constexpr (sizeof(V) == 2)
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b16(r, (int)lane, (int)uni, aux));
+    else if constexpr (sizeof(V) == 4)
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)lane, (int)uni, aux));
+    else
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane, (int)uni, aux));
+  }
+  template <bool NT>
+  __device__ void st(Off lane, Off uni, V v) const {
+    constexpr int aux = NT ? kNT : 0;
+    if constexpr (sizeof(V) == 2)
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)lane, (int)uni, aux);
+    else if constexpr (sizeof(V) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)lane, (int)uni, aux);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(
+          __builtin_bit_cast(unsigned int __attribute__((ext_vector_type(2))), v), r, (int)lane, (int)uni,
+          aux);
+  }
+};
 
 // map a (possibly out of range) coordinate onto the node whose moments the
 // stencil reads there: periodic wrap, or the mirror ghost at a wall
@@ -144,6 +205,15 @@ struct PushXY {
 __device__ constexpr int link_mask(int cx, int cy, int cz) {
   return (cx < 0 ? 1 : 0) | (cx > 0 ? 2 : 0) | (cy < 0 ? 4 : 0) | (cy > 0 ? 8 : 0) |
          (cz < 0 ? 16 : 0) | (cz > 0 ? 32 : 0);
+}
+
+// true when the whole lattice (qtot planes), the history and the field
+// buffer each span < 4 GiB: one buffer resource and 32-bit offsets reach
+// every value of each
+inline bool fits_buffer(int qtot, long long stride, size_t s_pop, size_t s_cmp, int nfields) {
+  const unsigned long long lim = (1ull << 32) - 1;
+  return (unsigned long long)qtot * stride * s_pop < lim &&
+         (unsigned long long)nfields * stride * s_cmp < lim;
 }
 
 // true when every population set (at most qset planes), the history and the

@@ -23,13 +23,19 @@
 // once per node; only the halo ring and the first two planes of a chunk are
 // recomputed.
 //
-// Addressing.  Each population set (f, g, h1, h2), the history and the
-// field buffer has a 64-bit base; a value is reached by an Off-typed byte
-// offset plane * stride + node.  With Off = uint32_t (every set below
-// 4 GiB, the usual case) the loads and stores take the scalar-base +
-// 32-bit-vector-offset form and each address costs one VGPR.  Push targets
-// come from per-lane x/y neighbour deltas and per-plane z deltas computed
-// once; bounce-back is a per-lane select, not a branch.
+// Addressing.  A value is reached by a byte offset plane * stride + node,
+// split into a per-lane part (the node's column within its z plane, and the
+// x / y step of a push) and a uniform part (set, plane, skew, z plane and
+// z step of a push).  With FP32 or FP64 storage, when the lattice, the
+// history and the field buffer each span < 4 GiB (the usual case), every
+// access is a buffer access over one resource per allocation: the address
+// unit adds the scalar part to the vector part, so loads cost no vector
+// instruction and a push store one at most.  16-bit lattices, and larger
+// FP32 / FP64 ones whose sets stay below 4 GiB (one tile shape), take
+// 32-bit offsets from a 64-bit base per set; larger ones 64-bit offsets.
+// Push targets come from per-lane x / y neighbour deltas and
+// per-plane z deltas computed once; bounce-back is a per-lane select, not
+// a branch.
 //
 // Scalar registers.  The loop body reads the lattice constants through a
 // pointer and the plane stride through values that the compiler must treat
@@ -79,7 +85,7 @@ struct Ring {
 // of the plane being collided -- no scalar ring, no h1, h2 of the halo; h1,
 // h2 then keep the uniform reference (c1_ref, c2_ref).
 template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off,
-          bool LOC>
+          bool LOC, bool BUF>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst,
                                                         const T* __restrict__ hin,
@@ -105,11 +111,21 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int z1 = (int)((long long)(zc + 1) * G.nz / G.nchunks);
 
-  // set bases (64-bit scalar arithmetic, once)
-  const S* __restrict__ sF = at(src, (size_t)Lay::F0 * G.sS);
-  const S* __restrict__ sG = at(src, (size_t)Lay::G0 * G.sS);
-  const S* __restrict__ sH1 = at(src, (size_t)Lay::H10 * G.sS);
-  const S* __restrict__ sH2 = at(src, (size_t)Lay::H20 * G.sS);
+  // Population sets: with BUF one buffer resource spans each lattice and a
+  // set's first plane joins the uniform offset; otherwise each set has a
+  // 64-bit base (scalar arithmetic, once).  The history and the field
+  // buffer are reached the same way.
+  using VS = View<BUF, const S, Off>;
+  using VD = View<BUF, S, Off>;
+  const Off lat_bytes = BUF ? Off(Lay::QTOT) * G.sS : Off(0);
+  const VS sF(BUF ? src : at(src, (size_t)Lay::F0 * G.sS), lat_bytes);
+  const VS sG(BUF ? src : at(src, (size_t)Lay::G0 * G.sS), lat_bytes);
+  const VS sH1(BUF ? src : at(src, (size_t)Lay::H10 * G.sS), lat_bytes);
+  const VS sH2(BUF ? src : at(src, (size_t)Lay::H20 * G.sS), lat_bytes);
+  const View<BUF, const T, Off> vin(hin, BUF ? Off(kHist3D) * G.sT : Off(0));
+  const View<BUF, T, Off> vout(hout, BUF ? Off(kHist3D) * G.sT : Off(0));
+  // byte offset of plane i of population set `set` from that set's view
+  auto pp = [&](int set, int i) -> Off { return plane<true>((BUF ? set : 0) + i, G.sS); };
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -135,18 +151,27 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
   const PushXY<Off> push(x, y, nx, ny, G.px, G.wall_x, G.wall_y, BS);
 
-  auto load_fh = [&](Off node, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
-    load_q<LF, NTL, true>(sF, G.sS, node, f);
-    load_q<LF, NTL, true>(sH1, G.sS, node, h1);
-    load_q<LF, NTL, true>(sH2, G.sS, node, h2);
+  // Loads of a node: `col` its byte offset within a z plane (per lane),
+  // `zb` the byte offset of its z plane (uniform).
+  // the 7 populations of a D3Q7 set
+  auto ldq = [&](const VS& v, int set, Off col, Off zb, T (&x)[7]) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+      x[i] = Codec<S, T>::ld(v.template ld<NTL>(col, pp(set, i) + zb + skew<LF, S, Off>(i)),
+                             T(LF::w[i]));
+  };
+  auto load_fh = [&](Off col, Off zb, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
+    ldq(sF, Lay::F0, col, zb, f);
+    ldq(sH1, Lay::H10, col, zb, h1);
+    ldq(sH2, Lay::H20, col, zb, h2);
   };
   // the references (phi, c1, c2 of the previous level) of a node
-  auto load_ref = [&](Off node, T (&r)[3]) {
-    const Off nT = node * TS;
-    r[0] = *at(hin, plane<true>(kPhi, G.sT) + nT);
+  auto load_ref = [&](Off col, Off zb, T (&r)[3]) {
+    const Off cT = col * TS, zT = zb * TS;
+    r[0] = vin.template ld<false>(cT, zT + plane<true>(kPhi, G.sT));
     if (!LOC) {
-      r[1] = *at(hin, plane<true>(kC1, G.sT) + nT);
-      r[2] = *at(hin, plane<true>(kC2, G.sT) + nT);
+      r[1] = vin.template ld<false>(cT, zT + plane<true>(kC1, G.sT));
+      r[2] = vin.template ld<false>(cT, zT + plane<true>(kC2, G.sT));
     } else {
       r[1] = T(0);
       r[2] = T(0);
@@ -154,8 +179,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   };
   // the pressure bracket a node's flow populations are stored relative to
   // (the rest slot of its g)
-  auto load_pi = [&](Off node) -> T {
-    return Codec<S, T>::ld(ld_pop<NTG>(at(sG, node)), T(LG::w[0]));
+  auto load_pi = [&](Off col, Off zb) -> T {
+    return Codec<S, T>::ld(sG.template ld<NTG>(col, pp(Lay::G0, 0) + zb), T(LG::w[0]));
   };
   // moments of plane zp of the own node into the ring
   auto put_own = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7],
@@ -177,15 +202,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     if (!halo) return;
     const int sl = slot_of(zp);
     T hf[7], hr[3];
-    load_q<LF, NTL, true>(sF, G.sS, pbase + halo_col, hf);
-    load_ref(pbase + halo_col, hr);
-    R.pi[sl][hy + 1][hx + 1] = load_pi(pbase + halo_col);
+    ldq(sF, Lay::F0, halo_col, pbase, hf);
+    load_ref(halo_col, pbase, hr);
+    R.pi[sl][hy + 1][hx + 1] = load_pi(halo_col, pbase);
     if constexpr (LOC) {
       R.phi[sl][hy + 1][hx + 1] = hr[0] + phase_sum<LF>(hf);
     } else {
       T hh1[7], hh2[7];
-      load_q<LF, NTL, true>(sH1, G.sS, pbase + halo_col, hh1);
-      load_q<LF, NTL, true>(sH2, G.sS, pbase + halo_col, hh2);
+      ldq(sH1, Lay::H10, halo_col, pbase, hh1);
+      ldq(sH2, Lay::H20, halo_col, pbase, hh2);
       Node<T> q;
       moments<LF>(P, hf, hh1, hh2, hr[0], hr[1], hr[2], q);
       R.phi[sl][hy + 1][hx + 1] = q.phi;
@@ -203,15 +228,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     T af[7], ah1[7], ah2[7], ar[3];
     const Off pm = Off(fold(z0 - 1, nz, G.wall_z)) * G.nxy;
     const Off p0 = Off(z0) * G.nxy;
-    load_fh(pm + own_col, af, ah1, ah2);
-    load_ref(pm + own_col, ar);
-    const T apm = load_pi(pm + own_col);
+    load_fh(own_col, pm, af, ah1, ah2);
+    load_ref(own_col, pm, ar);
+    const T apm = load_pi(own_col, pm);
     halo_plane(P, z0 - 1, pm);
     Node<T> tmp;
     put_own(P, z0 - 1, af, ah1, ah2, ar, apm, tmp);
-    load_fh(p0 + own_col, f, h1, h2);
-    load_ref(p0 + own_col, r);
-    const T ap0 = load_pi(p0 + own_col);
+    load_fh(own_col, p0, f, h1, h2);
+    load_ref(own_col, p0, r);
+    const T ap0 = load_pi(own_col, p0);
     halo_plane(P, z0, p0);
     put_own(P, z0, f, h1, h2, r, ap0, s);
   }
@@ -223,24 +248,23 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
   for (int z = z0; z < z1; ++z) {
     const KParams<T>& P = params(Pg);
-    const Off zoff = Off(z) * G.nxy;
-    const Off node = zoff + own_col;  // bytes, population arrays
-    const Off nodeT = node * TS;      // bytes, history / fields
+    const Off zoff = Off(z) * G.nxy;  // bytes, population arrays (uniform part)
+    const Off colT = own_col * TS, zoffT = zoff * TS;  // bytes, history / fields
     const Off pn = Off(fold(z + 1, nz, G.wall_z)) * G.nxy;
     // ---- 1. global loads of this plane
     T g[19], uo[3], nf[7], nh1[7], nh2[7], nr[3];
     auto load_g = [&] {
 #pragma unroll
       for (int i = 1; i < 19; ++i)
-        g[i] = Codec<S, T>::ld(
-            ld_pop<NTG>(at(sG, plane<true>(i, G.sS) + node + skew<LG, S, Off>(i))), T(LG::w[i]));
+        g[i] = Codec<S, T>::ld(sG.template ld<NTG>(own_col, pp(Lay::G0, i) + zoff + skew<LG, S, Off>(i)),
+                               T(LG::w[i]));
 #pragma unroll
-      for (int k = 0; k < 3; ++k) uo[k] = *at(hin, plane<true>(k, G.sT) + nodeT);
+      for (int k = 0; k < 3; ++k) uo[k] = vin.template ld<false>(colT, zoffT + plane<true>(k, G.sT));
     };
     if (PREF && active) load_g();
-    load_fh(pn + own_col, nf, nh1, nh2);
-    load_ref(pn + own_col, nr);
-    const T npi = load_pi(pn + own_col);
+    load_fh(own_col, pn, nf, nh1, nh2);
+    load_ref(own_col, pn, nr);
+    const T npi = load_pi(own_col, pn);
     // ---- 2. moments of plane z+1 into the ring
     halo_plane(P, z + 1, pn);
     Node<T> ns;
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       grad_pairs<LG, T>(nbp, gphi);
       const T lap = lap_of<LG, T>(nbp, s.phi);
       if (P.local_phase) {
-        if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
+        if (LATE) ldq(sF, Lay::F0, own_col, zoff, f);
         local_grad_phi<LF>(P, f, s.phi, uo, r[0], gphi);
       }
       if constexpr (!LOC) {
@@ -293,7 +317,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       Flow<T> fl;
       flow_macros<LG>(P, g, s, gphi, lap, pi0, fl);
       if (MODE == kModeMacros) {
-        auto put_field = [&](int k, T v) { *at(fields, plane<true>(k, G.sT) + nodeT) = v; };
+        const View<BUF, T, Off> vf(fields, BUF ? Off(kNumFields) * G.sT : Off(0));
+        auto put_field = [&](int k, T v) { vf.template st<false>(colT, zoffT + plane<true>(k, G.sT), v); };
         put_field(kFieldPhi, s.phi);
         put_field(kFieldP, fl.p);
         put_field(kFieldUx, fl.u[0]);
@@ -310,39 +335,45 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           dJphi[a] = s.phi * fl.u[a] - r[0] * uo[a];
-          dJ1[a] = s.c1 * fl.u[a] - (LOC ? *at(hin, plane<true>(kC1, G.sT) + nodeT) : r[1]) * uo[a];
-          dJ2[a] = s.c2 * fl.u[a] - (LOC ? *at(hin, plane<true>(kC2, G.sT) + nodeT) : r[2]) * uo[a];
+          dJ1[a] = s.c1 * fl.u[a] -
+                   (LOC ? vin.template ld<false>(colT, zoffT + plane<true>(kC1, G.sT)) : r[1]) * uo[a];
+          dJ2[a] = s.c2 * fl.u[a] -
+                   (LOC ? vin.template ld<false>(colT, zoffT + plane<true>(kC2, G.sT)) : r[2]) * uo[a];
         }
 #pragma unroll
         for (int k = 0; k < kHist3D; ++k) {
           const T v = k < 3 ? fl.u[k] : (k == kPhi ? s.phi : (k == kC1 ? s.c1 : s.c2));
-          *at(hout, plane<true>(k, G.sT) + nodeT) = v;
+          vout.template st<false>(colT, zoffT + plane<true>(k, G.sT), v);
         }
 
         // z push deltas of this plane (uniform)
         Off dzm = Off(0) - G.nxy, dzp = G.nxy;
         if (z == 0) dzm = Off(nz - 1) * G.nxy;
         if (z == nz - 1) dzp = Off(0) - Off(nz - 1) * G.nxy;
-        // byte offset of the push target of direction i (plane i of its set),
-        // or of the bounce-back target (plane opp(i), this node); the plane
-        // skew of direction i is -c_ix nodes, that of opp(i) +c_ix.  Without
-        // walls in the wave every store takes its push target without a
-        // select.  With walls both offsets are formed and selected per lane
-        // (the plane offsets are opaque to the compiler, which would
-        // otherwise branch around each one).
+        // byte offset of the push target of direction i (plane i of set
+        // `set`), or of the bounce-back target (plane opp(i), this node); the
+        // plane skew of direction i is -c_ix nodes, that of opp(i) +c_ix.
+        // Without walls in the wave a store takes its push target as a
+        // per-lane part (the node and its x / y step) and a uniform part
+        // (plane, skew, z plane and step).  With walls both whole offsets
+        // are formed and selected per lane (the plane offsets are opaque to
+        // the compiler, which would otherwise branch around each one).
         auto bounced = [&](int cx, int cy, int cz) {
           return walls && (bits & link_mask(cx, cy, cz)) != 0;
         };
-        auto target = [&](int i, int o, int cx, int cy, int cz) -> Off {
+        struct Tgt {
+          Off lane, uni;
+        };
+        auto target = [&](int set, int i, int o, int cx, int cy, int cz) -> Tgt {
           const Off sk = cx > 0 ? Off(0) - BS : (cx < 0 ? BS : Off(0));
-          Off t = node;
-          if (cx) t += cx < 0 ? push.dxm : push.dxp;
-          if (cy) t += cy < 0 ? push.dym : push.dyp;
-          if (cz) t += cz < 0 ? dzm : dzp;
-          const Off push_t = plane<true>(i, G.sS) + t + sk;
-          if (!walls) return push_t;
-          const Off back_t = plane<true>(o, G.sS) + node - sk;
-          return (bits & link_mask(cx, cy, cz)) ? back_t : push_t;
+          Off lane = own_col;
+          if (cx) lane += cx < 0 ? push.dxm : push.dxp;
+          if (cy) lane += cy < 0 ? push.dym : push.dyp;
+          Off uni = pp(set, i) + zoff + sk;
+          if (cz) uni += cz < 0 ? dzm : dzp;
+          if (!walls) return Tgt{lane, uni};
+          const Off back_t = pp(set, o) + zoff - sk + own_col;
+          return Tgt{(bits & link_mask(cx, cy, cz)) ? back_t : lane + uni, Off(0)};
         };
         // The collisions emit X_i* - w_i R(x), R(x) the node's own reference
         // (its moment at the previous level); the D3Q7 value stored at the
@@ -357,29 +388,29 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
                            : ring[sl][ty + 1 + LF::cy[i]][tx + 1 + LF::cx[i]];
           return store_shifted<S, T>(v, rown - rt, T(LF::w[i]), T(1.0 / LF::w[i]));
         };
-        S* __restrict__ dF = at(dst, (size_t)Lay::F0 * G.sS);
-        S* __restrict__ dG = at(dst, (size_t)Lay::G0 * G.sS);
-        S* __restrict__ dH1 = at(dst, (size_t)Lay::H10 * G.sS);
-        S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
+        const VD dF(BUF ? dst : at(dst, (size_t)Lay::F0 * G.sS), lat_bytes);
+        const VD dG(BUF ? dst : at(dst, (size_t)Lay::G0 * G.sS), lat_bytes);
+        const VD dH1(BUF ? dst : at(dst, (size_t)Lay::H10 * G.sS), lat_bytes);
+        const VD dH2(BUF ? dst : at(dst, (size_t)Lay::H20 * G.sS), lat_bytes);
         T n[3];
         normal(P, gphi, n);
         // flow set: the new bracket pi, as stored, is the reference of the
         // values this node emits and goes to its own rest slot
         const T pi_st = stored<S, T>(fl.pi, T(LG::w[0]), T(1.0 / LG::w[0]));
-        st_pop<NTW>(at(dG, node), Codec<S, T>::st(fl.pi, T(1.0 / LG::w[0])));
+        dG.template st<NTW>(own_col, pp(Lay::G0, 0) + zoff, Codec<S, T>::st(fl.pi, T(1.0 / LG::w[0])));
         collide_g<LG>(P, g, gphi, fl, [&](int i, T v) {
-          const Off t = target(i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
-          st_pop<NTW>(at(dG, t),
-                      Codec<S, T>::st(v + kp<LG, T>(i) * (pi0 - pi_st), T(1.0 / LG::w[i])));
+          const Tgt t = target(Lay::G0, i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
+          dG.template st<NTW>(t.lane, t.uni,
+                              Codec<S, T>::st(v + kp<LG, T>(i) * (pi0 - pi_st), T(1.0 / LG::w[i])));
         });
-        if (LATE) load_q<LF, NTL, true>(sF, G.sS, node, f);
+        if (LATE) ldq(sF, Lay::F0, own_col, zoff, f);
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
-          const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          st_pop<NTW>(at(dF, t), rebase(i, v, r[0], R.phi));
+          const Tgt t = target(Lay::F0, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          dF.template st<NTW>(t.lane, t.uni, rebase(i, v, r[0], R.phi));
         });
         if (LATE) {
-          load_q<LF, NTL, true>(sH1, G.sS, node, h1);
-          load_q<LF, NTL, true>(sH2, G.sS, node, h2);
+          ldq(sH1, Lay::H10, own_col, zoff, h1);
+          ldq(sH2, Lay::H20, own_col, zoff, h2);
         }
         if constexpr (LOC) {
           // local scheme, Eq. (39): grad c_k from the first moment of the
@@ -399,13 +430,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
           }
         }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
-          const Off t = target(i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          const Tgt t1 = target(Lay::H10, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          const Tgt t2 = target(Lay::H20, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
           if constexpr (!LOC) {
-            st_pop<NTW>(at(dH1, t), rebase(i, a, r[1], R.c1));
-            st_pop<NTW>(at(dH2, t), rebase(i, c, r[2], R.c2));
+            dH1.template st<NTW>(t1.lane, t1.uni, rebase(i, a, r[1], R.c1));
+            dH2.template st<NTW>(t2.lane, t2.uni, rebase(i, c, r[2], R.c2));
           } else {
-            st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / LF::w[i])));
-            st_pop<NTW>(at(dH2, t), Codec<S, T>::st(c, T(1.0 / LF::w[i])));
+            dH1.template st<NTW>(t1.lane, t1.uni, Codec<S, T>::st(a, T(1.0 / LF::w[i])));
+            dH2.template st<NTW>(t2.lane, t2.uni, Codec<S, T>::st(c, T(1.0 / LF::w[i])));
           }
         });
       }
@@ -461,10 +493,10 @@ int choose_chunks(int tiles_xy, int nz, int slots) {
 }
 
 template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE,
-          class Off, bool LOC = false>
+          class Off, bool LOC, bool BUF>
 hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, hipStream_t stream) {
-  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off, LOC>;
+  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off, LOC, BUF>;
   static std::atomic<int> per_cu{0};
   int groups = per_cu.load(std::memory_order_relaxed);
   if (groups < 1) {
@@ -516,18 +548,32 @@ hipError_t launch_scheme(const S* src, S* dst, const T* hin, T* hout, T* fields,
   if (!fits_u32(LG::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t, LOC>(
+      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, uint64_t, LOC, false>(
           src, dst, hin, hout, fields, P, Pdev, stream);
-    return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t, LOC>(
+    return launch_variant<S, T, 64, 4, 0, false, true, 1, M, uint64_t, LOC, false>(
+        src, dst, hin, hout, fields, P, Pdev, stream);
+  }
+  // Buffer addressing for FP32 / FP64 storage.  16-bit lattices keep the
+  // global form: there the scalar work of the uniform offsets (a product
+  // and two sums per access) costs more than the vector adds it removes
+  // (1.08 against 1.04 ms per 256^3 FP16 step; FP32 1.29 against 1.32).
+  constexpr bool kBuf = sizeof(S) >= 4;
+  if (kBuf && !fits_buffer(Lay::QTOT, P.stride, sizeof(S), sizeof(T), kNumFields)) {
+    // every set below 4 GiB but not the whole lattice: 32-bit offsets from
+    // a 64-bit base per set, one tile shape
+    if (mode == kModeMacros)
+      return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U, LOC, false>(
+          src, dst, hin, hout, fields, P, Pdev, stream);
+    return launch_variant<S, T, 64, 4, 2, false, false, 1, M, U, LOC, false>(
         src, dst, hin, hout, fields, P, Pdev, stream);
   }
   // the field read-out takes the scheme's references of h1, h2 (per node for
   // the central stencil, uniform for the local scheme)
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U, LOC>(
+    return launch_variant<S, T, 64, 4, 0, false, false, 1, kModeMacros, U, LOC, kBuf>(
         src, dst, hin, hout, fields, P, Pdev, stream);
 #define PFLB_V3(TX, TY, NT, PREF, LATE, WPE) \
-  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC>(src, dst, hin, hout, fields, P, Pdev, stream)
+  launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC, kBuf>(src, dst, hin, hout, fields, P, Pdev, stream)
   // NT: non-temporal hints (bit 0 f / h loads, bit 1 stores, bit 2 g loads);
   // LATE: f / h re-read before their collision; WPE: minimum waves per SIMD
   // the register allocator must allow (1: free)

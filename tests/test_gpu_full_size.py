@@ -125,7 +125,7 @@ def test_one_scalar_bubble_full_size(cplb):
     run_pair(cplb, w, 200, FP32_2D, 1e-5, "t=200")
 
 
-# --------------------------------------------- sets beyond 4 GiB (64-bit path)
+# ------------------------- lattices beyond 4 GiB (per-set and 64-bit offsets)
 
 def _random_field_pair(cplb, p, steps, names, tol, label):
     f = W.random_fields(p, seed=23)
@@ -151,8 +151,8 @@ def _random_field_pair(cplb, p, steps, names, tol, label):
 
 def test_64bit_offsets_3d_fp32(cplb):
     """384^3 FP32: the 19 planes of g span more than 4 GiB, so the step takes
-    its 64-bit-offset instantiation (every smaller case takes the 32-bit
-    one).  Random fields, walls on x and z, 2 steps, every field."""
+    its 64-bit-offset instantiation (smaller cases take 32-bit offsets).
+    Random fields, walls on x and z, 2 steps, every field."""
     n = 384
     assert 19 * n ** 3 * 4 > 1 << 32
     p = W.params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", periodic=(0, 1, 0), precision="f32",
@@ -161,6 +161,20 @@ def test_64bit_offsets_3d_fp32(cplb):
                  ref_f=W.phase_reference("f32"))
     say("384^3 f32 random fields (64-bit offsets), 2 steps")
     _random_field_pair(cplb, p, 2, FP32_3D + ("psi",), 1e-5, "t=2")
+
+
+def test_per_set_offsets_3d_fp64(cplb):
+    """256^3 FP64: the 40 population planes span more than 4 GiB but each set
+    less, so the 3-D step takes 32-bit offsets from a base per set instead
+    of buffer accesses over the whole lattice.  Random fields, walls on y,
+    2 steps, every field to FP64 round-off."""
+    n = 256
+    assert 40 * n ** 3 * 8 > 1 << 32 and 19 * (n ** 3 + 4096) * 8 < 1 << 32
+    p = W.params(nx=n, ny=n, nz=n, lattice="d3q19_d3q7", periodic=(1, 0, 1), precision="f64",
+                 sigma=2e-3, rho1=3.0, rho2=1.0, visc_law="exp", mu1=0.3, mu2=0.08, D1=0.07,
+                 D2=0.02, Keq=0.6, A=0.4, g=(1e-5, -2e-5, 3e-5), rho_ref=1.5)
+    say("256^3 f64 random fields (32-bit offsets per set), 2 steps")
+    _random_field_pair(cplb, p, 2, FP32_3D + ("mu", "psi"), 1e-12, "t=2")
 
 
 def test_64bit_offsets_2d_fp64(cplb):
