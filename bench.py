@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44272426, "write": 43020688,
-                                  "src": "c86daa52e20d4e10"},
-    "rising_droplet_256c_f32": {"read": 3162481621, "write": 3117583621,
-                               "src": "c86daa52e20d4e10"},
-    "rising_droplet_256c_f32_s16f": {"read": 1786464341, "write": 1773712506,
-                                    "src": "c86daa52e20d4e10"},
-    "rising_bubble_2048x4096_f32": {"read": 1465819968, "write": 1376908218,
-                                   "src": "c86daa52e20d4e10"},
-    "rising_bubble_one_256x1024_f32": {"read": 32824021, "write": 32532762,
-                                      "src": "c86daa52e20d4e10"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1736460288, "write": 1379446458,
-                                         "src": "c86daa52e20d4e10"},
-    "rising_droplet_local_256c_f32": {"read": 3171405440, "write": 3120242832,
-                                     "src": "c86daa52e20d4e10"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1773599872, "write": 1771606730,
-                                          "src": "c86daa52e20d4e10"},
+    "rising_bubble_256x1024_f32": {"read": 44324373, "write": 43023253,
+                                 "src": "97df2f6c61e1c247"},
+    "rising_droplet_256c_f32": {"read": 3255236138, "write": 3117534880,
+                              "src": "97df2f6c61e1c247"},
+    "rising_droplet_256c_f32_s16f": {"read": 1786744362, "write": 1773189152,
+                                   "src": "97df2f6c61e1c247"},
+    "rising_bubble_2048x4096_f32": {"read": 1385569386, "write": 1379612981,
+                                  "src": "97df2f6c61e1c247"},
+    "rising_bubble_one_256x1024_f32": {"read": 32821845, "write": 32532010,
+                                     "src": "97df2f6c61e1c247"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1379142400, "write": 1379600965,
+                                        "src": "97df2f6c61e1c247"},
+    "rising_droplet_local_256c_f32": {"read": 3269581013, "write": 3120992544,
+                                    "src": "97df2f6c61e1c247"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773721898, "write": 1771656901,
+                                         "src": "97df2f6c61e1c247"},
 }
 
 

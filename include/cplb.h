@@ -333,11 +333,12 @@ int cplb_batch_class_cases(const cplb_batch_t* b, int cls);
 int cplb_batch_get_variant(const cplb_batch_t* b, int cls);
 int cplb_batch_set_variant(cplb_batch_t* b, int cls, int variant);
 
-/* Autotuner: per class, time every variant for probe_steps launches on the
- * current state and keep the fastest.  The state is left as it was (probes
- * write only the idle lattices; histories are saved and restored).
- * Synchronises; *ms_per_step (may be NULL) receives the sum of the classes'
- * best times per step. */
+/* Autotuner: class after class, time every variant of the class within the
+ * whole sweep (the other classes at their current variants) for
+ * probe_steps sweeps on the current state, and keep the fastest.  The state
+ * is left as it was (probes write only the idle lattices and histories).
+ * Synchronises; *ms_per_step (may be NULL) receives the time per sweep of
+ * the final choice. */
 int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step);
 
 const char* cplb_batch_last_error(const cplb_batch_t* b);

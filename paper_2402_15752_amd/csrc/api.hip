@@ -102,11 +102,14 @@ int num_variants(const cplb_t* h) { return h->G.dim == 2 ? kVariants2D : kVarian
 // Cache); cplb_tune re-checks on the caller's own state.
 int default_variant(const cplb_params* p) {
   if (p->lattice == CPLB_D2Q9) {
-    // 128x4; with the local gradient scheme a lattice beyond the 256 MB
-    // Infinity Cache streams faster with non-temporal hints (128x4 nt)
+    // 128x4; a lattice beyond the 256 MB Infinity Cache streams faster with
+    // non-temporal stores and cached loads (128x4 nt-st): at 2048 x 4096
+    // FP32 596 against 627 us (central) and 553 against 579 us (local
+    // scheme, against non-temporal loads too), and its loads read 1.00x the
+    // algorithmic bytes (the halo re-reads hit L2) against 1.07x and 1.26x
     const int s_pop = p->precision == CPLB_F64 ? 8 : (p->precision == CPLB_F32 ? 4 : 2);
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
-    return p->scalar_grad == CPLB_GRAD_LOCAL && lattice_bytes > 256e6 ? 7 : 3;
+    return lattice_bytes > 256e6 ? 8 : 3;
   }
   // 3-D, every precision and gradient scheme: 64x4 with f, h1, h2 carried in
   // registers from the previous plane, non-temporal stores.  (With 16-bit

@@ -628,8 +628,12 @@ int cplb_batch_set_variant(cplb_batch_t* b, int cls, int v) {
 int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
   if (!b) return CPLB_EINVAL;
   if (probe_steps < 1) return set_err(b, CPLB_EINVAL, "probe_steps must be >= 1");
-  // Per class: the probes read the current lattices and histories and write
-  // only the idle ones (scratch), so the state is left as it was.
+  // Coordinate descent over the classes.  Every probe times the whole sweep
+  // -- each class with its current variant but the one being probed --
+  // because a class timed alone keeps its lattices in the Infinity Cache and
+  // favours variants that lose once the other classes stream beside it.
+  // The probes read the current lattices and histories and write only the
+  // idle ones, so the state is left as it was.
   hipEvent_t e0, e1;
   int rc = hip_check(b, hipEventCreate(&e0), "tune: event");
   if (rc) return rc;
@@ -638,38 +642,43 @@ int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
     (void)hipEventDestroy(e0);
     return rc;
   }
-  double total_ms = 0;
+  auto sweep = [&](int cls, int v) -> int {
+    for (int c = 0; c < kBatchClasses; ++c) {
+      if (b->cls_count[c] == 0) continue;
+      const int e = hip_check(b, run_class(b, c, kModeStep, c == cls ? v : b->variant[c]), "tune: probe");
+      if (e) return e;
+    }
+    return CPLB_OK;
+  };
+  float best_ms = -1.f;
   for (int cls = 0; cls < kBatchClasses && rc == CPLB_OK; ++cls) {
     if (b->cls_count[cls] == 0) continue;
     const int keep = b->variant[cls];
     int best = keep;
-    float best_ms = 0;
+    float cls_best = -1.f;
     for (int v = 0; v < kVariants2D && rc == CPLB_OK; ++v) {
-      rc = hip_check(b, run_class(b, cls, kModeStep, v), "tune: warm-up");
-      if (rc) break;
-      rc = hip_check(b, hipEventRecord(e0, b->stream), "tune: record");
-      for (int k = 0; k < probe_steps && rc == CPLB_OK; ++k)
-        rc = hip_check(b, run_class(b, cls, kModeStep, v), "tune: probe");
-      if (rc) break;
-      rc = hip_check(b, hipEventRecord(e1, b->stream), "tune: record");
+      rc = sweep(cls, v);  // warm-up
+      if (!rc) rc = hip_check(b, hipEventRecord(e0, b->stream), "tune: record");
+      for (int k = 0; k < probe_steps && rc == CPLB_OK; ++k) rc = sweep(cls, v);
+      if (!rc) rc = hip_check(b, hipEventRecord(e1, b->stream), "tune: record");
       if (!rc) rc = hip_check(b, hipEventSynchronize(e1), "tune: wait");
       float ms = 0;
       if (!rc) rc = hip_check(b, hipEventElapsedTime(&ms, e0, e1), "tune: time");
       if (rc) break;
-      if (v == 0 || ms < best_ms) {
-        best_ms = ms;
+      if (cls_best < 0 || ms < cls_best) {
+        cls_best = ms;
         best = v;
       }
     }
     b->variant[cls] = rc == CPLB_OK ? best : keep;
-    total_ms += best_ms;
+    best_ms = cls_best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const int rc3 = hip_check(b, hipStreamSynchronize(b->stream), "tune: synchronise");
   if (rc) return rc;
   if (rc3) return rc3;
-  if (ms_per_step) *ms_per_step = total_ms / probe_steps;
+  if (ms_per_step) *ms_per_step = best_ms > 0 ? best_ms / probe_steps : 0.0;
   return CPLB_OK;
 }
 

@@ -17,7 +17,7 @@ namespace {
 template <class X>
 using CPtr = const __attribute__((address_space(4))) X*;
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE>
+template <class S, class T, int TX, int TY, int NTM, int MODE>
 __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, CPtr<int> ids,
                                                          CPtr<int> prefix, int ncls,
                                                          CPtr<int> map, int total, KPtr<T> kps,
@@ -56,17 +56,17 @@ __global__ __launch_bounds__(TX* TY) void batch2d_kernel(CPtr<BatchCase> cases, 
   const S* src = (const S*)D->lat[parity];
   S* dst = (S*)D->lat[parity ^ 1];
   const KParams<T>& P = *(const KParams<T>*)(kps + c);
-  step2d_tile<S, T, TX, TY, NTS, MODE, uint32_t>(src, dst, (const T*)D->hist[parity],
+  step2d_tile<S, T, TX, TY, NTM, MODE, uint32_t>(src, dst, (const T*)D->hist[parity],
                                                  (T*)D->hist[parity ^ 1], (T*)D->fields, P, G,
                                                  tile);
 }
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE>
+template <class S, class T, int TX, int TY, int NTM, int MODE>
 hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, int ncls,
                     const int* map, int total, const KParams<T>* kps, int parity,
                     hipStream_t stream) {
   const int nblocks = ((total + 7) / 8) * 8;
-  hipLaunchKernelGGL((batch2d_kernel<S, T, TX, TY, NTS, MODE>), dim3(nblocks), dim3(TX * TY), 0,
+  hipLaunchKernelGGL((batch2d_kernel<S, T, TX, TY, NTM, MODE>), dim3(nblocks), dim3(TX * TY), 0,
                      stream, (CPtr<BatchCase>)cases, (CPtr<int>)ids, (CPtr<int>)prefix, ncls,
                      (CPtr<int>)map, total, (KPtr<T>)kps, parity);
   return hipGetLastError();
@@ -76,8 +76,8 @@ hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, i
 
 // tile shapes of the 2-D variants (the same table as the single-lattice step)
 int step2d_tiles(int nx, int ny, int variant) {
-  static const int tx[kVariants2D] = {64, 32, 32, 128, 64, 32, 32, 128};
-  static const int ty[kVariants2D] = {4, 8, 4, 4, 4, 8, 4, 4};
+  static const int tx[kVariants2D] = {64, 32, 32, 128, 64, 32, 32, 128, 128, 128};
+  static const int ty[kVariants2D] = {4, 8, 4, 4, 4, 8, 4, 4, 4, 4};
   if (variant < 0 || variant >= kVariants2D) variant = 0;
   return ((nx + tx[variant] - 1) / tx[variant]) * ((ny + ty[variant] - 1) / ty[variant]);
 }
@@ -89,17 +89,19 @@ hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* pre
   if (total <= 0) return hipSuccess;
   constexpr int M = kModeStep;
   if (mode == kModeMacros)
-    return launch_b<S, T, 64, 4, false, kModeMacros>(cases, ids, prefix, ncls, map, total, kps,
+    return launch_b<S, T, 64, 4, 0, kModeMacros>(cases, ids, prefix, ncls, map, total, kps,
                                                      parity, stream);
   switch (variant) {
-    case 1: return launch_b<S, T, 32, 8, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 2: return launch_b<S, T, 32, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 3: return launch_b<S, T, 128, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 4: return launch_b<S, T, 64, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 5: return launch_b<S, T, 32, 8, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 6: return launch_b<S, T, 32, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    case 7: return launch_b<S, T, 128, 4, true, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
-    default: return launch_b<S, T, 64, 4, false, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 1: return launch_b<S, T, 32, 8, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 2: return launch_b<S, T, 32, 4, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 3: return launch_b<S, T, 128, 4, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 4: return launch_b<S, T, 64, 4, 7, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 5: return launch_b<S, T, 32, 8, 7, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 6: return launch_b<S, T, 32, 4, 7, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 7: return launch_b<S, T, 128, 4, 7, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 8: return launch_b<S, T, 128, 4, 2, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 9: return launch_b<S, T, 128, 4, 3, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    default: return launch_b<S, T, 64, 4, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
   }
 }
 

@@ -29,7 +29,7 @@ using Lay = Layout<D2Q9, D2Q9>;
 // The lattice constants are read through a constant-address-space pointer
 // (scalar loads of the device copy) rather than passed by value: the kernel
 // arguments stay a few dozen bytes.
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL>
+template <class S, class T, int TX, int TY, int NTM, int MODE, class Off, int MODEL>
 __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst,
                                                         const T* __restrict__ hin,
@@ -43,11 +43,11 @@ __global__ __launch_bounds__(TX* TY) void step2d_kernel(const S* __restrict__ sr
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= G.ntiles) return;
-  step2d_tile<S, T, TX, TY, NTS, MODE, Off, MODEL>(src, dst, hin, hout, fields, params(Pg), G,
+  step2d_tile<S, T, TX, TY, NTM, MODE, Off, MODEL>(src, dst, hin, hout, fields, params(Pg), G,
                                                    tile);
 }
 
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL>
+template <class S, class T, int TX, int TY, int NTM, int MODE, class Off, int MODEL>
 hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, const float* closure, hipStream_t stream) {
   Geo2<Off> G;
@@ -62,7 +62,7 @@ hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields
   G.sT = Off(P.stride * (long long)sizeof(T));
   G.closure = closure;
   const int nblocks = ((G.ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTS, MODE, Off, MODEL>), dim3(nblocks), dim3(TX * TY),
+  hipLaunchKernelGGL((step2d_kernel<S, T, TX, TY, NTM, MODE, Off, MODEL>), dim3(nblocks), dim3(TX * TY),
                      0, stream, src, dst, hin, hout, fields, (KPtr<T>)Pdev, G);
   return hipGetLastError();
 }
@@ -72,7 +72,8 @@ hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields
 // variant table: tile TX x TY and non-temporal population traffic
 const char* step2d_variant_name(int v) {
   static const char* names[kVariants2D] = {"64x4",    "32x8",    "32x4",    "128x4",
-                                          "64x4 nt", "32x8 nt", "32x4 nt", "128x4 nt"};
+                                          "64x4 nt", "32x8 nt", "32x4 nt", "128x4 nt",
+                                          "128x4 nt-st", "128x4 nt-own"};
   return v >= 0 && v < kVariants2D ? names[v] : "?";
 }
 
@@ -88,23 +89,25 @@ hipError_t launch_model(const S* src, S* dst, const T* hin, T* hout, T* fields, 
   if (!fits_u32(L::Q, P.stride, sizeof(S), sizeof(T), kNumFields)) {
     // very large grids: 64-bit offsets, one tile shape
     if (mode == kModeMacros)
-      return launch_variant<S, T, 64, 4, false, kModeMacros, uint64_t, MODEL>(src, dst, hin, hout, fields,
+      return launch_variant<S, T, 64, 4, 0, kModeMacros, uint64_t, MODEL>(src, dst, hin, hout, fields,
                                                                            P, Pdev, closure, stream);
-    return launch_variant<S, T, 128, 4, false, M, uint64_t, MODEL>(src, dst, hin, hout, fields, P,
+    return launch_variant<S, T, 128, 4, 0, M, uint64_t, MODEL>(src, dst, hin, hout, fields, P,
                                                                 Pdev, closure, stream);
   }
   if (mode == kModeMacros)
-    return launch_variant<S, T, 64, 4, false, kModeMacros, U, MODEL>(src, dst, hin, hout, fields, P,
+    return launch_variant<S, T, 64, 4, 0, kModeMacros, U, MODEL>(src, dst, hin, hout, fields, P,
                                                                   Pdev, closure, stream);
   switch (variant) {
-    case 1: return launch_variant<S, T, 32, 8, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 2: return launch_variant<S, T, 32, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 3: return launch_variant<S, T, 128, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 4: return launch_variant<S, T, 64, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 5: return launch_variant<S, T, 32, 8, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 6: return launch_variant<S, T, 32, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    case 7: return launch_variant<S, T, 128, 4, true, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
-    default: return launch_variant<S, T, 64, 4, false, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 1: return launch_variant<S, T, 32, 8, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 2: return launch_variant<S, T, 32, 4, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 3: return launch_variant<S, T, 128, 4, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 4: return launch_variant<S, T, 64, 4, 7, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 5: return launch_variant<S, T, 32, 8, 7, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 6: return launch_variant<S, T, 32, 4, 7, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 7: return launch_variant<S, T, 128, 4, 7, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 8: return launch_variant<S, T, 128, 4, 2, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 9: return launch_variant<S, T, 128, 4, 3, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    default: return launch_variant<S, T, 64, 4, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
   }
 }
 

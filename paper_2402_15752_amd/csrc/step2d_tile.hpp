@@ -44,7 +44,7 @@ struct Geo2 {
 // planes, no h2 traffic, no psi stencil, history (u, phi, c);
 // kModelTwoDirichlet adds the Dirichlet faces' anti-bounce-back of h1, h2
 // (a compiled variant: the check costs the plain step ~5%).
-template <class S, class T, int TX, int TY, bool NTS, int MODE, class Off, int MODEL = kModelTwo>
+template <class S, class T, int TX, int TY, int NTM, int MODE, class Off, int MODEL = kModelTwo>
 __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ dst,
                                    const T* __restrict__ hin, T* __restrict__ hout,
                                    T* __restrict__ fields, const KParams<T>& P, const Geo2<Off>& G,
@@ -58,6 +58,9 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NHALO = 2 * LX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
   constexpr Off BS = sizeof(S);
+  // non-temporal hints: bit 0 the own node's loads, bit 1 the stores, bit 2
+  // the halo node's loads (lines a neighbouring tile reads again)
+  constexpr bool NTL = NTM & 1, NTW = NTM & 2, NTH = NTM & 4;
   __shared__ T sphi[LY][LX];
   __shared__ T spi[LY][LX];  // pressure brackets: the references of the flow set
   __shared__ T sc1[HALO_H ? LY : 1][LX];
@@ -103,20 +106,20 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   T hr[3] = {T(0), T(0), T(0)};  // references (phi, c1, c2) of the halo node
   T hpi = T(0);                  // and its pressure bracket (rest slot of g)
   if (own_slot) {
-    load_q<L, NTS, false>(sF, G.sS, node, f);
-    load_q<L, NTS, false>(sH1, G.sS, node, h1);
-    if (!ONE) load_q<L, NTS, false>(sH2, G.sS, node, h2);
-    load_q<L, NTS, false>(sG, G.sS, node, g);
+    load_q<L, NTL, false>(sF, G.sS, node, f);
+    load_q<L, NTL, false>(sH1, G.sS, node, h1);
+    if (!ONE) load_q<L, NTL, false>(sH2, G.sS, node, h2);
+    load_q<L, NTL, false>(sG, G.sS, node, g);
 #pragma unroll
     for (int k = 0; k < NH; ++k) hs[k] = *at(hin, plane<false>(k, G.sT) + nodeT);
   }
   if (halo) {
-    load_q<L, NTS, false>(sF, G.sS, halo_node, hf);
-    hpi = Codec<S, T>::ld(ld_pop<NTS>(at(sG, halo_node)), T(L::w[0]));
+    load_q<L, NTH, false>(sF, G.sS, halo_node, hf);
+    hpi = Codec<S, T>::ld(ld_pop<NTH>(at(sG, halo_node)), T(L::w[0]));
     hr[0] = *at(hin, plane<false>(kPhi, G.sT) + halo_nodeT);
     if (HALO_H) {
-      load_q<L, NTS, false>(sH1, G.sS, halo_node, hh1);
-      load_q<L, NTS, false>(sH2, G.sS, halo_node, hh2);
+      load_q<L, NTH, false>(sH1, G.sS, halo_node, hh1);
+      load_q<L, NTH, false>(sH2, G.sS, halo_node, hh2);
       hr[1] = *at(hin, plane<false>(kC1, G.sT) + halo_nodeT);
       hr[2] = *at(hin, plane<false>(kC2, G.sT) + halo_nodeT);
     }
@@ -250,15 +253,15 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
   S* __restrict__ dH2 = at(dst, (size_t)Lay::H20 * G.sS);
   const T rphi = hs[kPhi];
   auto emit_f = [&](int i, T v) {
-    st_pop<NTS>(at(dF, target(i)),
+    st_pop<NTW>(at(dF, target(i)),
                 Codec<S, T>::st(rebase_phi(i, v, rphi), T(1.0 / L::w[i])));
   };
   // flow set: the new bracket pi, as stored, is the reference of the values
   // this node emits and goes to its own rest slot
   const T pi_st = stored<S, T>(fl.pi, T(L::w[0]), T(1.0 / L::w[0]));
-  st_pop<NTS>(at(dG, target(0)), Codec<S, T>::st(fl.pi, T(1.0 / L::w[0])));
+  st_pop<NTW>(at(dG, target(0)), Codec<S, T>::st(fl.pi, T(1.0 / L::w[0])));
   auto emit_g = [&](int i, T v) {
-    st_pop<NTS>(at(dG, target(i)),
+    st_pop<NTW>(at(dG, target(i)),
                 Codec<S, T>::st(v + kp<L, T>(i) * (pi0 - pi_st), T(1.0 / L::w[i])));
   };
   // Dirichlet faces this node's links reach (0 for every interior node)
@@ -269,7 +272,7 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
     collide_g<L>(P, g, gphi, fl, emit_g);
     collide_f<L>(P, f, s, n, fl, dJphi, emit_f);
     collide_h3<L>(P, h1, s, fl, dJ1, [&](int i, T v) {
-      st_pop<NTS>(at(dH1, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
+      st_pop<NTW>(at(dH1, target(i)), Codec<S, T>::st(v, T(1.0 / L::w[i])));
     });
     return;
   }
@@ -320,8 +323,8 @@ __device__ inline void step2d_tile(const S* __restrict__ src, S* __restrict__ ds
             }
           }
         }
-        st_pop<NTS>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
-        st_pop<NTS>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
+        st_pop<NTW>(at(dH1, t), Codec<S, T>::st(a, T(1.0 / L::w[i])));
+        st_pop<NTW>(at(dH2, t), Codec<S, T>::st(b, T(1.0 / L::w[i])));
       },
       G.closure ? T(G.closure[y * nx + x]) : T(0),
       G.closure ? T(G.closure[(long long)nx * ny + y * nx + x]) : T(0));

@@ -126,6 +126,20 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const View<BUF, T, Off> vout(hout, BUF ? Off(kHist3D) * G.sT : Off(0));
   // byte offset of plane i of population set `set` from that set's view
   auto pp = [&](int set, int i) -> Off { return plane<true>((BUF ? set : 0) + i, G.sS); };
+  // The (lane, uniform) parts of an access at column `col` of the z plane at
+  // byte offset `zb`, plus the access's own uniform offset u (set, plane)
+  // and constant k (skew).  BUF keeps the z plane in the uniform part; the
+  // global form adds it to the column once per plane (the node's offset)
+  // and u and k to that per access, k as the instruction's offset.
+  struct Acc {
+    Off lane, uni;
+  };
+  auto acc = [&](Off col, Off zb, Off u, Off k) -> Acc {
+    if constexpr (BUF)
+      return Acc{col, u + zb + k};
+    else
+      return Acc{Off(0), u + (zb + col) + k};
+  };
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -156,9 +170,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // the 7 populations of a D3Q7 set
   auto ldq = [&](const VS& v, int set, Off col, Off zb, T (&x)[7]) {
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
-      x[i] = Codec<S, T>::ld(v.template ld<NTL>(col, pp(set, i) + zb + skew<LF, S, Off>(i)),
-                             T(LF::w[i]));
+    for (int i = 0; i < 7; ++i) {
+      const Acc a = acc(col, zb, pp(set, i), skew<LF, S, Off>(i));
+      x[i] = Codec<S, T>::ld(v.template ld<NTL>(a.lane, a.uni), T(LF::w[i]));
+    }
+  };
+  // history and field planes (T values): the column and z plane in T bytes
+  auto ldh = [&](Off col, Off zb, int k) -> T {
+    const Acc a = acc(col * TS, zb * TS, plane<true>(k, G.sT), Off(0));
+    return vin.template ld<false>(a.lane, a.uni);
   };
   auto load_fh = [&](Off col, Off zb, T (&f)[7], T (&h1)[7], T (&h2)[7]) {
     ldq(sF, Lay::F0, col, zb, f);
@@ -167,11 +187,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   };
   // the references (phi, c1, c2 of the previous level) of a node
   auto load_ref = [&](Off col, Off zb, T (&r)[3]) {
-    const Off cT = col * TS, zT = zb * TS;
-    r[0] = vin.template ld<false>(cT, zT + plane<true>(kPhi, G.sT));
+    r[0] = ldh(col, zb, kPhi);
     if (!LOC) {
-      r[1] = vin.template ld<false>(cT, zT + plane<true>(kC1, G.sT));
-      r[2] = vin.template ld<false>(cT, zT + plane<true>(kC2, G.sT));
+      r[1] = ldh(col, zb, kC1);
+      r[2] = ldh(col, zb, kC2);
     } else {
       r[1] = T(0);
       r[2] = T(0);
@@ -180,7 +199,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // the pressure bracket a node's flow populations are stored relative to
   // (the rest slot of its g)
   auto load_pi = [&](Off col, Off zb) -> T {
-    return Codec<S, T>::ld(sG.template ld<NTG>(col, pp(Lay::G0, 0) + zb), T(LG::w[0]));
+    const Acc a = acc(col, zb, pp(Lay::G0, 0), Off(0));
+    return Codec<S, T>::ld(sG.template ld<NTG>(a.lane, a.uni), T(LG::w[0]));
   };
   // moments of plane zp of the own node into the ring
   auto put_own = [&](const KParams<T>& P, int zp, const T (&f)[7], const T (&h1)[7],
@@ -248,18 +268,19 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
   for (int z = z0; z < z1; ++z) {
     const KParams<T>& P = params(Pg);
-    const Off zoff = Off(z) * G.nxy;  // bytes, population arrays (uniform part)
-    const Off colT = own_col * TS, zoffT = zoff * TS;  // bytes, history / fields
+    const Off zoff = Off(z) * G.nxy;  // bytes, population arrays (uniform)
+    const Off node = zoff + own_col;  // the global form's per-lane offset of the node
     const Off pn = Off(fold(z + 1, nz, G.wall_z)) * G.nxy;
     // ---- 1. global loads of this plane
     T g[19], uo[3], nf[7], nh1[7], nh2[7], nr[3];
     auto load_g = [&] {
 #pragma unroll
-      for (int i = 1; i < 19; ++i)
-        g[i] = Codec<S, T>::ld(sG.template ld<NTG>(own_col, pp(Lay::G0, i) + zoff + skew<LG, S, Off>(i)),
-                               T(LG::w[i]));
+      for (int i = 1; i < 19; ++i) {
+        const Acc a = acc(own_col, zoff, pp(Lay::G0, i), skew<LG, S, Off>(i));
+        g[i] = Codec<S, T>::ld(sG.template ld<NTG>(a.lane, a.uni), T(LG::w[i]));
+      }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) uo[k] = vin.template ld<false>(colT, zoffT + plane<true>(k, G.sT));
+      for (int k = 0; k < 3; ++k) uo[k] = ldh(own_col, zoff, k);
     };
     if (PREF && active) load_g();
     load_fh(own_col, pn, nf, nh1, nh2);
@@ -318,7 +339,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       flow_macros<LG>(P, g, s, gphi, lap, pi0, fl);
       if (MODE == kModeMacros) {
         const View<BUF, T, Off> vf(fields, BUF ? Off(kNumFields) * G.sT : Off(0));
-        auto put_field = [&](int k, T v) { vf.template st<false>(colT, zoffT + plane<true>(k, G.sT), v); };
+        auto put_field = [&](int k, T v) {
+          const Acc a = acc(own_col * TS, zoff * TS, plane<true>(k, G.sT), Off(0));
+          vf.template st<false>(a.lane, a.uni, v);
+        };
         put_field(kFieldPhi, s.phi);
         put_field(kFieldP, fl.p);
         put_field(kFieldUx, fl.u[0]);
@@ -335,15 +359,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           dJphi[a] = s.phi * fl.u[a] - r[0] * uo[a];
-          dJ1[a] = s.c1 * fl.u[a] -
-                   (LOC ? vin.template ld<false>(colT, zoffT + plane<true>(kC1, G.sT)) : r[1]) * uo[a];
-          dJ2[a] = s.c2 * fl.u[a] -
-                   (LOC ? vin.template ld<false>(colT, zoffT + plane<true>(kC2, G.sT)) : r[2]) * uo[a];
+          dJ1[a] = s.c1 * fl.u[a] - (LOC ? ldh(own_col, zoff, kC1) : r[1]) * uo[a];
+          dJ2[a] = s.c2 * fl.u[a] - (LOC ? ldh(own_col, zoff, kC2) : r[2]) * uo[a];
         }
 #pragma unroll
         for (int k = 0; k < kHist3D; ++k) {
           const T v = k < 3 ? fl.u[k] : (k == kPhi ? s.phi : (k == kC1 ? s.c1 : s.c2));
-          vout.template st<false>(colT, zoffT + plane<true>(k, G.sT), v);
+          const Acc h = acc(own_col * TS, zoff * TS, plane<true>(k, G.sT), Off(0));
+          vout.template st<false>(h.lane, h.uni, v);
         }
 
         // z push deltas of this plane (uniform)
@@ -366,14 +389,27 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         };
         auto target = [&](int set, int i, int o, int cx, int cy, int cz) -> Tgt {
           const Off sk = cx > 0 ? Off(0) - BS : (cx < 0 ? BS : Off(0));
-          Off lane = own_col;
-          if (cx) lane += cx < 0 ? push.dxm : push.dxp;
-          if (cy) lane += cy < 0 ? push.dym : push.dyp;
-          Off uni = pp(set, i) + zoff + sk;
-          if (cz) uni += cz < 0 ? dzm : dzp;
-          if (!walls) return Tgt{lane, uni};
-          const Off back_t = pp(set, o) + zoff - sk + own_col;
-          return Tgt{(bits & link_mask(cx, cy, cz)) ? back_t : lane + uni, Off(0)};
+          if constexpr (BUF) {
+            Off lane = own_col;
+            if (cx) lane += cx < 0 ? push.dxm : push.dxp;
+            if (cy) lane += cy < 0 ? push.dym : push.dyp;
+            Off uni = pp(set, i) + zoff + sk;
+            if (cz) uni += cz < 0 ? dzm : dzp;
+            if (!walls) return Tgt{lane, uni};
+            const Off back_t = pp(set, o) + zoff - sk + own_col;
+            return Tgt{(bits & link_mask(cx, cy, cz)) ? back_t : lane + uni, Off(0)};
+          } else {
+            // the whole offset per lane: the node, its x / y / z step, then
+            // plane and skew
+            Off tn = node;
+            if (cx) tn += cx < 0 ? push.dxm : push.dxp;
+            if (cy) tn += cy < 0 ? push.dym : push.dyp;
+            if (cz) tn += cz < 0 ? dzm : dzp;
+            const Off push_t = pp(set, i) + tn + sk;
+            if (!walls) return Tgt{push_t, Off(0)};
+            const Off back_t = pp(set, o) + node - sk;
+            return Tgt{(bits & link_mask(cx, cy, cz)) ? back_t : push_t, Off(0)};
+          }
         };
         // The collisions emit X_i* - w_i R(x), R(x) the node's own reference
         // (its moment at the previous level); the D3Q7 value stored at the
@@ -397,7 +433,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         // flow set: the new bracket pi, as stored, is the reference of the
         // values this node emits and goes to its own rest slot
         const T pi_st = stored<S, T>(fl.pi, T(LG::w[0]), T(1.0 / LG::w[0]));
-        dG.template st<NTW>(own_col, pp(Lay::G0, 0) + zoff, Codec<S, T>::st(fl.pi, T(1.0 / LG::w[0])));
+        {
+          const Acc a = acc(own_col, zoff, pp(Lay::G0, 0), Off(0));
+          dG.template st<NTW>(a.lane, a.uni, Codec<S, T>::st(fl.pi, T(1.0 / LG::w[0])));
+        }
         collide_g<LG>(P, g, gphi, fl, [&](int i, T v) {
           const Tgt t = target(Lay::G0, i, LG::opp[i], LG::cx[i], LG::cy[i], LG::cz[i]);
           dG.template st<NTW>(t.lane, t.uni,
@@ -431,7 +470,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         }
         collide_h<LF>(P, h1, h2, s, n, gphi, gpsi, fl, dJ1, dJ2, [&](int i, T a, T c) {
           const Tgt t1 = target(Lay::H10, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
-          const Tgt t2 = target(Lay::H20, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
+          // (the global form reaches h1 and h2 at the same offset from their bases)
+          const Tgt t2 = BUF ? target(Lay::H20, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]) : t1;
           if constexpr (!LOC) {
             dH1.template st<NTW>(t1.lane, t1.uni, rebase(i, a, r[1], R.c1));
             dH2.template st<NTW>(t2.lane, t2.uni, rebase(i, c, r[2], R.c2));

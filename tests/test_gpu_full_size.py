@@ -5,8 +5,8 @@ FP64 oracle on the same seeded inputs.
 The benchmark's headline lattice (rising bubble 256 x 1024) and the 3-D FP32
 droplet at 256^3 are covered in test_gpu_parity.py.  Here: the 3-D droplet
 with FP16 storage and with the local gradient scheme (Eq. (39)), the 2-D
-lattice at 2048 x 4096 -- beyond the 256 MB Infinity Cache, where the local
-scheme takes the non-temporal variant -- and the one-scalar model
+lattice at 2048 x 4096 -- beyond the 256 MB Infinity Cache, where the step
+takes the variant with non-temporal stores -- and the one-scalar model
 (Sec. III D) at 256 x 1024.  A few steps each: the oracle takes ~0.3 s per
 step for 8 M nodes and ~0.6 s for 16.7 M nodes on 16 cores.
 
