@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44324373, "write": 43023253,
-                                 "src": "97df2f6c61e1c247"},
-    "rising_droplet_256c_f32": {"read": 3255236138, "write": 3117534880,
-                              "src": "97df2f6c61e1c247"},
-    "rising_droplet_256c_f32_s16f": {"read": 1786744362, "write": 1773189152,
-                                   "src": "97df2f6c61e1c247"},
-    "rising_bubble_2048x4096_f32": {"read": 1385569386, "write": 1379612981,
-                                  "src": "97df2f6c61e1c247"},
-    "rising_bubble_one_256x1024_f32": {"read": 32821845, "write": 32532010,
-                                     "src": "97df2f6c61e1c247"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1379142400, "write": 1379600965,
-                                        "src": "97df2f6c61e1c247"},
-    "rising_droplet_local_256c_f32": {"read": 3269581013, "write": 3120992544,
-                                    "src": "97df2f6c61e1c247"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1773721898, "write": 1771656901,
-                                         "src": "97df2f6c61e1c247"},
+    "rising_bubble_256x1024_f32": {"read": 44334165, "write": 43021450,
+                                 "src": "71cf04528b51694b"},
+    "rising_droplet_256c_f32": {"read": 3249836053, "write": 3117521386,
+                              "src": "71cf04528b51694b"},
+    "rising_droplet_256c_f32_s16f": {"read": 1813754858, "write": 1779236026,
+                                   "src": "71cf04528b51694b"},
+    "rising_bubble_2048x4096_f32": {"read": 1385106666, "write": 1379602650,
+                                  "src": "71cf04528b51694b"},
+    "rising_bubble_one_256x1024_f32": {"read": 32822357, "write": 32530464,
+                                     "src": "71cf04528b51694b"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1378502186, "write": 1379624400,
+                                        "src": "71cf04528b51694b"},
+    "rising_droplet_local_256c_f32": {"read": 3264600789, "write": 3120899317,
+                                    "src": "71cf04528b51694b"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773651840, "write": 1771582634,
+                                         "src": "71cf04528b51694b"},
 }
 
 

@@ -111,12 +111,16 @@ int default_variant(const cplb_params* p) {
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
     return lattice_bytes > 256e6 ? 8 : 3;
   }
-  // 3-D, every precision and gradient scheme: 64x4 with f, h1, h2 carried in
-  // registers from the previous plane, non-temporal stores.  (With 16-bit
-  // storage the variant that re-reads f, h1, h2 before their collision is
-  // 4% faster, but 41% of those re-reads miss L2: 1.41 x the algorithmic
-  // read bytes against 1.03 x.)
-  return 4;
+  // 3-D: 64x4 tiles, non-temporal stores, f, h1, h2 carried from the
+  // previous plane in registers -- or, for 16-bit storage with the central
+  // stencil for grad psi, in LDS, which takes the flow collision from two to
+  // three waves per SIMD (0.90 against 1.02 ms per 256^3 FP16 step; with
+  // FP32 storage the LDS carry is slower, 1.34 against 1.28 ms, and with the
+  // local scheme no faster).  The variant that re-reads f, h1, h2 before
+  // their collision is slower than the LDS carry, and 41% of its re-reads
+  // miss L2 (1.41 x the algorithmic read bytes).
+  const bool s16 = p->precision == CPLB_F32_S16F || p->precision == CPLB_F32_S16B;
+  return s16 && p->scalar_grad != CPLB_GRAD_LOCAL ? 8 : 4;
 }
 
 hipError_t run_kernel(cplb_t* h, int mode) {

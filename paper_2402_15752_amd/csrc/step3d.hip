@@ -7,10 +7,10 @@
 // z the group
 //   1. loads f, h1, h2 (21 values) and their references (phi, c1, c2 of
 //      the previous level, from the history) of its own nodes at z+1 --
-//      kept in registers for the next plane -- and of at most one halo node
-//      at z+1 (re-read from L2: neighbouring tiles march the same planes on
-//      the same XCD); the prefetching variants also load g and the velocity
-//      history of plane z here, before the barrier;
+//      kept for the next plane (in registers, or in LDS) -- and of at most
+//      one halo node at z+1 (re-read from L2: neighbouring tiles march the
+//      same planes on the same XCD); the prefetching variants also load g
+//      and the velocity history of plane z here, before the barrier;
 //   2. puts the moments of plane z+1 in the ring, then one barrier;
 //   3. collides plane z: 19-point stencils from ring planes z-1, z, z+1,
 //      all four sets collided and pushed to x + c_i of the other lattice
@@ -71,6 +71,8 @@ struct Geo3 {
 
 __device__ inline int slot_of(int z) { return (z + 4) & 3; }
 
+enum { kCarryRegs = 0, kCarryLate = 1, kCarryLds = 2 };
+
 template <class T, int TX, int TY, bool PSI>
 struct Ring {
   // phi, c1, c2 of four planes over the tile and its halo, exactly the
@@ -84,7 +86,7 @@ struct Ring {
 // LOC: grad(c1 + Keq c2) by the local scheme of Eq. (39) from the own h1, h2
 // of the plane being collided -- no scalar ring, no h1, h2 of the halo; h1,
 // h2 then keep the uniform reference (c1_ref, c2_ref).
-template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE, class Off,
+template <class S, class T, int TX, int TY, int NT, bool PREF, int CARRY, int WPE, int MODE, class Off,
           bool LOC, bool BUF>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(const S* __restrict__ src,
                                                         S* __restrict__ dst,
@@ -98,7 +100,13 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr bool NTL = NT & 1, NTW = NT & 2, NTG = NT & 4;
   constexpr Off BS = sizeof(S);
   constexpr int kPhi = 3, kC1 = 4, kC2 = 5;  // history planes: ux, uy, uz, phi, c1, c2
+  // where the own f, h1, h2 of a plane wait for its collision one z step
+  // after their load: registers, L2 (LATE: read again), or LDS (LDSC)
+  constexpr bool LATE = CARRY == kCarryLate, LDSC = CARRY == kCarryLds;
   __shared__ Ring<T, TX, TY, !LOC> R;
+  // LDSC: the lane's own f, h1, h2 of the plane being collided (each lane
+  // reads and writes only its own column: no barrier)
+  __shared__ T own[LDSC ? 21 : 1][LDSC ? NTH : 1];
   // XCD-aware order (see the 2-D kernel): XCD k runs a contiguous tile range
   const int per = (G.ntiles + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -259,12 +267,23 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const T ap0 = load_pi(own_col, p0);
     halo_plane(P, z0, p0);
     put_own(P, z0, f, h1, h2, r, ap0, s);
+    if constexpr (LDSC) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        own[i][tid] = f[i];
+        own[7 + i][tid] = h1[i];
+        own[14 + i][tid] = h2[i];
+      }
+    }
   }
-  // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits: the
-  // same lines were read for the moments one plane earlier) right before
-  // collide_f and collide_h, instead of being held in registers from the
-  // previous plane through the whole g collision.  21 more loads per node
-  // that HBM does not see; only the node state and references are carried.
+  // LATE: the own f, h1, h2 of plane z are read again (L1 / L2 hits when
+  // the lines survive the plane step) right before collide_f and
+  // collide_h, instead of being held in registers from the previous plane
+  // through the whole g collision; only the node state and references are
+  // carried.  LDSC: they wait in LDS, each lane's own slots: collide_f
+  // takes this plane's f out of them and puts the next plane's in (held in
+  // registers since its load), collide_h the same for h1, h2.  Through the
+  // flow collision 21 values fewer are live than with registers only.
 
   for (int z = z0; z < z1; ++z) {
     const KParams<T>& P = params(Pg);
@@ -303,6 +322,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
       const T lap = lap_of<LG, T>(nbp, s.phi);
       if (P.local_phase) {
         if (LATE) ldq(sF, Lay::F0, own_col, zoff, f);
+        if constexpr (LDSC) {
+#pragma unroll
+          for (int i = 0; i < 7; ++i) f[i] = own[i][tid];
+        }
         local_grad_phi<LF>(P, f, s.phi, uo, r[0], gphi);
       }
       if constexpr (!LOC) {
@@ -443,6 +466,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
                               Codec<S, T>::st(v + kp<LG, T>(i) * (pi0 - pi_st), T(1.0 / LG::w[i])));
         });
         if (LATE) ldq(sF, Lay::F0, own_col, zoff, f);
+        if constexpr (LDSC) {
+          // this plane's f out of its slots, the next plane's in
+#pragma unroll
+          for (int i = 0; i < 7; ++i) {
+            f[i] = own[i][tid];
+            own[i][tid] = nf[i];
+          }
+        }
         collide_f<LF>(P, f, s, n, fl, dJphi, [&](int i, T v) {
           const Tgt t = target(Lay::F0, i, LF::opp[i], LF::cx[i], LF::cy[i], LF::cz[i]);
           dF.template st<NTW>(t.lane, t.uni, rebase(i, v, r[0], R.phi));
@@ -450,6 +481,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         if (LATE) {
           ldq(sH1, Lay::H10, own_col, zoff, h1);
           ldq(sH2, Lay::H20, own_col, zoff, h2);
+        }
+        if constexpr (LDSC) {
+#pragma unroll
+          for (int i = 0; i < 7; ++i) {
+            h1[i] = own[7 + i][tid];
+            own[7 + i][tid] = nh1[i];
+            h2[i] = own[14 + i][tid];
+            own[14 + i][tid] = nh2[i];
+          }
         }
         if constexpr (LOC) {
           // local scheme, Eq. (39): grad c_k from the first moment of the
@@ -482,7 +522,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) v
         });
       }
     }
-    if (!LATE) {
+    if (CARRY == kCarryRegs) {
 #pragma unroll
       for (int i = 0; i < 7; ++i) {
         f[i] = nf[i];
@@ -532,11 +572,11 @@ int choose_chunks(int tiles_xy, int nz, int slots) {
   return best;
 }
 
-template <class S, class T, int TX, int TY, int NT, bool PREF, bool LATE, int WPE, int MODE,
+template <class S, class T, int TX, int TY, int NT, bool PREF, int CARRY, int WPE, int MODE,
           class Off, bool LOC, bool BUF>
 hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields, const KParams<T>& P,
                           const KParams<T>* Pdev, hipStream_t stream) {
-  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, LATE, WPE, MODE, Off, LOC, BUF>;
+  constexpr auto kernel = step3d_kernel<S, T, TX, TY, NT, PREF, CARRY, WPE, MODE, Off, LOC, BUF>;
   static std::atomic<int> per_cu{0};
   int groups = per_cu.load(std::memory_order_relaxed);
   if (groups < 1) {
@@ -573,7 +613,8 @@ hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields
 const char* step3d_variant_name(int v) {
   static const char* names[kVariants3D] = {
       "64x4 late",         "64x4 late nt-st", "32x8 late",          "64x4",
-      "64x4 nt-st",        "64x4 nt-g-st",    "64x4 late nt-g-st",  "64x4 late w4"};
+      "64x4 nt-st",        "64x4 nt-g-st",    "64x4 late nt-g-st",  "64x4 late w4",
+      "64x4 lds nt-st"};
   return v >= 0 && v < kVariants3D ? names[v] : "?";
 }
 
@@ -615,8 +656,9 @@ hipError_t launch_scheme(const S* src, S* dst, const T* hin, T* hout, T* fields,
 #define PFLB_V3(TX, TY, NT, PREF, LATE, WPE) \
   launch_variant<S, T, TX, TY, NT, PREF, LATE, WPE, M, U, LOC, kBuf>(src, dst, hin, hout, fields, P, Pdev, stream)
   // NT: non-temporal hints (bit 0 f / h loads, bit 1 stores, bit 2 g loads);
-  // LATE: f / h re-read before their collision; WPE: minimum waves per SIMD
-  // the register allocator must allow (1: free)
+  // CARRY: f / h carried in registers (false), re-read before their
+  // collision (true), or carried through LDS (kCarryLds); WPE: minimum
+  // waves per SIMD the register allocator must allow (1: free)
   switch (variant) {
     case 1: return PFLB_V3(64, 4, 2, false, true, 1);
     case 2: return PFLB_V3(32, 8, 0, false, true, 1);
@@ -625,6 +667,7 @@ hipError_t launch_scheme(const S* src, S* dst, const T* hin, T* hout, T* fields,
     case 5: return PFLB_V3(64, 4, 6, false, false, 1);
     case 6: return PFLB_V3(64, 4, 6, false, true, 1);
     case 7: return PFLB_V3(64, 4, 0, false, true, 4);
+    case 8: return PFLB_V3(64, 4, 2, false, kCarryLds, 1);
     default: return PFLB_V3(64, 4, 0, false, true, 1);
   }
 #undef PFLB_V3
