@@ -295,7 +295,10 @@ int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes
                            int ic1, int ic2);
 
 /* Advance every case nsteps >= 0 steps.  Asynchronous; a caller may capture
- * the launches in a HIP graph. */
+ * the launches in a HIP graph.  The size classes run on streams the batch
+ * creates for itself (default priority, destroyed with the batch), forked
+ * from the caller's stream and joined back into it by events, so the call
+ * is ordered on the caller's stream like every other. */
 int cplb_batch_step(cplb_batch_t* b, int64_t nsteps);
 
 int cplb_batch_num_cases(const cplb_batch_t* b);

@@ -148,6 +148,20 @@ struct cplb_batch {
   int total[kBatchClasses][kVariants2D];
   int variant[kBatchClasses];
   hipStream_t stream;
+  // The size classes step on streams of their own, forked from and joined
+  // back into `stream` around every call: their cases are disjoint, so one
+  // class's launches fill the tail of another's.  (Library-owned, default
+  // priority; null when they could not be created, and the classes then
+  // take turns on `stream`.)
+  hipStream_t cls_stream[kBatchClasses] = {};
+  hipEvent_t fork = nullptr, join[kBatchClasses] = {};
+  ~cplb_batch() {
+    for (int c = 0; c < kBatchClasses; ++c) {
+      if (cls_stream[c]) (void)hipStreamDestroy(cls_stream[c]);
+      if (join[c]) (void)hipEventDestroy(join[c]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  }
   char* ws;
   double* partials;
   BatchCase* d_cases;
@@ -187,22 +201,61 @@ size_t prefix_at(const cplb_batch_t* b, int cls, int v) {
 }
 
 template <class S, class T>
-hipError_t launch_class(cplb_batch_t* b, int cls, int mode, int v, const KParams<T>* kdev) {
+hipError_t launch_class(cplb_batch_t* b, int cls, int mode, int v, const KParams<T>* kdev,
+                        int parity, hipStream_t stream) {
   if (b->cls_count[cls] == 0) return hipSuccess;
   const int pv = mode == kModeMacros ? 0 : v;  // the read-out uses the first tile shape
   return launch_batch2d<S, T>(b->d_cases, b->d_ids + b->cls_first[cls],
                               b->d_prefix + prefix_at(b, cls, pv), b->cls_count[cls],
-                              b->d_map + 2 * b->map_at[cls][pv], b->total[cls][pv], kdev, b->cur,
-                              mode, v, b->stream);
+                              b->d_map + 2 * b->map_at[cls][pv], b->total[cls][pv], kdev, parity,
+                              mode, v, stream);
+}
+
+// one launch of class cls reading lattice `parity`, on `stream`
+hipError_t run_class_on(cplb_batch_t* b, int cls, int mode, int v, int parity, hipStream_t stream) {
+  switch (b->precision) {
+    case CPLB_F64: return launch_class<double, double>(b, cls, mode, v, b->d_k64, parity, stream);
+    case CPLB_F32: return launch_class<float, float>(b, cls, mode, v, b->d_k32, parity, stream);
+    case CPLB_F32_S16F: return launch_class<__half, float>(b, cls, mode, v, b->d_k32, parity, stream);
+    default: return launch_class<__hip_bfloat16, float>(b, cls, mode, v, b->d_k32, parity, stream);
+  }
 }
 
 hipError_t run_class(cplb_batch_t* b, int cls, int mode, int v) {
-  switch (b->precision) {
-    case CPLB_F64: return launch_class<double, double>(b, cls, mode, v, b->d_k64);
-    case CPLB_F32: return launch_class<float, float>(b, cls, mode, v, b->d_k32);
-    case CPLB_F32_S16F: return launch_class<__half, float>(b, cls, mode, v, b->d_k32);
-    default: return launch_class<__hip_bfloat16, float>(b, cls, mode, v, b->d_k32);
+  return run_class_on(b, cls, mode, v, b->cur, b->stream);
+}
+
+// nsteps sweeps over every class, class cls with tile variant var[cls].
+// advance: the lattices alternate as in stepping (the caller flips `cur`);
+// otherwise every sweep reads the current lattice and writes the idle one
+// (the tuner's probes).  Each class runs on its own stream, after the work
+// already on `stream` (fork) and before any that follows (join); graph
+// capture of `stream` takes the class streams in through the events.
+int enqueue_sweeps(cplb_batch_t* b, const int* var, int64_t nsteps, bool advance) {
+  if (nsteps <= 0) return CPLB_OK;
+  if (!b->fork) {
+    for (int64_t k = 0; k < nsteps; ++k)
+      for (int cls = 0; cls < kBatchClasses; ++cls) {
+        const int par = advance ? b->cur ^ (int)(k & 1) : b->cur;
+        const int rc = hip_check(b, run_class_on(b, cls, kModeStep, var[cls], par, b->stream),
+                                 "batch step kernel");
+        if (rc) return rc;
+      }
+    return CPLB_OK;
   }
+  int rc = hip_check(b, hipEventRecord(b->fork, b->stream), "batch step: fork");
+  for (int cls = 0; cls < kBatchClasses && !rc; ++cls) {
+    if (b->cls_count[cls] == 0) continue;
+    hipStream_t s = b->cls_stream[cls];
+    rc = hip_check(b, hipStreamWaitEvent(s, b->fork, 0), "batch step: fork");
+    for (int64_t k = 0; k < nsteps && !rc; ++k) {
+      const int par = advance ? b->cur ^ (int)(k & 1) : b->cur;
+      rc = hip_check(b, run_class_on(b, cls, kModeStep, var[cls], par, s), "batch step kernel");
+    }
+    if (!rc) rc = hip_check(b, hipEventRecord(b->join[cls], s), "batch step: join");
+    if (!rc) rc = hip_check(b, hipStreamWaitEvent(b->stream, b->join[cls], 0), "batch step: join");
+  }
+  return rc;
 }
 
 // The field planes of one case, recomputed from its current populations on
@@ -373,6 +426,22 @@ int cplb_batch_create(const cplb_params* prm, int ncases, void* dev_workspace, s
     delete b;
     return rc;
   }
+  // the class streams (optional: without them the classes share `stream`)
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int c = 0; c < kBatchClasses && ok; ++c)
+    ok = hipStreamCreateWithFlags(&b->cls_stream[c], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    for (int c = 0; c < kBatchClasses; ++c) {
+      if (b->cls_stream[c]) (void)hipStreamDestroy(b->cls_stream[c]);
+      if (b->join[c]) (void)hipEventDestroy(b->join[c]);
+      b->cls_stream[c] = nullptr;
+      b->join[c] = nullptr;
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    b->fork = nullptr;
+  }
   *out = b;
   return CPLB_OK;
 }
@@ -479,14 +548,10 @@ int cplb_batch_init_planes(cplb_batch_t* b, const float* dev_planes, int nplanes
 int cplb_batch_step(cplb_batch_t* b, int64_t nsteps) {
   if (!b) return CPLB_EINVAL;
   if (nsteps < 0) return set_err(b, CPLB_EINVAL, "nsteps must be >= 0");
-  for (int64_t s = 0; s < nsteps; ++s) {
-    for (int cls = 0; cls < kBatchClasses; ++cls) {
-      const int rc = hip_check(b, run_class(b, cls, kModeStep, b->variant[cls]), "batch step kernel");
-      if (rc) return rc;
-    }
-    b->cur ^= 1;
-    b->step++;
-  }
+  const int rc = enqueue_sweeps(b, b->variant, nsteps, true);
+  if (rc) return rc;
+  b->cur ^= (int)(nsteps & 1);
+  b->step += nsteps;
   return CPLB_OK;
 }
 
@@ -643,12 +708,9 @@ int cplb_batch_tune(cplb_batch_t* b, int probe_steps, double* ms_per_step) {
     return rc;
   }
   auto sweep = [&](int cls, int v) -> int {
-    for (int c = 0; c < kBatchClasses; ++c) {
-      if (b->cls_count[c] == 0) continue;
-      const int e = hip_check(b, run_class(b, c, kModeStep, c == cls ? v : b->variant[c]), "tune: probe");
-      if (e) return e;
-    }
-    return CPLB_OK;
+    int var[kBatchClasses];
+    for (int c = 0; c < kBatchClasses; ++c) var[c] = c == cls ? v : b->variant[c];
+    return enqueue_sweeps(b, var, 1, false);
   };
   float best_ms = -1.f;
   for (int cls = 0; cls < kBatchClasses && rc == CPLB_OK; ++cls) {
