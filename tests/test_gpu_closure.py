@@ -10,7 +10,9 @@ the input (leaky-ReLU kinks flip where z is within BF16 noise of 0), up to
 oracle's BF16 storage model (same rounding points, FP64 arithmetic), which
 only FP32 accumulation order separates from the GPU -- 1e-2 -- and against
 the FP64 network -- 3e-2 (output), 1.2e-1 (gradients, per layer, relative
-L2).  The closure hook is plain FP64 / FP32 arithmetic: 1e-12 / 1e-5 as
+L2).  On a network built so that every value is a short dyadic fraction
+(exact FP32 sums, nothing for BF16 to round) the outputs equal the FP64
+network's exactly.  The closure hook is plain FP64 / FP32 arithmetic: 1e-12 / 1e-5 as
 for the step itself.
 """
 import sys
@@ -79,6 +81,59 @@ def test_forward_matches_oracle(cplb, B, H, Wd):
     # balanced: the corrections add nothing to a sample's total
     tot = (out[:, 0].astype(np.float64) + out[:, 1]).sum(axis=(1, 2))
     assert np.all(np.abs(tot) <= 1e-5 * np.abs(out).sum(axis=(1, 2, 3))), tot
+    net.close()
+
+
+def dyadic_network(seed, cin=5):
+    """Parameters under which every value the network forms is a short
+    dyadic fraction: layer 1 sums 0/1 inputs with weights 0 or 1/64, and
+    each output channel of layers 2-4 reads one or two (channel, tap) pairs
+    of the layer below with weights 1/2 or 1.  Every sum is exact in FP32 and
+    every activation has at most 8 significant bits, so BF16 storage rounds
+    nothing, no pre-activation is negative (the leaky slope never applies),
+    and a correct GPU network equals the FP64 one exactly."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for n, (ci, co) in enumerate(C.LAYERS):
+        W = np.zeros((co, ci, 3, 3))
+        b = np.zeros(co)
+        if n == 0:
+            W[:, :cin] = (rng.random((co, cin, 3, 3)) < 0.5) / 64.0
+            b[:] = rng.integers(0, 4, size=co) / 64.0
+        else:
+            for o in range(co):
+                for _ in range(1 if n < 3 else 2):
+                    W[o, rng.integers(ci), rng.integers(3), rng.integers(3)] = 0.5 if n < 3 else 1.0
+            b[:] = rng.integers(0, 4, size=co) / (64.0 * 2 ** n)
+        layers.append((W, b))
+    return C.pack(layers)
+
+
+@pytest.mark.parametrize("B,H,Wd", [(2, 8, 64), (1, 16, 32)])
+def test_forward_exact_on_dyadic_network(cplb, B, H, Wd):
+    """Zero-tolerance pin of the convolution layout (taps, channels, padding
+    in y, wrap in x) and of the balance: on the dyadic network the GPU's
+    forward and inference outputs equal the FP64 network's bit for bit."""
+    import torch
+    say(f"cnn exact forward on a dyadic network B={B} H={H} W={Wd}")
+    rng = np.random.default_rng(B * 7 + H)
+    theta = dyadic_network(B * 13 + Wd)
+    planes = (rng.random((B, 5, H, Wd)) < 0.5).astype(np.float64)
+    x = np.zeros((B, 16, H, Wd))
+    x[:, :5] = planes
+    ref64 = C.output(theta, x)
+    # the data is what the construction promises: BF16 storage changes nothing
+    assert np.array_equal(C.output(theta, x, storage="bf16"), ref64)
+    assert np.abs(ref64).max() > 0
+    net = cplb.ClosureNet(B, H, Wd)
+    net.set_params(theta)
+    net.set_input_scale(np.ones(5))
+    net.set_output_scale(1.0, 1.0)
+    tp = torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous()
+    out = net.forward(tp).cpu().numpy().astype(np.float64)
+    inf = net.infer(tp).cpu().numpy().astype(np.float64)
+    say(f"  max |GPU - FP64| forward {np.abs(out - ref64).max():.1e}, inference {np.abs(inf - ref64).max():.1e}")
+    assert np.array_equal(out, ref64) and np.array_equal(inf, ref64)
     net.close()
 
 
