@@ -11,8 +11,8 @@ oracle's BF16 storage model (same rounding points, FP64 arithmetic), which
 only FP32 accumulation order separates from the GPU -- 1e-2 -- and against
 the FP64 network -- 3e-2 (output), 1.2e-1 (gradients, per layer, relative
 L2).  On a network built so that every value is a short dyadic fraction
-(exact FP32 sums, nothing for BF16 to round) the outputs equal the FP64
-network's exactly.  The closure hook is plain FP64 / FP32 arithmetic: 1e-12 / 1e-5 as
+(exact FP32 sums, nothing for BF16 to round) the outputs, the loss and
+every gradient equal the FP64 network's exactly.  The closure hook is plain FP64 / FP32 arithmetic: 1e-12 / 1e-5 as
 for the step itself.
 """
 import sys
@@ -90,8 +90,9 @@ def dyadic_network(seed, cin=5):
     each output channel of layers 2-4 reads one or two (channel, tap) pairs
     of the layer below with weights 1/2 or 1.  Every sum is exact in FP32 and
     every activation has at most 8 significant bits, so BF16 storage rounds
-    nothing, no pre-activation is negative (the leaky slope never applies),
-    and a correct GPU network equals the FP64 one exactly."""
+    nothing; the biases are positive, so every pre-activation is (the leaky
+    slope never applies, forward or backward), and a correct GPU network
+    equals the FP64 one exactly."""
     rng = np.random.default_rng(seed)
     layers = []
     for n, (ci, co) in enumerate(C.LAYERS):
@@ -99,12 +100,12 @@ def dyadic_network(seed, cin=5):
         b = np.zeros(co)
         if n == 0:
             W[:, :cin] = (rng.random((co, cin, 3, 3)) < 0.5) / 64.0
-            b[:] = rng.integers(0, 4, size=co) / 64.0
+            b[:] = rng.integers(1, 4, size=co) / 64.0
         else:
             for o in range(co):
                 for _ in range(1 if n < 3 else 2):
                     W[o, rng.integers(ci), rng.integers(3), rng.integers(3)] = 0.5 if n < 3 else 1.0
-            b[:] = rng.integers(0, 4, size=co) / (64.0 * 2 ** n)
+            b[:] = rng.integers(1, 4, size=co) / (64.0 * 2 ** n)
         layers.append((W, b))
     return C.pack(layers)
 
@@ -134,6 +135,46 @@ def test_forward_exact_on_dyadic_network(cplb, B, H, Wd):
     inf = net.infer(tp).cpu().numpy().astype(np.float64)
     say(f"  max |GPU - FP64| forward {np.abs(out - ref64).max():.1e}, inference {np.abs(inf - ref64).max():.1e}")
     assert np.array_equal(out, ref64) and np.array_equal(inf, ref64)
+    net.close()
+
+
+def test_gradients_exact_on_dyadic_network(cplb):
+    """Zero-tolerance pin of the backward pass: on the dyadic network with a
+    target that differs from the output by +-1/4 or +-1/2 at four pixels,
+    every back-propagated value is again a short dyadic fraction and every
+    gradient a sum of a few exact terms, so the GPU's loss and every weight
+    and bias gradient equal the FP64 network's bit for bit."""
+    import torch
+    B, H, Wd = 2, 8, 64
+    say(f"cnn exact gradients on a dyadic network B={B} H={H} W={Wd}")
+    rng = np.random.default_rng(5)
+    theta = dyadic_network(29)
+    planes = (rng.random((B, 5, H, Wd)) < 0.5).astype(np.float64)
+    x = np.zeros((B, 16, H, Wd))
+    x[:, :5] = planes
+    out = C.forward(theta, x)[0]
+    target = out.copy()
+    for _ in range(4):
+        target[rng.integers(B), rng.integers(2), rng.integers(H), rng.integers(Wd)] -= \
+            rng.choice([-0.5, -0.25, 0.25, 0.5])
+    lref, gref = C.loss_and_grad(theta, x, target)
+    l16, g16 = C.loss_and_grad(theta, x, target, storage="bf16")
+    assert l16 == lref and np.array_equal(g16, gref)  # nothing for BF16 to round
+    net = cplb.ClosureNet(B, H, Wd)
+    net.set_params(theta)
+    net.set_input_scale(np.ones(5))
+    net.forward(torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous())
+    loss = net.backward(torch.tensor(target, dtype=torch.float32, device="cuda").contiguous())
+    g = np.asarray(net.grads(), dtype=np.float64)
+    k = 0
+    for n, (ci, co) in enumerate(C.LAYERS):
+        nw = co * ci * 9
+        say(f"  layer {n}: {np.count_nonzero(gref[k:k + nw + co])} nonzero gradients, "
+            f"max |GPU - FP64| {np.abs(g[k:k + nw + co] - gref[k:k + nw + co]).max():.1e}")
+        assert np.count_nonzero(gref[k:k + nw + co]) > 0
+        k += nw + co
+    say(f"  loss {loss!r} FP64 {lref!r}")
+    assert loss == lref and np.array_equal(g, gref)
     net.close()
 
 
