@@ -1,5 +1,7 @@
 // Closure network: forward, backward and Adam on the GPU, with BF16 MFMA
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulate) for every convolution.
+// and FP32 accumulation: v_mfma_f32_16x16x32_bf16 for the convolutions
+// (forward, adjoint, inference), v_mfma_f32_16x16x16_bf16 for the weight
+// gradients.
 //
 // Network (fixed): four 3x3 correlations 16 -> 32 -> 32 -> 32 -> 16 with
 // leaky-ReLU (slope 0.1) after the first three; the outputs are channels 0
@@ -15,10 +17,16 @@
 // of the padded correlation into a forward correlation with the same
 // padding.
 //
-// MFMA 16x16x16 operand layout (lane l, g = l / 16, j = 0..3):
-//   A[m][k]: lane holds A[l % 16][4 g + j];  B[k][n]: B[4 g + j][l % 16];
-//   D[m][n]: lane holds D[4 g + j][l % 16].
+// MFMA operand layouts (lane l, g = l / 16):
+//   16x16x16: A[m][k]: lane holds A[l % 16][4 g + j], B[k][n]: B[4 g + j][l % 16]
+//             (j = 0..3);
+//   16x16x32: A[m][k]: lane holds A[l % 16][8 g + j], B[k][n]: B[8 g + j][l % 16]
+//             (j = 0..7);
+//   both:     D[m][n]: lane holds D[4 g + j][l % 16] (j = 0..3).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
 
 #include "../../include/cplb.h"
 #include "kernels.hpp"
@@ -79,13 +87,20 @@ constexpr int kWgradParts = 1024;
 // stage_rows: rows R0-1 .. R0+kConvRows and columns x0-1 .. x0+kConvCols of
 // an NHWC BF16 tensor of C channels (pixel stride PS in LDS), wrapped in x;
 // columns past x = W and rows outside [0, rows) are zero.
-template <int C, int PS, int ROWS = kConvRows, int NTH = 256>
-__device__ inline void stage_rows(const unsigned short* __restrict__ X, unsigned short* sx, int R0,
-                                  int x0, int W, int rows) {
+// (in two halves: load_rows into registers, store_rows into LDS, so a
+// persistent work-group can fetch its next tile while it computes one)
+template <int C, int ROWS, int NTH>
+constexpr int rows_per_thread() {
+  return ((kConvCols + 2) * (ROWS + 2) * (C / 4) + NTH - 1) / NTH;
+}
+
+template <int C, int ROWS, int NTH>
+__device__ inline void load_rows(const unsigned short* __restrict__ X,
+                                 unsigned long long (&v)[rows_per_thread<C, ROWS, NTH>()], int R0,
+                                 int x0, int W, int rows) {
   typedef unsigned long long u64;
   constexpr int LC = kConvCols + 2, LR = ROWS + 2, N = LR * LC * (C / 4);
-  constexpr int IT = (N + NTH - 1) / NTH;
-  u64 v[IT];
+  constexpr int IT = rows_per_thread<C, ROWS, NTH>();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * NTH;
@@ -99,11 +114,27 @@ __device__ inline void stage_rows(const unsigned short* __restrict__ X, unsigned
       v[it] = *(const u64*)(X + ((long long)Rg * W + xs) * C + c4 * 4);
     }
   }
+}
+
+template <int C, int PS, int ROWS, int NTH>
+__device__ inline void store_rows(unsigned short* sx,
+                                  const unsigned long long (&v)[rows_per_thread<C, ROWS, NTH>()]) {
+  typedef unsigned long long u64;
+  constexpr int LC = kConvCols + 2, LR = ROWS + 2, N = LR * LC * (C / 4);
+  constexpr int IT = rows_per_thread<C, ROWS, NTH>();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * NTH;
     if (e < N) *(u64*)(sx + (e / (C / 4)) * PS + (e % (C / 4)) * 4) = v[it];
   }
+}
+
+template <int C, int PS, int ROWS = kConvRows, int NTH = 256>
+__device__ inline void stage_rows(const unsigned short* __restrict__ X, unsigned short* sx, int R0,
+                                  int x0, int W, int rows) {
+  unsigned long long v[rows_per_thread<C, ROWS, NTH>()];
+  load_rows<C, ROWS, NTH>(X, v, R0, x0, W, rows);
+  store_rows<C, PS, ROWS, NTH>(sx, v);
 }
 
 // stage_matrix: NR rows of NC BF16 values (NC % 4 == 0, row i starts at
@@ -161,77 +192,92 @@ __global__ __launch_bounds__(64 * kConvRowsF) void conv_kernel(const unsigned sh
   typedef unsigned long long u64;
 
   const int tiles_x = (W + kConvCols - 1) / kConvCols;
-  const int x0 = (blockIdx.x % tiles_x) * kConvCols;
-  const int R0 = (blockIdx.x / tiles_x) * kConvRowsF;
-  // stage the input rows R0-1 .. R0+kConvRowsF and columns x0-1 .. x0+kConvCols
-  // (the zero padding in y between samples is applied per tap below) and the
-  // layer's weights
-  stage_rows<CIN, PS, kConvRowsF, 64 * kConvRowsF>(X, sx, R0, x0, W, rows);
-  stage_matrix<COUT, K, KS, 64 * kConvRowsF>([&](int co) { return Wg + (long long)co * K; }, sw,
-                            [](int) { return true; });
+  const int ntiles = tiles_x * ((rows + kConvRowsF - 1) / kConvRowsF);
+  constexpr int NTH = 64 * kConvRowsF;
+  // the layer's weights, once per work-group
+  stage_matrix<COUT, K, KS, NTH>([&](int co) { return Wg + (long long)co * K; }, sw,
+                                 [](int) { return true; });
   if constexpr (32 * NK > K) {
     // zero weights of the padded K range
-    for (int e = threadIdx.x; e < COUT * (32 * NK - K); e += 64 * kConvRowsF)
+    for (int e = threadIdx.x; e < COUT * (32 * NK - K); e += NTH)
       sw[(e / (32 * NK - K)) * KS + K + e % (32 * NK - K)] = 0;
   }
-  __syncthreads();
-
+  // Persistent work-group: tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+  // The input rows R0-1 .. R0+kConvRowsF and columns x0-1 .. x0+kConvCols of
+  // the next tile (the zero padding in y between samples is applied per tap
+  // below) are loaded into registers while the current tile is computed.
+  u64 nxt[rows_per_thread<CIN, kConvRowsF, NTH>()];
+  int tile = blockIdx.x;
+  if (tile < ntiles)
+    load_rows<CIN, kConvRowsF, NTH>(X, nxt, (tile / tiles_x) * kConvRowsF, (tile % tiles_x) * kConvCols,
+                                    W, rows);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R = R0 + wave;  // global row (sample * H + y) of this wave
-  if (R >= rows) return;
   const int m = lane & 15, g = lane >> 4;
-  const int y = R % H;
-  float4v acc[G][NT];
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (tile % tiles_x) * kConvCols;
+    const int R0 = (tile / tiles_x) * kConvRowsF;
+    __syncthreads();  // every wave is done with the previous tile's rows
+    store_rows<CIN, PS, kConvRowsF, NTH>(sx, nxt);
+    __syncthreads();  // the rows (and, the first time, the weights) are in place
+    const int next = tile + gridDim.x;
+    if (next < ntiles)
+      load_rows<CIN, kConvRowsF, NTH>(X, nxt, (next / tiles_x) * kConvRowsF,
+                                      (next % tiles_x) * kConvCols, W, rows);
+    const int R = R0 + wave;  // global row (sample * H + y) of this wave
+    if (R >= rows) continue;
+    const int y = R % H;
+    float4v acc[G][NT];
 #pragma unroll
-  for (int q = 0; q < G; ++q)
+    for (int q = 0; q < G; ++q)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NT; ++t) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 0; ks < NK; ++ks) {
-    // this lane's 8 values of the K step: tap and first channel
-    const int k = 32 * ks + 8 * g;
-    const int tap = k / CIN, ci = k % CIN;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    // zero padding in y, and the zero-weight K padding past the ninth tap
-    const bool live = tap < 9 && y + dy >= 0 && y + dy < H;
-    const unsigned short* xrow = sx + (wave + 1 + (tap < 9 ? dy : 0)) * LC * PS;
-    bf16x8 b[NT];
+    for (int ks = 0; ks < NK; ++ks) {
+      // this lane's 8 values of the K step: tap and first channel
+      const int k = 32 * ks + 8 * g;
+      const int tap = k / CIN, ci = k % CIN;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      // zero padding in y, and the zero-weight K padding past the ninth tap
+      const bool live = tap < 9 && y + dy >= 0 && y + dy < H;
+      const unsigned short* xrow = sx + (wave + 1 + (tap < 9 ? dy : 0)) * LC * PS;
+      bf16x8 b[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = lds8(sw + (t * 16 + m) * KS + k);
+      for (int t = 0; t < NT; ++t) b[t] = lds8(sw + (t * 16 + m) * KS + k);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int col = q * 16 + m + (tap < 9 ? dx : 0) + 1;  // LDS column of this lane's A row
+        bf16x8 a = lds8(xrow + col * PS + ci);
+        if (!live) a = bf16x8{};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = mfma32(a, b[t], acc[q][t]);
+      }
+    }
+    // D[pixel 4 g + j][channel l % 16]
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-      const int col = q * 16 + m + (tap < 9 ? dx : 0) + 1;  // LDS column of this lane's A row
-      bf16x8 a = lds8(xrow + col * PS + ci);
-      if (!live) a = bf16x8{};
+      const int xq = x0 + q * 16;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[q][t] = mfma32(a, b[t], acc[q][t]);
-    }
-  }
-  // D[pixel 4 g + j][channel l % 16]
+      for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + m;
+        if (MODE == kInfOut && co >= kOut) continue;
 #pragma unroll
-  for (int q = 0; q < G; ++q) {
-    const int xq = x0 + q * 16;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + m;
-      if (MODE == kInfOut && co >= kOut) continue;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int xp = xq + 4 * g + j;
-        if (xp >= W) continue;
-        const long long p = (long long)R * W + xp;
-        float v = acc[q][t][j];
-        if (MODE == kBwd) {
-          const float zp = Zprev[p * COUT + co];
-          v *= zp > 0.f ? 1.f : kSlope;
-          A[p * COUT + co] = to_bf16(v);
-        } else if (MODE == kInfOut) {
-          const long long q = (long long)(R % H) * W + xp, hw = (long long)H * W;
-          Z[((long long)(R / H) * kOut + co) * hw + q] = (co == 0 ? scale0 : scale1) * (v + bias[co]);
-        } else {
-          v += bias[co];
-          if (MODE != kInfAct) Z[p * COUT + co] = v;
-          A[p * COUT + co] = to_bf16(MODE == kFwdLinear ? v : (v > 0.f ? v : kSlope * v));
+        for (int j = 0; j < 4; ++j) {
+          const int xp = xq + 4 * g + j;
+          if (xp >= W) continue;
+          const long long p = (long long)R * W + xp;
+          float v = acc[q][t][j];
+          if (MODE == kBwd) {
+            const float zp = Zprev[p * COUT + co];
+            v *= zp > 0.f ? 1.f : kSlope;
+            A[p * COUT + co] = to_bf16(v);
+          } else if (MODE == kInfOut) {
+            const long long q = (long long)(R % H) * W + xp, hw = (long long)H * W;
+            Z[((long long)(R / H) * kOut + co) * hw + q] = (co == 0 ? scale0 : scale1) * (v + bias[co]);
+          } else {
+            v += bias[co];
+            if (MODE != kInfAct) Z[p * COUT + co] = v;
+            A[p * COUT + co] = to_bf16(MODE == kFwdLinear ? v : (v > 0.f ? v : kSlope * v));
+          }
         }
       }
     }
@@ -528,15 +574,42 @@ __global__ void weights_kernel(const float* __restrict__ W, int cin, int cout,
 
 // ------------------------------------------------------------------ launch
 
+namespace {
+
+// work-groups of conv_kernel<CI, CO, MO> the device holds at once (the
+// persistent grid), from its compiled resource usage; cached per kernel
+template <int CI, int CO, int MO>
+long long conv_resident() {
+  static std::atomic<long long> cache{0};
+  long long n = cache.load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(conv_kernel<CI, CO, MO>), 64 * kConvRowsF, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  n = (long long)per_cu * cus;
+  cache.store(n, std::memory_order_relaxed);
+  return n;
+}
+
+}  // namespace
+
 hipError_t cnn_conv(int layer, int mode, const unsigned short* X, const unsigned short* Wg,
                     const float* bias, float* Z, unsigned short* A, const float* Zprev, int H,
                     int W, int rows, float scale0, float scale1, hipStream_t s) {
-  const long long blocks =
+  const long long ntiles =
       (long long)((W + kConvCols - 1) / kConvCols) * ((rows + kConvRowsF - 1) / kConvRowsF);
-  const dim3 grid((unsigned)blocks), blk(64 * kConvRowsF);
-#define PFLB_CONV(CI, CO, MO) \
-  hipLaunchKernelGGL((conv_kernel<CI, CO, MO>), grid, blk, 0, s, X, Wg, bias, Z, A, Zprev, H, W, rows, \
-                     scale0, scale1)
+  const dim3 blk(64 * kConvRowsF);
+  // a persistent grid: at most the work-groups the device holds at once
+#define PFLB_CONV(CI, CO, MO)                                                                     \
+  hipLaunchKernelGGL((conv_kernel<CI, CO, MO>),                                                    \
+                     dim3((unsigned)std::min(ntiles, conv_resident<CI, CO, MO>())), blk, 0, s, X, Wg, \
+                     bias, Z, A, Zprev, H, W, rows, scale0, scale1)
   // forward: layer l maps C_in(l) -> C_out(l); backward (the adjoint of
   // layer l) maps C_out(l) -> C_in(l)
   switch (mode) {
