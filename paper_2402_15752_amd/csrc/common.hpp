@@ -481,17 +481,23 @@ __device__ inline void collide_g(const KParams<T>& P, const T (&g)[LG::Q], const
   // j = rho u itself, not from rho times the rounded u, so that the
   // collision hands the populations their momentum back without the
   // rounding of u (a bias that otherwise recurs every step)
-  auto eq = [&](int i, T cu) {
-    return kp<LG, T>(i) * fl.dpi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso) +
-           kw<LG, T>(i) * cdot<LG>(i, fl.j);
-  };
+  // Opposite links share every term: c.u, c.F, c.grad phi and c.j change
+  // sign, so the even part of the equilibrium (pressure and second-order
+  // terms) is formed once per pair and the odd ones enter with both signs,
+  // in expressions of the same shape -- the same roundings (and fused
+  // multiply-adds) the two links would get one by one.
 #pragma unroll
   for (int i = 1; i < LG::Q; ++i) {
+    if (!first_of_pair<LG>(i)) continue;
+    const int o = LG::opp[i];
     const T cu = cdot<LG>(i, fl.u);
     const T cF = cdot<LG>(i, fl.F);
     const T cg = cdot<LG>(i, gphi);
-    const T Gi = kw<LG, T>(i) * (cF + P.drho * cu * cg);
-    emit(i, relax(g[i], eq(i, cu), del_g, hdel_g, Gi));
+    const T cj = cdot<LG>(i, fl.j);
+    const T even = kp<LG, T>(i) * fl.dpi + T(LG::w[i]) * fl.rho * (cu * cu * half_inv_csg2 - iso);
+    const T dcu = P.drho * cu;
+    emit(i, relax(g[i], even + kw<LG, T>(i) * cj, del_g, hdel_g, kw<LG, T>(i) * (cF + dcu * cg)));
+    emit(o, relax(g[o], even - kw<LG, T>(i) * cj, del_g, hdel_g, kw<LG, T>(i) * (dcu * cg - cF)));
   }
 }
 
