@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44334165, "write": 43021450,
-                                 "src": "71cf04528b51694b"},
-    "rising_droplet_256c_f32": {"read": 3249836053, "write": 3117521386,
-                              "src": "71cf04528b51694b"},
-    "rising_droplet_256c_f32_s16f": {"read": 1813754858, "write": 1779236026,
-                                   "src": "71cf04528b51694b"},
-    "rising_bubble_2048x4096_f32": {"read": 1385106666, "write": 1379602650,
-                                  "src": "71cf04528b51694b"},
-    "rising_bubble_one_256x1024_f32": {"read": 32822357, "write": 32530464,
-                                     "src": "71cf04528b51694b"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1378502186, "write": 1379624400,
-                                        "src": "71cf04528b51694b"},
-    "rising_droplet_local_256c_f32": {"read": 3264600789, "write": 3120899317,
-                                    "src": "71cf04528b51694b"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1773651840, "write": 1771582634,
-                                         "src": "71cf04528b51694b"},
+    "rising_bubble_256x1024_f32": {"read": 44484650, "write": 43022442,
+                                 "src": "9bc3f55546d7aacc"},
+    "rising_droplet_256c_f32": {"read": 3255644906, "write": 3117664245,
+                              "src": "9bc3f55546d7aacc"},
+    "rising_droplet_256c_f32_s16f": {"read": 1813939456, "write": 1779121029,
+                                   "src": "9bc3f55546d7aacc"},
+    "rising_bubble_2048x4096_f32": {"read": 1385515221, "write": 1379649578,
+                                  "src": "9bc3f55546d7aacc"},
+    "rising_bubble_one_256x1024_f32": {"read": 32821802, "write": 32533738,
+                                     "src": "9bc3f55546d7aacc"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1379099285, "write": 1379605994,
+                                        "src": "9bc3f55546d7aacc"},
+    "rising_droplet_local_256c_f32": {"read": 3268947029, "write": 3120970346,
+                                    "src": "9bc3f55546d7aacc"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1772969557, "write": 1771782917,
+                                         "src": "9bc3f55546d7aacc"},
 }
 
 
