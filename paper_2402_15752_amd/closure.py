@@ -431,8 +431,9 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
     during training.  Returns a summary: median scalar errors (c1, c2
     relative L2 against the restricted fine run) with and without the
     closure, wall times of the fine, plain coarse and closure-corrected
-    coarse runs (`steps` coarse steps, F^2 fine steps each), training time,
-    training and held-out losses."""
+    coarse runs (`steps` coarse steps, F^2 fine steps each), the times of data
+    generation and of training (a second round's data included), training
+    and held-out losses."""
     import torch
     t0 = time.perf_counter()
     gen_steps = gen_steps or steps
@@ -442,6 +443,7 @@ def experiment(n_train=64, n_test=16, steps=200, nc=64, iters=(3000, 2000), batc
     X, Y = generate_chunked(train_cases, gen_steps, chunk, log=log, every=every, skip=skip)
     Xh, Yh = generate_chunked(held_cases, gen_steps, chunk, every=every, skip=skip)
     t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
     net, scale, l1, h1 = train(X, Y, iters=iters[0], batch=batch, seed=seed, log=log,
                                capacity=max(n_test, batch, min(chunk, n_train)), held=(Xh, Yh))
     l2, h2 = l1, []
