@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44484650, "write": 43022442,
-                                 "src": "9bc3f55546d7aacc"},
-    "rising_droplet_256c_f32": {"read": 3255644906, "write": 3117664245,
-                              "src": "9bc3f55546d7aacc"},
-    "rising_droplet_256c_f32_s16f": {"read": 1813939456, "write": 1779121029,
-                                   "src": "9bc3f55546d7aacc"},
-    "rising_bubble_2048x4096_f32": {"read": 1385515221, "write": 1379649578,
-                                  "src": "9bc3f55546d7aacc"},
-    "rising_bubble_one_256x1024_f32": {"read": 32821802, "write": 32533738,
-                                     "src": "9bc3f55546d7aacc"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1379099285, "write": 1379605994,
-                                        "src": "9bc3f55546d7aacc"},
-    "rising_droplet_local_256c_f32": {"read": 3268947029, "write": 3120970346,
-                                    "src": "9bc3f55546d7aacc"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1772969557, "write": 1771782917,
-                                         "src": "9bc3f55546d7aacc"},
+    "rising_bubble_256x1024_f32": {"read": 44432170, "write": 43021328,
+                                 "src": "21efb95acee4a734"},
+    "rising_droplet_256c_f32": {"read": 3170188138, "write": 3120244576,
+                              "src": "21efb95acee4a734"},
+    "rising_droplet_256c_f32_s16f": {"read": 1814083882, "write": 1779040768,
+                                   "src": "21efb95acee4a734"},
+    "rising_bubble_2048x4096_f32": {"read": 1385556480, "write": 1379629509,
+                                  "src": "21efb95acee4a734"},
+    "rising_bubble_one_256x1024_f32": {"read": 32821013, "write": 32533712,
+                                     "src": "21efb95acee4a734"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1379222869, "write": 1379598789,
+                                        "src": "21efb95acee4a734"},
+    "rising_droplet_local_256c_f32": {"read": 3128944938, "write": 3122574730,
+                                    "src": "21efb95acee4a734"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773478634, "write": 1771677328,
+                                         "src": "21efb95acee4a734"},
 }
 
 

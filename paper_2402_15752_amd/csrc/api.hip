@@ -111,14 +111,17 @@ int default_variant(const cplb_params* p) {
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
     return lattice_bytes > 256e6 ? 8 : 3;
   }
-  // 3-D: 64x4 tiles, non-temporal stores, f, h1, h2 carried from the
-  // previous plane in registers -- or, for 16-bit storage with the central
-  // stencil for grad psi, in LDS, which takes the flow collision from two to
-  // three waves per SIMD (0.90 against 1.02 ms per 256^3 FP16 step; with
-  // FP32 storage the LDS carry is slower, 1.34 against 1.28 ms, and with the
-  // local scheme no faster).  The variant that re-reads f, h1, h2 before
-  // their collision is slower than the LDS carry, and 41% of its re-reads
-  // miss L2 (1.41 x the algorithmic read bytes).
+  // 3-D: non-temporal stores, f, h1, h2 carried from the previous plane.
+  // FP32: 128x4 tiles (one 8-wave work-group per CU; rows of 128 nodes, so
+  // every plane stream of a tile moves 512-byte runs: 1.23 against 1.29 ms
+  // per 256^3 step with 64x4).  16-bit storage: 64x4 tiles, with the central
+  // stencil for grad psi the carry in LDS, which takes the flow collision
+  // from two to three waves per SIMD (0.89 against 1.01 ms; 128x4 tiles
+  // 0.97), with the local scheme in registers (0.78 ms; LDS 0.79, 128x4
+  // 0.90).  FP64: 64x4 (its registers do not fit an 8-wave group).  The
+  // variant that re-reads f, h1, h2 before their collision is slower, and 41%
+  // of its re-reads miss L2 (1.41 x the algorithmic read bytes).
+  if (p->precision == CPLB_F32) return 9;
   const bool s16 = p->precision == CPLB_F32_S16F || p->precision == CPLB_F32_S16B;
   return s16 && p->scalar_grad != CPLB_GRAD_LOCAL ? 8 : 4;
 }

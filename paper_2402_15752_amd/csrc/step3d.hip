@@ -614,7 +614,7 @@ const char* step3d_variant_name(int v) {
   static const char* names[kVariants3D] = {
       "64x4 late",         "64x4 late nt-st", "32x8 late",          "64x4",
       "64x4 nt-st",        "64x4 nt-g-st",    "64x4 late nt-g-st",  "64x4 late w4",
-      "64x4 lds nt-st"};
+      "64x4 lds nt-st",    "128x4 nt-st"};
   return v >= 0 && v < kVariants3D ? names[v] : "?";
 }
 
@@ -668,6 +668,7 @@ hipError_t launch_scheme(const S* src, S* dst, const T* hin, T* hout, T* fields,
     case 6: return PFLB_V3(64, 4, 6, false, true, 1);
     case 7: return PFLB_V3(64, 4, 0, false, true, 4);
     case 8: return PFLB_V3(64, 4, 2, false, kCarryLds, 1);
+    case 9: return PFLB_V3(128, 4, 2, false, false, 1);
     default: return PFLB_V3(64, 4, 0, false, true, 1);
   }
 #undef PFLB_V3
