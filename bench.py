@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44432170, "write": 43021328,
-                                 "src": "21efb95acee4a734"},
-    "rising_droplet_256c_f32": {"read": 3170188138, "write": 3120244576,
-                              "src": "21efb95acee4a734"},
-    "rising_droplet_256c_f32_s16f": {"read": 1814083882, "write": 1779040768,
-                                   "src": "21efb95acee4a734"},
-    "rising_bubble_2048x4096_f32": {"read": 1385556480, "write": 1379629509,
-                                  "src": "21efb95acee4a734"},
-    "rising_bubble_one_256x1024_f32": {"read": 32821013, "write": 32533712,
-                                     "src": "21efb95acee4a734"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1379222869, "write": 1379598789,
-                                        "src": "21efb95acee4a734"},
-    "rising_droplet_local_256c_f32": {"read": 3128944938, "write": 3122574730,
-                                    "src": "21efb95acee4a734"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1773478634, "write": 1771677328,
-                                         "src": "21efb95acee4a734"},
+    "rising_bubble_256x1024_f32": {"read": 44299157, "write": 43021589,
+                                 "src": "a085406caa394eb7"},
+    "rising_droplet_256c_f32": {"read": 3166056234, "write": 3120537754,
+                              "src": "a085406caa394eb7"},
+    "rising_droplet_256c_f32_s16f": {"read": 1814076544, "write": 1779111621,
+                                   "src": "a085406caa394eb7"},
+    "rising_bubble_2048x4096_f32": {"read": 1399834389, "write": 1381021189,
+                                  "src": "a085406caa394eb7"},
+    "rising_bubble_one_256x1024_f32": {"read": 32820437, "write": 32529562,
+                                     "src": "a085406caa394eb7"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1385705493, "write": 1381364912,
+                                        "src": "a085406caa394eb7"},
+    "rising_droplet_local_256c_f32": {"read": 3129244288, "write": 3122389408,
+                                    "src": "a085406caa394eb7"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773010261, "write": 1771639317,
+                                         "src": "a085406caa394eb7"},
 }
 
 
@@ -199,11 +199,12 @@ def time_gpu_with_reduce(w, steps, warmup, every=100):
                 reduce_every=every, nonfinite=r["nonfinite"])
 
 
-def time_batch(steps, warmup, tune_steps=5):
+def time_batch(steps, warmup, tune_steps=5, tune=True):
     """The batched sweep: 512 independent 2-D cases (sizes 64..256 a side)
     advanced together, one launch per size class per step, the tile variant
-    of each class picked by the autotuner; `steps` steps captured in a HIP
-    graph and timed as one replay."""
+    of each class picked by the autotuner (tune=False: the library's default
+    per class, so that separate profiling runs time the same kernels);
+    `steps` steps captured in a HIP graph and timed as one replay."""
     import torch
 
     import workloads as W
@@ -214,7 +215,7 @@ def time_batch(steps, warmup, tune_steps=5):
     for k, c in enumerate(sw["cases"]):
         b.init_sdf(k, c["sdf"], c1=c["init"]["c1"], c2=c["init"]["c2"])
     b.step(warmup)
-    tuned_ms = b.tune(tune_steps)
+    tuned_ms = b.tune(tune_steps) if tune else None
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
@@ -240,7 +241,7 @@ def time_batch(steps, warmup, tune_steps=5):
             "ms_per_step": round(per, 5), "mlups": round(n * steps / (ms * 1e-3) / 1e6, 1),
             "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "graph": True,
-            "tuned_ms_per_step": round(tuned_ms, 4),
+            "tuned_ms_per_step": round(tuned_ms, 4) if tuned_ms is not None else None,
             "classes": [{"cases": c, "variant": v} for c, v in classes],
             "pe_shifted_cases": len(sw["shifted"]), "nonfinite_sampled": nonfinite}
 
@@ -351,6 +352,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (5 launches): the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch part: keep the library's default tile per size class")
     ap.add_argument("--part", choices=("step", "batch", "closure"), default="step",
                     help="batch / closure: run only that side measurement and print its JSON "
                          "(for profiling runs)")
@@ -366,7 +369,7 @@ def main():
         raise SystemExit("bench.py needs a GPU")
 
     if args.part == "batch":
-        print(json.dumps(time_batch(args.steps, args.warmup)), flush=True)
+        print(json.dumps(time_batch(args.steps, args.warmup, tune=not args.no_tune)), flush=True)
         return
     if args.part == "closure":
         print(json.dumps(closure_speedup()), flush=True)

@@ -338,7 +338,8 @@ int cplb_batch_set_variant(cplb_batch_t* b, int cls, int variant);
 
 /* Autotuner: class after class, time every variant of the class within the
  * whole sweep (the other classes at their current variants) for
- * probe_steps sweeps on the current state, and keep the fastest.  The state
+ * probe_steps sweeps on the current state, and keep the fastest (the
+ * current variant stays unless another is faster by more than 2%).  The state
  * is left as it was (probes write only the idle lattices and histories).
  * Synchronises; *ms_per_step (may be NULL) receives the time per sweep of
  * the final choice. */

@@ -102,14 +102,16 @@ int num_variants(const cplb_t* h) { return h->G.dim == 2 ? kVariants2D : kVarian
 // Cache); cplb_tune re-checks on the caller's own state.
 int default_variant(const cplb_params* p) {
   if (p->lattice == CPLB_D2Q9) {
-    // 128x4; a lattice beyond the 256 MB Infinity Cache streams faster with
-    // non-temporal stores and cached loads (128x4 nt-st): at 2048 x 4096
-    // FP32 596 against 627 us (central) and 553 against 579 us (local
-    // scheme, against non-temporal loads too), and its loads read 1.00x the
-    // algorithmic bytes (the halo re-reads hit L2) against 1.07x and 1.26x
+    // 128x4; a lattice beyond the 256 MB Infinity Cache streams faster on
+    // 256x4 tiles (runs of 256 nodes per plane stream) with non-temporal
+    // stores and cached loads (256x4 nt-st): at 2048 x 4096 FP32 570 us
+    // against 599 (128x4 nt-st) and 629 (128x4) for the central stencil,
+    // 536 against 555 and 571 for the local scheme; with cached loads the
+    // halo re-reads hit L2 (1.00x the algorithmic read bytes against 1.07x
+    // and 1.26x with non-temporal loads)
     const int s_pop = p->precision == CPLB_F64 ? 8 : (p->precision == CPLB_F32 ? 4 : 2);
     const double lattice_bytes = (double)p->nx * p->ny * 36.0 * s_pop;
-    return lattice_bytes > 256e6 ? 8 : 3;
+    return lattice_bytes > 256e6 ? 11 : 3;
   }
   // 3-D: non-temporal stores, f, h1, h2 carried from the previous plane.
   // FP32: 128x4 tiles (one 8-wave work-group per CU; rows of 128 nodes, so

@@ -76,8 +76,8 @@ hipError_t launch_b(const BatchCase* cases, const int* ids, const int* prefix, i
 
 // tile shapes of the 2-D variants (the same table as the single-lattice step)
 int step2d_tiles(int nx, int ny, int variant) {
-  static const int tx[kVariants2D] = {64, 32, 32, 128, 64, 32, 32, 128, 128, 128};
-  static const int ty[kVariants2D] = {4, 8, 4, 4, 4, 8, 4, 4, 4, 4};
+  static const int tx[kVariants2D] = {64, 32, 32, 128, 64, 32, 32, 128, 128, 128, 256, 256};
+  static const int ty[kVariants2D] = {4, 8, 4, 4, 4, 8, 4, 4, 4, 4, 4, 4};
   if (variant < 0 || variant >= kVariants2D) variant = 0;
   return ((nx + tx[variant] - 1) / tx[variant]) * ((ny + ty[variant] - 1) / ty[variant]);
 }
@@ -101,6 +101,8 @@ hipError_t launch_batch2d(const BatchCase* cases, const int* ids, const int* pre
     case 7: return launch_b<S, T, 128, 4, 7, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
     case 8: return launch_b<S, T, 128, 4, 2, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
     case 9: return launch_b<S, T, 128, 4, 3, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 10: return launch_b<S, T, 256, 4, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
+    case 11: return launch_b<S, T, 256, 4, 2, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
     default: return launch_b<S, T, 64, 4, 0, M>(cases, ids, prefix, ncls, map, total, kps, parity, stream);
   }
 }

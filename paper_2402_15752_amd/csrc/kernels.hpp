@@ -34,7 +34,7 @@ constexpr int kHist3D = 6;  // ux, uy, uz, phi, c1, c2
 
 // step kernels; `variant` picks a compiled tile shape / streaming hint
 // (0 is the default; the macros mode always uses variant 0)
-constexpr int kVariants2D = 10;
+constexpr int kVariants2D = 12;
 constexpr int kVariants3D = 10;
 const char* step2d_variant_name(int v);
 const char* step3d_variant_name(int v);

@@ -73,7 +73,7 @@ hipError_t launch_variant(const S* src, S* dst, const T* hin, T* hout, T* fields
 const char* step2d_variant_name(int v) {
   static const char* names[kVariants2D] = {"64x4",    "32x8",    "32x4",    "128x4",
                                           "64x4 nt", "32x8 nt", "32x4 nt", "128x4 nt",
-                                          "128x4 nt-st", "128x4 nt-own"};
+                                          "128x4 nt-st", "128x4 nt-own", "256x4", "256x4 nt-st"};
   return v >= 0 && v < kVariants2D ? names[v] : "?";
 }
 
@@ -107,6 +107,8 @@ hipError_t launch_model(const S* src, S* dst, const T* hin, T* hout, T* fields, 
     case 7: return launch_variant<S, T, 128, 4, 7, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
     case 8: return launch_variant<S, T, 128, 4, 2, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
     case 9: return launch_variant<S, T, 128, 4, 3, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 10: return launch_variant<S, T, 256, 4, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
+    case 11: return launch_variant<S, T, 256, 4, 2, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
     default: return launch_variant<S, T, 64, 4, 0, M, U, MODEL>(src, dst, hin, hout, fields, P, Pdev, closure, stream);
   }
 }
