@@ -38,22 +38,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # when the sources differ the figure no longer describes the kernel and the
 # bench reports traffic as null.  Commands and raw figures: profiles/.
 TRAFFIC = {
-    "rising_bubble_256x1024_f32": {"read": 44299157, "write": 43021589,
-                                 "src": "a085406caa394eb7"},
-    "rising_droplet_256c_f32": {"read": 3166056234, "write": 3120537754,
-                              "src": "a085406caa394eb7"},
-    "rising_droplet_256c_f32_s16f": {"read": 1814076544, "write": 1779111621,
-                                   "src": "a085406caa394eb7"},
-    "rising_bubble_2048x4096_f32": {"read": 1399834389, "write": 1381021189,
-                                  "src": "a085406caa394eb7"},
-    "rising_bubble_one_256x1024_f32": {"read": 32820437, "write": 32529562,
-                                     "src": "a085406caa394eb7"},
-    "rising_bubble_local_2048x4096_f32": {"read": 1385705493, "write": 1381364912,
-                                        "src": "a085406caa394eb7"},
-    "rising_droplet_local_256c_f32": {"read": 3129244288, "write": 3122389408,
-                                    "src": "a085406caa394eb7"},
-    "rising_droplet_local_256c_f32_s16f": {"read": 1773010261, "write": 1771639317,
-                                         "src": "a085406caa394eb7"},
+    "rising_bubble_256x1024_f32": {"read": 44327722, "write": 43021269,
+                                 "src": "56116601f9a4ddd6"},
+    "rising_droplet_256c_f32": {"read": 3167235093, "write": 3120879242,
+                              "src": "56116601f9a4ddd6"},
+    "rising_droplet_256c_f32_s16f": {"read": 1814247360, "write": 1779050981,
+                                   "src": "56116601f9a4ddd6"},
+    "rising_bubble_2048x4096_f32": {"read": 1396950506, "write": 1380970026,
+                                  "src": "56116601f9a4ddd6"},
+    "rising_bubble_one_256x1024_f32": {"read": 32821461, "write": 32524096,
+                                     "src": "56116601f9a4ddd6"},
+    "rising_bubble_local_2048x4096_f32": {"read": 1385056597, "write": 1381315504,
+                                        "src": "56116601f9a4ddd6"},
+    "rising_droplet_local_256c_f32": {"read": 3133757226, "write": 3122591946,
+                                    "src": "56116601f9a4ddd6"},
+    "rising_droplet_local_256c_f32_s16f": {"read": 1773479360, "write": 1771738480,
+                                         "src": "56116601f9a4ddd6"},
 }
 
 

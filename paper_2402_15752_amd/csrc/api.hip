@@ -123,7 +123,9 @@ int default_variant(const cplb_params* p) {
   // 0.90).  FP64: 64x4 (its registers do not fit an 8-wave group).  The
   // variant that re-reads f, h1, h2 before their collision is slower, and 41%
   // of its re-reads miss L2 (1.41 x the algorithmic read bytes).
-  if (p->precision == CPLB_F32) return 9;
+  // (128-wide tiles only where they leave no more idle columns than 64-wide
+  // ones: nx a multiple of 128, or more than 64 past one)
+  if (p->precision == CPLB_F32 && (p->nx % 128 == 0 || p->nx % 128 > 64)) return 9;
   const bool s16 = p->precision == CPLB_F32_S16F || p->precision == CPLB_F32_S16B;
   return s16 && p->scalar_grad != CPLB_GRAD_LOCAL ? 8 : 4;
 }
